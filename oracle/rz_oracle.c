@@ -1,0 +1,313 @@
+/*
+ * rz_oracle.c -- plain CPU reference of the compute point rasterizer of
+ * Schuetz & Wimmer, "Rendering Point Clouds with Compute Shaders"
+ * (arXiv 1908.02681).
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load this file's library.  The product path
+ * (the HIP library under paper_1908_02681_amd/) never links, loads or calls
+ * it, and the two share no source, header, table or helper.
+ *
+ * Plain, single-threaded and literal: every point is visited in input order,
+ * every pixel in row order, one step of the method after the other.  Build
+ * with -ffp-contract=off and without fast-math, so that every float and
+ * double operation below is one IEEE-754 operation rounded to nearest and no
+ * multiply-add is fused.
+ *
+ * What the method computes (section 2.1): each point becomes one fragment,
+ * a 64-bit key whose upper 40 bits are an integer depth and whose lower 24
+ * bits are the point's RGB colour; the framebuffer keeps, per pixel, the
+ * smallest key (atomicMin).  A second per-pixel pass copies the colour bits
+ * to the image and resets the framebuffer to depth all-ones plus the
+ * background colour.  The result is a plain definition: fb[p] is the minimum
+ * over the keys of all fragments that fall into pixel p, whatever their
+ * order.  High-quality splatting (section 2.2) adds a pass that sums the
+ * colours and counts the fragments whose linear depth is within a factor
+ * (1 + eps) of the pixel's nearest depth, and a pass that divides.
+ *
+ * Readings of points the paper leaves open (all listed with reasons in the
+ * design notes of the repository):
+ *  - depth d is the clip-space w of the view-projection (row 3), computed in
+ *    double precision; for a perspective matrix it is the linear view depth;
+ *  - projection to pixels is done in single precision: clip = VPf * p with
+ *    VPf = (float)VP, ndc = clip.xy / clip.w, window = (ndc + 1) * size / 2,
+ *    pixel = floor(window), half-open [0, size), row 0 at the bottom;
+ *  - fragments with w <= 0, outside the window, or with d outside
+ *    [near, far) are discarded;
+ *  - integer depth q = floor((d - o) * s), clamped to 2^40 - 2 so that a
+ *    fragment always beats the cleared value 2^40 - 1;  "linear" maps
+ *    [near, far) onto [0, 2^40 - 1) (o = near), "scale" is the paper's
+ *    millimetre example (o = 0, s = 1000 for metres);
+ *  - colour word = R | G << 8 | B << 16; on equal depth the smaller word wins;
+ *  - the eps window is tested exactly in integers:
+ *    den * (q - qmin) <= num * (qmin + z0) with z0 = floor(o * s), so that
+ *    q + z0 is proportional to d;
+ *  - the splat average rounds half up: (2 * sum + count) / (2 * count).
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#define RZO_DEPTH_ONES 0xFFFFFFFFFF000000ull /* cleared depth, section 2.1 */
+#define RZO_RGB_MASK 0xFFFFFFull
+#define RZO_Q_MAX ((double)((1ull << 40) - 2)) /* largest fragment depth   */
+#define RZO_Q_RANGE ((double)((1ull << 40) - 1))
+
+enum { RZO_LINEAR = 0, RZO_SCALE = 1 };
+
+typedef struct {
+    float m[16];       /* view-projection rounded to float, row-major */
+    double vp[16];     /* the same in double                          */
+    double near_, far_;
+    double o, s;       /* q = floor((d - o) * s)                      */
+    uint64_t z0;       /* floor(o * s): q + z0 is proportional to d   */
+    float fw, fh;      /* framebuffer size as float                   */
+    float hw, hh;      /* half of it                                  */
+    int32_t w, h;
+} rzo_cam;
+
+static int rzo_cam_init(rzo_cam *c, const double *vp, double near_, double far_,
+                        int32_t w, int32_t h, int32_t kind, double scale)
+{
+    int i;
+    if (w < 1 || h < 1 || !(near_ > 0.0) || !(far_ > near_))
+        return -1;
+    for (i = 0; i < 16; i++) {
+        c->vp[i] = vp[i];
+        c->m[i] = (float)vp[i];
+    }
+    c->near_ = near_;
+    c->far_ = far_;
+    if (kind == RZO_LINEAR) {
+        c->o = near_;
+        c->s = RZO_Q_RANGE / (far_ - near_);
+    } else if (kind == RZO_SCALE) {
+        c->o = 0.0;
+        c->s = scale;
+        if (!(scale > 0.0))
+            return -1;
+    } else {
+        return -1;
+    }
+    c->z0 = (uint64_t)floor(c->o * c->s);
+    c->w = w;
+    c->h = h;
+    c->fw = (float)w;
+    c->fh = (float)h;
+    c->hw = 0.5f * c->fw;
+    c->hh = 0.5f * c->fh;
+    return 0;
+}
+
+/*
+ * The fragment of one point (section 2.1): its pixel index and its 40-bit
+ * integer depth.  Returns 0 when the point is discarded.
+ */
+static int rzo_fragment(const rzo_cam *c, float x, float y, float z,
+                        int64_t *pix, uint64_t *q)
+{
+    const float *m = c->m;
+    const double *v = c->vp;
+    float cx, cy, cw, nx, ny, fx, fy;
+    double d, t, tf;
+    int32_t px, py;
+
+    /* clip coordinates in single precision, left to right */
+    cx = m[0] * x;
+    cx = cx + m[1] * y;
+    cx = cx + m[2] * z;
+    cx = cx + m[3];
+    cy = m[4] * x;
+    cy = cy + m[5] * y;
+    cy = cy + m[6] * z;
+    cy = cy + m[7];
+    cw = m[12] * x;
+    cw = cw + m[13] * y;
+    cw = cw + m[14] * z;
+    cw = cw + m[15];
+    if (!(cw > 0.0f))
+        return 0;
+
+    /* perspective divide and viewport */
+    nx = cx / cw;
+    ny = cy / cw;
+    fx = (nx + 1.0f) * c->hw;
+    fy = (ny + 1.0f) * c->hh;
+    if (!(fx >= 0.0f && fx < c->fw && fy >= 0.0f && fy < c->fh))
+        return 0;
+    px = (int32_t)fx;
+    py = (int32_t)fy;
+
+    /* depth in double precision (section 1, section 2.1) */
+    d = v[12] * (double)x;
+    d = d + v[13] * (double)y;
+    d = d + v[14] * (double)z;
+    d = d + v[15];
+    if (!(d >= c->near_ && d < c->far_))
+        return 0;
+
+    /* integer part of the scaled depth, kept inside 40 bits */
+    t = (d - c->o) * c->s;
+    tf = floor(t);
+    if (tf > RZO_Q_MAX)
+        tf = RZO_Q_MAX;
+
+    *pix = (int64_t)py * c->w + px;
+    *q = (uint64_t)tf;
+    return 1;
+}
+
+/* ---------------------------------------------------------------------- */
+/* exported entry points (called through ctypes by the tests)             */
+/* ---------------------------------------------------------------------- */
+
+/* Depth-map constants (o, s, z0) as the oracle derives them. */
+int rzo_depth_constants(const double *vp, double near_, double far_, int32_t w,
+                        int32_t h, int32_t kind, double scale, double *o,
+                        double *s, uint64_t *z0)
+{
+    rzo_cam c;
+    if (rzo_cam_init(&c, vp, near_, far_, w, h, kind, scale))
+        return -1;
+    *o = c.o;
+    *s = c.s;
+    *z0 = c.z0;
+    return 0;
+}
+
+/* Per-point fragments: pix[i] = pixel index or -1, q[i] = integer depth. */
+int rzo_fragments(const float *x, const float *y, const float *z, int64_t n,
+                  const double *vp, double near_, double far_, int32_t w,
+                  int32_t h, int32_t kind, double scale, int64_t *pix,
+                  uint64_t *q)
+{
+    rzo_cam c;
+    int64_t i;
+    if (rzo_cam_init(&c, vp, near_, far_, w, h, kind, scale))
+        return -1;
+    for (i = 0; i < n; i++) {
+        int64_t p;
+        uint64_t qq;
+        if (rzo_fragment(&c, x[i], y[i], z[i], &p, &qq)) {
+            pix[i] = p;
+            q[i] = qq;
+        } else {
+            pix[i] = -1;
+            q[i] = 0;
+        }
+    }
+    return 0;
+}
+
+/* Reset a framebuffer: depth all ones, colour = background (section 2.1). */
+void rzo_clear(uint64_t *fb, int64_t npix, uint32_t bg)
+{
+    int64_t p;
+    for (p = 0; p < npix; p++)
+        fb[p] = RZO_DEPTH_ONES | ((uint64_t)bg & RZO_RGB_MASK);
+}
+
+/*
+ * Rasterization via atomicMin (section 2.1): depth shifted 24 bits left,
+ * colour in the low 24 bits, the smaller key kept.
+ */
+int rzo_raster_min(const float *x, const float *y, const float *z,
+                   const uint32_t *rgb, int64_t n, const double *vp,
+                   double near_, double far_, int32_t w, int32_t h,
+                   int32_t kind, double scale, uint64_t *fb)
+{
+    rzo_cam c;
+    int64_t i;
+    if (rzo_cam_init(&c, vp, near_, far_, w, h, kind, scale))
+        return -1;
+    for (i = 0; i < n; i++) {
+        int64_t p;
+        uint64_t q, key;
+        if (!rzo_fragment(&c, x[i], y[i], z[i], &p, &q))
+            continue;
+        key = (q << 24) | ((uint64_t)rgb[i] & RZO_RGB_MASK);
+        if (key < fb[p])
+            fb[p] = key;
+    }
+    return 0;
+}
+
+/*
+ * Second step of section 2.1: copy the colour bits of every pixel into the
+ * image, then clear the framebuffer for the next frame.
+ */
+void rzo_resolve_min(uint64_t *fb, int64_t npix, uint32_t bg, uint32_t *img)
+{
+    int64_t p;
+    for (p = 0; p < npix; p++) {
+        img[p] = (uint32_t)(fb[p] & RZO_RGB_MASK);
+        fb[p] = RZO_DEPTH_ONES | ((uint64_t)bg & RZO_RGB_MASK);
+    }
+}
+
+/*
+ * Second pass of high-quality splatting (section 2.2): every fragment whose
+ * depth is at most eps larger than the nearest depth of its pixel adds its
+ * red, green and blue values and increments the pixel's counter.  sums holds
+ * four exact 64-bit totals per pixel: R, G, B, count.
+ */
+int rzo_hq_accumulate(const float *x, const float *y, const float *z,
+                      const uint32_t *rgb, int64_t n, const double *vp,
+                      double near_, double far_, int32_t w, int32_t h,
+                      int32_t kind, double scale, uint32_t eps_num,
+                      uint32_t eps_den, const uint64_t *fb, uint64_t *sums)
+{
+    rzo_cam c;
+    int64_t i;
+    if (eps_den == 0)
+        return -1;
+    if (rzo_cam_init(&c, vp, near_, far_, w, h, kind, scale))
+        return -1;
+    for (i = 0; i < n; i++) {
+        int64_t p;
+        uint64_t q, qmin;
+        uint32_t col;
+        if (!rzo_fragment(&c, x[i], y[i], z[i], &p, &q))
+            continue;
+        qmin = fb[p] >> 24;
+        if (q < qmin)
+            return -2; /* fb does not hold this cloud's depth pass */
+        /* exact: 128-bit products cannot overflow */
+        if ((unsigned __int128)eps_den * (q - qmin) >
+            (unsigned __int128)eps_num * ((unsigned __int128)qmin + c.z0))
+            continue;
+        col = rgb[i];
+        sums[4 * p + 0] += col & 0xFFu;
+        sums[4 * p + 1] += (col >> 8) & 0xFFu;
+        sums[4 * p + 2] += (col >> 16) & 0xFFu;
+        sums[4 * p + 3] += 1;
+    }
+    return 0;
+}
+
+/*
+ * Third pass of high-quality splatting (section 2.2): the average colour of
+ * the accepted fragments, or the background where none was accepted; then
+ * the framebuffer and the sums are cleared.
+ */
+void rzo_hq_resolve(uint64_t *sums, uint64_t *fb, int64_t npix, uint32_t bg,
+                    uint32_t *img)
+{
+    int64_t p;
+    for (p = 0; p < npix; p++) {
+        uint64_t cnt = sums[4 * p + 3];
+        if (cnt == 0) {
+            img[p] = bg & 0xFFFFFFu;
+        } else {
+            uint64_t r = (2 * sums[4 * p + 0] + cnt) / (2 * cnt);
+            uint64_t g = (2 * sums[4 * p + 1] + cnt) / (2 * cnt);
+            uint64_t b = (2 * sums[4 * p + 2] + cnt) / (2 * cnt);
+            img[p] = (uint32_t)(r | (g << 8) | (b << 16));
+        }
+        sums[4 * p + 0] = 0;
+        sums[4 * p + 1] = 0;
+        sums[4 * p + 2] = 0;
+        sums[4 * p + 3] = 0;
+        fb[p] = RZO_DEPTH_ONES | ((uint64_t)bg & RZO_RGB_MASK);
+    }
+}

@@ -1,0 +1,103 @@
+"""The oracle's pins must catch plausible mistakes.  Each mutant below plants
+one mistake in a private copy of the oracle source (on the CPU), and at least
+one pin of tests/test_oracle.py has to fail on it."""
+import ctypes
+import os
+import subprocess
+
+import pytest
+
+from oracle import oracle as O
+from tests import test_oracle as T
+
+MUTANTS = {
+    "transposed matrix": ("cx = cx + m[1] * y;", "cx = cx + m[4] * y;"),
+    "dropped translation": ("cx = cx + m[3];", ""),
+    "wrong w row": ("cw = m[12] * x;", "cw = m[8] * x;"),
+    "viewport sign": ("fx = (nx + 1.0f) * c->hw;", "fx = (nx - 1.0f) * c->hw;"),
+    "half sizes swapped": ("fy = (ny + 1.0f) * c->hh;", "fy = (ny + 1.0f) * c->hw;"),
+    "ndc divides by x": ("ny = cy / cw;", "ny = cy / cx;"),
+    "window edge inclusive": ("fx < c->fw", "fx <= c->fw"),
+    "depth from row 2": ("d = v[12] * (double)x;", "d = v[8] * (double)x;"),
+    "depth offset dropped": ("d = d + v[15];", ""),
+    "depth in single precision": ("d = d + v[15];", "d = d + v[15];\n    d = (double)cw;"),
+    "far inclusive": ("d < c->far_", "d <= c->far_"),
+    "near exclusive": ("d >= c->near_", "d > c->near_"),
+    "round instead of floor": ("tf = floor(t);", "tf = round(t);"),
+    "no clamp below clear depth": ("#define RZO_Q_MAX ((double)((1ull << 40) - 2))",
+                                   "#define RZO_Q_MAX ((double)((1ull << 40) - 1))"),
+    "linear range off by one": ("#define RZO_Q_RANGE ((double)((1ull << 40) - 1))",
+                                "#define RZO_Q_RANGE ((double)((1ull << 40)))"),
+    "pixel index transposed": ("*pix = (int64_t)py * c->w + px;", "*pix = (int64_t)px * c->h + py;"),
+    "colour shift 23": ("key = (q << 24)", "key = (q << 23)"),
+    "max instead of min": ("if (key < fb[p])", "if (key > fb[p])"),
+    "colour mask 16 bits": ("key = (q << 24) | ((uint64_t)rgb[i] & RZO_RGB_MASK);",
+                            "key = (q << 24) | ((uint64_t)rgb[i] & 0xFFFFu);"),
+    "eps window exclusive": ("(unsigned __int128)eps_den * (q - qmin) >\n",
+                             "(unsigned __int128)eps_den * (q - qmin) >=\n"),
+    "eps offset z0 dropped": ("((unsigned __int128)qmin + c.z0)", "((unsigned __int128)qmin)"),
+    "eps num and den swapped": ("if ((unsigned __int128)eps_den * (q - qmin) >\n            (unsigned __int128)eps_num",
+                                "if ((unsigned __int128)eps_num * (q - qmin) >\n            (unsigned __int128)eps_den"),
+    "truncating average": ("uint64_t r = (2 * sums[4 * p + 0] + cnt) / (2 * cnt);",
+                           "uint64_t r = sums[4 * p + 0] / cnt;"),
+    "green reads blue": ("sums[4 * p + 1] += (col >> 8) & 0xFFu;", "sums[4 * p + 1] += (col >> 16) & 0xFFu;"),
+    "count steps by two": ("sums[4 * p + 3] += 1;", "sums[4 * p + 3] += 2;"),
+    "resolve clear drops background": (
+        "img[p] = (uint32_t)(fb[p] & RZO_RGB_MASK);\n        fb[p] = RZO_DEPTH_ONES | ((uint64_t)bg & RZO_RGB_MASK);",
+        "img[p] = (uint32_t)(fb[p] & RZO_RGB_MASK);\n        fb[p] = RZO_DEPTH_ONES;"),
+    "splat background lost": ("img[p] = bg & 0xFFFFFFu;", "img[p] = 0;"),
+    "splat sums not cleared": ("        sums[4 * p + 3] = 0;\n", ""),
+}
+
+PINS = [
+    (T.test_clear_value_matches_paper, {}),
+    (T.test_empty_cloud_gives_background, {}),
+    *[(T.test_hand_cases, {"case": i}) for i in range(len(T._gold("hand_cases.json")["cases"]))],
+    (T.test_depth_edges, {}),
+    (T.test_depth_clamps_below_clear_depth, {}),
+    (T.test_moon_in_millimetres, {}),
+    (T.test_linear_map_is_uniform, {}),
+    (T.test_window_edges_and_culling, {}),
+    (T.test_behind_camera_and_outside_range_culled, {}),
+    (T.test_optical_axis_hits_centre_pixel, {}),
+    (T.test_resolve_clears_framebuffer, {}),
+    (T.test_fragments_match_exact_projection, {"seed": 1, "kind": 0, "scale": 0.0}),
+    (T.test_framebuffer_matches_brute_force, {"seed": 5}),
+    (T.test_eps_window_relative_to_linear_depth, {}),
+    (T.test_hq_depth_pass_equals_basic, {}),
+    (T.test_hq_huge_eps_averages_whole_pixel, {}),
+    (T.test_hq_integer_window_matches_linear_depth, {}),
+]
+
+
+def _first_failing_pin(lib):
+    saved = O._lib
+    O._lib = lib
+    try:
+        for fn, kw in PINS:
+            try:
+                fn(O, **kw)
+            except (AssertionError, ValueError):
+                return f"{fn.__name__}{kw or ''}"
+        return None
+    finally:
+        O._lib = saved
+
+
+def test_unmutated_oracle_passes_every_pin():
+    O.build()
+    assert _first_failing_pin(O.configure(ctypes.CDLL(O.LIB))) is None
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(tmp_path, name):
+    old, new = MUTANTS[name]
+    src = open(O.SRC).read()
+    assert src.count(old) == 1, f"mutation site of {name!r} is not unique"
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / "libmutant.so"
+    flags = [f for f in O.CFLAGS if f != "-Werror"]
+    subprocess.run(["gcc", *flags, str(path), "-o", str(so), "-lm"], check=True)
+    lib = O.configure(ctypes.CDLL(str(so)))
+    assert _first_failing_pin(lib) is not None, f"no pin catches: {name}"
