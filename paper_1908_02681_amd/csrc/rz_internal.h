@@ -1,0 +1,53 @@
+// Internal declarations shared by the host side of the library and the
+// kernel launchers.  Not part of the public C ABI (that is include/rz.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rz {
+
+// Per-view constants of one rasterization, derived on the host in double
+// precision and passed to the kernels by value.
+struct Proj {
+    float m[12];          // rows 0, 1 and 3 of (float)VP, row-major
+    float fw, fh;         // framebuffer size as float
+    float hw, hh;         // half of it
+    double v[4];          // row 3 of VP in double: the depth row
+    double near_, far_;
+    double o, s;          // q = floor((d - o) * s)
+    uint64_t z0;          // floor(o * s)
+    int32_t width, height;
+};
+
+// Launch shape of the point kernels.
+struct Tune {
+    int block = 256;       // threads per workgroup (multiple of 64, <= 1024)
+    int ppt = 8;           // points per thread (multiple of 4, <= 16)
+    int early_out = 1;     // read the framebuffer before the atomic
+    int xcd_remap = 1;     // give each XCD a contiguous range of chunks
+    int bin = 0;           // LDS tile merge before the global atomics
+};
+
+constexpr uint64_t kDepthOnes = 0xFFFFFFFFFF000000ull;
+constexpr uint64_t kRgbMask = 0xFFFFFFull;
+constexpr uint64_t kHqCountMax = 16843009ull;   // floor((2^32 - 1) / 255)
+
+// Point planes on the device.
+struct Pts {
+    const float *x, *y, *z;
+    const uint32_t *rgb;
+    int64_t n;
+};
+
+hipError_t launch_raster_min(const Pts &p, const Proj &P, uint64_t *fb, const Tune &t,
+                             hipStream_t s);
+hipError_t launch_hq_accum(const Pts &p, const Proj &P, uint32_t eps_num, uint32_t eps_den,
+                           const uint64_t *fb, uint64_t *acc, const Tune &t, hipStream_t s);
+hipError_t launch_resolve_min(uint64_t *fb, int64_t npix, uint32_t bg, uint32_t *img,
+                              hipStream_t s);
+hipError_t launch_resolve_hq(uint64_t *fb, uint64_t *acc, int64_t npix, uint32_t bg,
+                             uint32_t *img, uint32_t *status, hipStream_t s);
+hipError_t launch_clear(uint64_t *fb, uint64_t *acc, int64_t npix, uint32_t bg, hipStream_t s);
+
+}  // namespace rz

@@ -1,0 +1,135 @@
+"""The C-ABI library loads, exports every function include/rz.h declares, and
+rejects bad arguments with the documented codes before touching a device
+(no GPU needed: validation runs on the host before any HIP call)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
+
+
+@pytest.fixture(scope="module")
+def rz():
+    from paper_1908_02681_amd import build, rz as binding
+    if not os.path.exists(binding.LIB_PATH):
+        build.build()
+    binding.load()
+    return binding
+
+
+def declared_functions():
+    names = []
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(",
+                             text, flags=re.M):
+            names.append(m.group(1))
+    return sorted(set(names))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("rasterize_atomicmin", "rasterize_hq_splat", "rz_clear", "rz_resolve_min",
+              "rz_resolve_hq", "rz_error_string"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(rz):
+    lib = ctypes.CDLL(rz.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_signatures_cover_header(rz):
+    assert set(declared_functions()) <= set(rz.SIGNATURES)
+
+
+def test_error_strings(rz):
+    assert rz.error_string(0) == "ok"
+    for code in (rz.RZ_EINVAL, rz.RZ_EDEPTHRANGE, rz.RZ_EHIP, rz.RZ_EOVERFLOW, rz.RZ_EBUDGET,
+                 rz.RZ_ESTATE):
+        assert rz.error_string(code) not in ("ok", "unknown error")
+    assert rz.error_string(12345) == "unknown error"
+    assert rz.load().rz_version() >= 100
+
+
+class _View:
+    def __init__(self, near=0.5, far=100.0, w=64, h=48, vp=None):
+        self.vp = np.eye(4) if vp is None else vp
+        self.near, self.far, self.width, self.height = near, far, w, h
+
+
+def _call_min(rz, pts=None, view=None, depth=(0, 0.0), fb=1, img=1, flags=0):
+    lib = rz.load()
+    ps = pts if pts is not None else rz.rz_points(1, 1, 1, 1, 10)
+    vs = rz.view_struct(view or _View())
+    ds = rz.depth_struct(*depth)
+    return lib.rasterize_atomicmin(ctypes.byref(ps), ctypes.byref(vs), ctypes.byref(ds), 0,
+                                   fb and ctypes.c_void_p(fb), img and ctypes.c_void_p(img),
+                                   flags, None)
+
+
+def test_argument_validation(rz):
+    E = rz
+    lib = rz.load()
+    assert _call_min(rz, pts=rz.rz_points(0, 1, 1, 1, 10)) == E.RZ_EINVAL        # null plane
+    assert _call_min(rz, pts=rz.rz_points(1, 1, 1, 1, -1)) == E.RZ_EINVAL        # n < 0
+    assert _call_min(rz, pts=rz.rz_points(1, 1, 1, 1, 2 ** 32)) == E.RZ_EINVAL   # n too large
+    assert _call_min(rz, view=_View(w=0)) == E.RZ_EINVAL
+    assert _call_min(rz, view=_View(h=40000)) == E.RZ_EINVAL
+    assert _call_min(rz, view=_View(near=0.0)) == E.RZ_EINVAL
+    assert _call_min(rz, view=_View(near=2.0, far=1.0)) == E.RZ_EINVAL
+    bad = np.eye(4)
+    bad[0, 0] = np.nan
+    assert _call_min(rz, view=_View(vp=bad)) == E.RZ_EINVAL
+    assert _call_min(rz, depth=(7, 0.0)) == E.RZ_EINVAL                            # unknown map
+    assert _call_min(rz, depth=(1, -1.0)) == E.RZ_EINVAL                           # scale <= 0
+    # millimetres up to 1e9 m fit 40 bits; 1.1e9 m do not (section 2.1)
+    assert _call_min(rz, view=_View(far=1.2e9), depth=(1, 1000.0)) == E.RZ_EDEPTHRANGE
+    assert _call_min(rz, fb=0) == E.RZ_EINVAL
+    assert _call_min(rz, img=0) == E.RZ_EINVAL                                     # img needed
+    assert _call_min(rz, flags=2) == E.RZ_EINVAL
+    # hq: eps limits
+    ps, vs, ds = rz.rz_points(1, 1, 1, 1, 10), rz.view_struct(_View()), rz.depth_struct()
+    for num, den, code in ((1, 0, E.RZ_EINVAL), (1, 2 ** 21, E.RZ_EINVAL),
+                           (2 ** 21, 1, E.RZ_EINVAL)):
+        hq = rz.rz_hq_params(num, den)
+        assert lib.rasterize_hq_splat(ctypes.byref(ps), ctypes.byref(vs), ctypes.byref(ds),
+                                      ctypes.byref(hq), 0, ctypes.c_void_p(1), ctypes.c_void_p(1),
+                                      ctypes.c_void_p(1), None, 0, None) == code
+    # eps test would overflow: huge near/far ratio makes z0 enormous
+    vz = rz.view_struct(_View(near=1e6, far=1e6 + 1e-3))
+    hq = rz.rz_hq_params(2 ** 20, 1)
+    assert lib.rasterize_hq_splat(ctypes.byref(ps), ctypes.byref(vz), ctypes.byref(ds),
+                                  ctypes.byref(hq), 0, ctypes.c_void_p(1), ctypes.c_void_p(1),
+                                  ctypes.c_void_p(1), None, 0, None) == E.RZ_EDEPTHRANGE
+    assert lib.rz_clear(None, None, 5, 0, None) == E.RZ_EINVAL
+    assert lib.rz_clear(None, None, -1, 0, None) == E.RZ_EINVAL
+    assert lib.rz_resolve_min(ctypes.c_void_p(1), 4, 0, None, None) == E.RZ_EINVAL
+    assert lib.rz_resolve_hq(ctypes.c_void_p(1), None, 4, 0, ctypes.c_void_p(1), None,
+                             None) == E.RZ_EINVAL
+
+
+def test_launch_shape_validation(rz):
+    lib = rz.load()
+    before = rz.get_launch()
+    for bad in ((96, 8, 1, 1, 0), (256, 6, 1, 1, 0), (256, 8, 2, 1, 0), (256, 8, 1, 5, 0)):
+        assert lib.rz_set_launch(ctypes.byref(rz.rz_launch(*bad))) == rz.RZ_EINVAL
+    assert rz.get_launch() == before
+    rz.set_launch(128, 4, 0, 0)
+    assert rz.get_launch()["block"] == 128 and rz.get_launch()["ppt"] == 4
+    rz.set_launch(**before)
+
+
+def test_binding_refuses_without_gpu(rz):
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(rz.RzError):
+        rz.new_framebuffer(_View())

@@ -1,0 +1,232 @@
+"""GPU path vs CPU oracle, bit for bit (framebuffer keys, splat sums and
+images are integers).  Runs through the C ABI via the Python binding."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1908_02681_amd import gen
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rz():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1908_02681_amd import rz as binding
+    binding.load()
+    yield binding
+    binding.set_launch()
+
+
+def gpu_min(rz, pts, view, depth=None, bg=0):
+    """(keys, image) from the GPU: keys via RZ_KEEP_KEYS, image via a full call."""
+    import torch
+    fb, _ = rz.new_framebuffer(view, bg)
+    fb, _ = rz.rasterize_atomicmin(pts, view, depth, bg, fb=fb, keep_keys=True)
+    keys = rz.to_u64(fb)
+    img = rz.resolve_min(fb, view.width * view.height, bg)
+    torch.cuda.synchronize()
+    cleared = rz.to_u64(fb)
+    return keys, rz.to_u32(img), cleared
+
+
+def gpu_hq(rz, pts, view, depth=None, eps=(1, 100), bg=0):
+    import torch
+    fb, acc = rz.new_framebuffer(view, bg, hq=True)
+    rz.rasterize_hq_splat(pts, view, depth, eps, bg, fb=fb, acc=acc, keep_keys=True)
+    keys = rz.to_u64(fb)
+    sums = rz.unpack_acc(acc)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    img = rz.resolve_hq(fb, acc, view.width * view.height, bg, status=status)
+    torch.cuda.synchronize()
+    return keys, sums, rz.to_u32(img), rz.to_u64(fb), rz.to_u64(acc), int(status.item())
+
+
+def full_call(rz, pts, view, depth=None, eps=(1, 100), bg=0):
+    """Images of the one-call forms (resolve included)."""
+    import torch
+    _, img = rz.rasterize_atomicmin(pts, view, depth, bg)
+    fb, acc, himg, status = rz.rasterize_hq_splat(pts, view, depth, eps, bg)
+    torch.cuda.synchronize()
+    return rz.to_u32(img), rz.to_u32(himg), rz.to_u64(fb), rz.to_u64(acc), int(status.item())
+
+
+def check_scene(rz, oracle, cloud, view, depth=(0, 0.0), eps=(1, 100), bg=0, label=""):
+    say(f"[parity] {label} n={cloud.n} {view.width}x{view.height} depth={depth} eps={eps}")
+    pts = rz.Points.from_cloud(cloud)
+    ok_keys, ok_img = oracle.render_atomicmin(cloud.x, cloud.y, cloud.z, cloud.rgb, view.vp,
+                                              view.near, view.far, view.width, view.height,
+                                              depth[0], depth[1], bg)
+    keys, img, cleared = gpu_min(rz, pts, view, depth, bg)
+    assert np.array_equal(keys, ok_keys), f"{label}: keys differ at {np.flatnonzero(keys != ok_keys)[:10]}"
+    assert np.array_equal(img, ok_img)
+    assert (cleared == np.uint64(oracle.clear_value(bg))).all()
+    hk, hs, himg = oracle.render_hq(cloud.x, cloud.y, cloud.z, cloud.rgb, view.vp, view.near,
+                                    view.far, view.width, view.height, depth[0], depth[1], eps, bg)
+    k2, s2, i2, fb_after, acc_after, status = gpu_hq(rz, pts, view, depth, eps, bg)
+    assert np.array_equal(k2, hk)
+    assert np.array_equal(s2, hs), f"{label}: sums differ at {np.flatnonzero((s2 != hs).any(1))[:10]}"
+    assert np.array_equal(i2, himg)
+    assert (fb_after == np.uint64(oracle.clear_value(bg))).all() and (acc_after == 0).all()
+    assert status == 0
+    a, b, fb3, acc3, st3 = full_call(rz, pts, view, depth, eps, bg)
+    assert np.array_equal(a, ok_img) and np.array_equal(b, himg)
+    assert (fb3 == np.uint64(oracle.clear_value(bg))).all() and (acc3 == 0).all() and st3 == 0
+    return ok_keys, hs
+
+
+# --------------------------------------------------------------------------
+
+def test_hand_cases_on_gpu(rz, oracle):
+    with open(os.path.join(GOLD, "hand_cases.json")) as f:
+        g = json.load(f)
+    view = gen.View(np.array(g["vp"], np.float64), g["near"], g["far"], g["width"], g["height"])
+    for c in g["cases"]:
+        say(f"[hand] {c['name']}")
+        a = np.array([[r[0], r[1], r[2]] for r in c["points"]], np.float32)
+        rgb = np.array([int(r[3], 16) for r in c["points"]], np.uint32)
+        cloud = gen.Cloud(a[:, 0].copy(), a[:, 1].copy(), a[:, 2].copy(), rgb)
+        pts = rz.Points.from_cloud(cloud)
+        keys, img, _ = gpu_min(rz, pts, view, (1, g["scale"]))
+        if "key" in c:
+            assert int(keys[c["pixel"]]) == int(c["key"], 16)
+            assert int(img[c["pixel"]]) == int(c["image"], 16)
+        if "sums" in c:
+            _, sums, himg, *_ = gpu_hq(rz, pts, view, (1, g["scale"]), tuple(c["eps"]))
+            assert sums[c["pixel"]].tolist() == c["sums"]
+            assert int(himg[c["pixel"]]) == int(c["hq_image"], 16)
+
+
+def test_config1_spheres(rz, oracle):
+    cloud, view = gen.config1()
+    check_scene(rz, oracle, cloud, view, label="1M spheres 1024x768")
+
+
+def test_background_and_scale_map(rz, oracle):
+    cloud, view = gen.config1(n=300_000)
+    check_scene(rz, oracle, cloud, view, depth=(1, 1000.0), bg=0x3A2B1C, label="mm map, bg")
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 63, 1000, 4097, 2048 * 8 + 5, 123_457])
+def test_ragged_sizes(rz, oracle, n):
+    cloud = gen.terrain(max(n, 1), 5, extent=50.0, amplitude=5.0, wavelength=20.0)
+    cloud = cloud.take(np.arange(n))
+    view = gen.terrain_view(97, 61, extent=50.0, distance=60.0, near=0.5, far=400.0)
+    check_scene(rz, oracle, cloud, view, label=f"ragged n={n}")
+
+
+LAUNCHES = [(b, p, e, x) for b in (64, 256, 512) for p in (4, 8, 16) for e in (0, 1) for x in (0, 1)]
+
+
+def test_every_launch_shape_is_bit_identical(rz, oracle):
+    cloud = gen.terrain(200_003, 9, extent=100.0, amplitude=10.0, wavelength=40.0)
+    view = gen.terrain_view(160, 120, extent=100.0, distance=120.0, near=0.5, far=400.0)
+    ok_keys, _ = oracle.render_atomicmin(cloud.x, cloud.y, cloud.z, cloud.rgb, view.vp, view.near,
+                                         view.far, view.width, view.height)
+    _, ok_sums, ok_img = oracle.render_hq(cloud.x, cloud.y, cloud.z, cloud.rgb, view.vp, view.near,
+                                          view.far, view.width, view.height)
+    pts = rz.Points.from_cloud(cloud)
+    try:
+        for b, p, e, x in LAUNCHES:
+            say(f"[launch] block={b} ppt={p} early={e} xcd={x}")
+            rz.set_launch(b, p, e, x)
+            keys, _, _ = gpu_min(rz, pts, view)
+            assert np.array_equal(keys, ok_keys)
+            _, sums, img, *_ = gpu_hq(rz, pts, view)
+            assert np.array_equal(sums, ok_sums) and np.array_equal(img, ok_img)
+    finally:
+        rz.set_launch()
+
+
+def test_unaligned_planes_take_the_scalar_path(rz, oracle):
+    import torch
+    cloud = gen.terrain(50_001, 4, extent=50.0, amplitude=5.0, wavelength=20.0)
+    view = gen.terrain_view(80, 60, extent=50.0, distance=60.0, near=0.5, far=400.0)
+    ok_keys, ok_img = oracle.render_atomicmin(cloud.x[1:], cloud.y[1:], cloud.z[1:], cloud.rgb[1:],
+                                              view.vp, view.near, view.far, view.width, view.height)
+    full = rz.Points.from_cloud(cloud)
+    pts = rz.Points(full.x[1:], full.y[1:], full.z[1:], full.rgb[1:])
+    assert pts.x.data_ptr() % 16 != 0
+    keys, img, _ = gpu_min(rz, pts, view)
+    assert np.array_equal(keys, ok_keys) and np.array_equal(img, ok_img)
+
+
+def test_degenerate_points(rz, oracle):
+    """NaN, infinities, points behind the camera and outside [near, far),
+    points exactly on the window edges."""
+    rng = np.random.default_rng(0)
+    n = 5000
+    W, H = 32, 16
+    vp = np.eye(4)
+    vp[2, :] = 0
+    vp[3, :] = [0, 0, 0.25, 1.0]
+    x = rng.choice(np.array([-1, -0.5, 0, 0.5, 1, np.nan, np.inf, -np.inf, 0.9999999], np.float32), n)
+    y = rng.choice(np.array([-1, -0.25, 0, 0.75, 1, np.nan, 0.5], np.float32), n)
+    z = rng.uniform(-12, 12, n).astype(np.float32)
+    z[::17] = np.nan
+    rgb = rng.integers(0, 2 ** 32, n, dtype=np.uint32)   # high byte must be ignored
+    cloud = gen.Cloud(x, y, z, rgb)
+    view = gen.View(vp, 0.5, 3.0, W, H)
+    check_scene(rz, oracle, cloud, view, label="degenerate")
+
+
+def test_config2_terrain_full_size(rz, oracle):
+    """The 50M-point Morton terrain at 1920x1080, every pixel, both modes."""
+    cloud, view = gen.config2()
+    keys, sums = check_scene(rz, oracle, cloud, view, label="50M terrain 1920x1080")
+    # the workload is non-trivial: most of the screen is covered, many
+    # fragments per pixel fall in the 1% window
+    assert (keys != np.uint64(oracle.clear_value(0))).mean() > 0.3
+    assert sums[:, 3].max() > 10
+
+
+def test_config2_shuffled_sample(rz, oracle):
+    cloud, view = gen.config2(n=8_000_000)
+    check_scene(rz, oracle, gen.shuffle(cloud, 1), view, label="8M terrain shuffled")
+
+
+def test_repeated_calls_reuse_cleared_buffers(rz, oracle):
+    import torch
+    cloud, view = gen.config1(n=200_000)
+    pts = rz.Points.from_cloud(cloud)
+    fb, acc = rz.new_framebuffer(view, 7, hq=True)
+    outs = []
+    for _ in range(3):
+        _, img = rz.rasterize_atomicmin(pts, view, background=7, fb=fb)
+        _, _, himg, _ = rz.rasterize_hq_splat(pts, view, background=7, fb=fb, acc=acc)
+        torch.cuda.synchronize()
+        outs.append((rz.to_u32(img), rz.to_u32(himg)))
+    for a, b in outs[1:]:
+        assert np.array_equal(a, outs[0][0]) and np.array_equal(b, outs[0][1])
+
+
+def test_hq_count_limit(rz, oracle):
+    """Largest exact splat count: 16843009 white fragments in one pixel sum to
+    2^32 - 1 per channel; one more sets the overflow status."""
+    import torch
+    view = gen.View(np.diag([1.0, 1.0, 0.0, 0.0]) + np.array(
+        [[0, 0, 0, 0], [0, 0, 0, 0], [0, 0, 0, 0], [0, 0, -1.0, 0]]), 1.0, 100.0, 2, 2)
+    for n, over in ((16_843_009, False), (16_843_010, True)):
+        say(f"[count] n={n}")
+        pts = rz.Points(torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"),
+                        torch.full((n,), -10.0, device="cuda"),
+                        torch.full((n,), 0xFFFFFF, dtype=torch.int32, device="cuda"))
+        fb, acc, img, status = rz.rasterize_hq_splat(pts, view)
+        torch.cuda.synchronize()
+        st = int(status.item())
+        if over:
+            assert st & rz.RZ_STATUS_HQ_OVERFLOW
+        else:
+            assert st == 0
+            assert rz.to_u32(img)[3] == 0xFFFFFF
+        del pts
