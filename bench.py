@@ -87,6 +87,9 @@ def main():
     ap.add_argument("--workload", default="terrain50m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="verify one frame against the oracle")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="after the timed region, copy BYTES between two device buffers "
+                         "(a plain copy kernel of known size for scaling HBM counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the sharded "
@@ -173,7 +176,7 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["ms"] * kern[k]["launches_per_step"])
     dk = kern[dom]
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    tfile = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if os.path.exists(tfile):
         with open(tfile) as f:
             tr = json.load(f)
@@ -207,6 +210,14 @@ def main():
             "launch": rz.get_launch(),
         },
     }
+    if a.calibrate_copy:
+        src = torch.empty(a.calibrate_copy // 4, dtype=torch.int32, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {src.numel() * 4} bytes done")
+        del src, dst
     if not a.no_cpu_baseline:
         log("[bench] timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(cloud, view, eps)

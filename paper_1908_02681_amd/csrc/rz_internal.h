@@ -22,11 +22,11 @@ struct Proj {
 
 // Launch shape of the point kernels.
 struct Tune {
-    int block = 256;       // threads per workgroup (multiple of 64, <= 1024)
-    int ppt = 8;           // points per thread (multiple of 4, <= 16)
+    int block = 256;       // threads per workgroup: 64, 128, 256 or 512
+    int ppt = 16;          // points per thread: 4, 8 or 16
     int early_out = 1;     // read the framebuffer before the atomic
     int xcd_remap = 1;     // give each XCD a contiguous range of chunks
-    int bin = 0;           // LDS tile merge before the global atomics
+    int bin = 1;           // LDS tile merge before the global atomics
 };
 
 constexpr uint64_t kDepthOnes = 0xFFFFFFFFFF000000ull;

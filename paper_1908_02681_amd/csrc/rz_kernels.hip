@@ -23,10 +23,10 @@ namespace {
 constexpr double kQMax = 1099511627774.0;   // 2^40 - 2
 constexpr int kXcds = 8;                     // XCDs of an MI355X
 
-// The fragment of one point: pixel index and 40-bit depth (section 2.1).
-// Returns false when the point is discarded.
+// The fragment of one point: pixel coordinates and 40-bit depth (section
+// 2.1).  Returns false when the point is discarded.
 __device__ __forceinline__ bool fragment(const Proj &P, float x, float y, float z,
-                                         uint32_t &pix, uint64_t &q)
+                                         uint32_t &px, uint32_t &py, uint64_t &q)
 {
     float cx = P.m[0] * x;
     cx = cx + P.m[1] * y;
@@ -48,8 +48,8 @@ __device__ __forceinline__ bool fragment(const Proj &P, float x, float y, float 
     const float fy = (ny + 1.0f) * P.hh;
     if (!(fx >= 0.0f && fx < P.fw && fy >= 0.0f && fy < P.fh))
         return false;
-    const uint32_t px = (uint32_t)(int32_t)fx;
-    const uint32_t py = (uint32_t)(int32_t)fy;
+    px = (uint32_t)(int32_t)fx;
+    py = (uint32_t)(int32_t)fy;
 
     // depth in double precision (section 1, section 2.1)
     double d = P.v[0] * (double)x;
@@ -65,7 +65,6 @@ __device__ __forceinline__ bool fragment(const Proj &P, float x, float y, float 
     const uint32_t hi = (uint32_t)(tf * 0x1p-32);
     const uint32_t lo = (uint32_t)(tf - (double)hi * 0x1p32);
     q = ((uint64_t)hi << 32) | lo;
-    pix = py * (uint32_t)P.width + px;
     return true;
 }
 
@@ -139,18 +138,90 @@ __device__ __forceinline__ void load_points(const Pts &p, int64_t base, float (&
     }
 }
 
-// Depth pass (section 2.1): one 64-bit atomic minimum per surviving
-// fragment.  Two refinements that never change the result, because the
-// framebuffer only ever decreases and min is order independent:
-//  - consecutive fragments of one thread that hit the same pixel are merged
-//    in registers first;
-//  - with EARLY, the current framebuffer value is read first and the atomic
-//    is skipped when it is already <= the key (a stale read can only be
-//    larger than the true value, so the skip is always safe).
-template <int PPT, bool VEC, bool EARLY, bool XCD>
+// Minimum over the 64 lanes of a wave with DPP moves (all lanes active):
+// quads, 8-lane halves, 16-lane rows, then row broadcasts into lane 63.
+__device__ __forceinline__ uint32_t wave_min(uint32_t v)
+{
+#define RZ_DPP_MIN(ctrl, rows)                                                             \
+    {                                                                                      \
+        const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, ctrl,     \
+                                                                 rows, 0xF, false);        \
+        v = v < t ? v : t;                                                                 \
+    }
+    RZ_DPP_MIN(0xB1, 0xF)    // quad_perm [1,0,3,2]
+    RZ_DPP_MIN(0x4E, 0xF)    // quad_perm [2,3,0,1]
+    RZ_DPP_MIN(0x141, 0xF)   // row_half_mirror
+    RZ_DPP_MIN(0x140, 0xF)   // row_mirror
+    RZ_DPP_MIN(0x142, 0xA)   // row_bcast:15 into rows 1 and 3
+    RZ_DPP_MIN(0x143, 0xC)   // row_bcast:31 into rows 2 and 3
+#undef RZ_DPP_MIN
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Screen rectangle of the live fragments of the workgroup.  Every thread
+// must call it (it synchronises the workgroup); every thread gets the same
+// answer.  Empty when x0 > x1.
+struct Box {
+    uint32_t x0, y0, x1, y1;
+};
+
+template <int PPT>
+__device__ __forceinline__ Box block_box(const uint32_t (&px)[PPT], const uint32_t (&py)[PPT],
+                                         const bool (&live)[PPT], uint32_t (*s_box)[4])
+{
+    uint32_t m[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const uint32_t a = live[j] ? px[j] : 0xFFFFFFFFu;
+        const uint32_t b = live[j] ? py[j] : 0xFFFFFFFFu;
+        const uint32_t c = live[j] ? ~px[j] : 0xFFFFFFFFu;
+        const uint32_t d = live[j] ? ~py[j] : 0xFFFFFFFFu;
+        m[0] = a < m[0] ? a : m[0];
+        m[1] = b < m[1] ? b : m[1];
+        m[2] = c < m[2] ? c : m[2];
+        m[3] = d < m[3] ? d : m[3];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        m[k] = wave_min(m[k]);
+    const uint32_t wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            s_box[wave][k] = m[k];
+    }
+    __syncthreads();
+    const uint32_t nw = blockDim.x >> 6;
+    for (uint32_t w = 0; w < nw; ++w) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            m[k] = s_box[w][k] < m[k] ? s_box[w][k] : m[k];
+    }
+    return Box{m[0], m[1], ~m[2], ~m[3]};
+}
+
+constexpr int kMaxWaves = 512 / 64;
+constexpr uint32_t kTileMin = 4096;   // LDS tile of the depth pass: 32 KiB
+constexpr uint32_t kTileHq = 2048;    // LDS tile of the accumulate pass: 32 KiB
+
+// Depth pass (section 2.1): every surviving fragment takes part in a 64-bit
+// minimum per pixel.  None of the refinements below changes the result,
+// because min is order independent and the framebuffer only decreases:
+//  - consecutive fragments of a thread in one pixel are merged in registers;
+//  - BIN: when the workgroup's fragments fall in a small screen rectangle,
+//    they are merged with LDS atomics in a tile first, and the tile is
+//    flushed row by row (coalesced global atomics, one per touched pixel);
+//  - EARLY: the framebuffer is read first and the atomic skipped when it is
+//    already <= the key (a stale read can only be larger than the true
+//    value, so the skip is always safe).
+// Straight-line selects only: no array element is updated inside a
+// divergent branch (a form this compiler has been seen to mis-allocate).
+template <int PPT, bool VEC, bool EARLY, bool XCD, bool BIN>
 __global__ void __launch_bounds__(512) k_raster_min(Pts p, Proj P, uint64_t *__restrict__ fb,
                                                     int64_t nchunks)
 {
+    __shared__ uint64_t s_tile[BIN ? kTileMin : 1];
+    __shared__ uint32_t s_box[kMaxWaves][4];
     const int64_t chunk = chunk_index<XCD>();
     if (chunk >= nchunks)
         return;
@@ -160,17 +231,17 @@ __global__ void __launch_bounds__(512) k_raster_min(Pts p, Proj P, uint64_t *__r
     bool in[PPT];
     load_points<PPT, VEC>(p, base, x, y, z, c, in);
 
-    // Straight-line selects only: no array element is updated inside a
-    // divergent branch (a form this compiler has been seen to mis-allocate).
-    uint32_t pix[PPT];
+    uint32_t px[PPT], py[PPT], pix[PPT];
     uint64_t key[PPT];
     bool live[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         uint64_t q = 0;
-        uint32_t px = 0;
-        live[j] = in[j] && fragment(P, x[j], y[j], z[j], px, q);
-        pix[j] = px;
+        uint32_t a = 0, b = 0;
+        live[j] = in[j] && fragment(P, x[j], y[j], z[j], a, b, q);
+        px[j] = a;
+        py[j] = b;
+        pix[j] = b * (uint32_t)P.width + a;
         key[j] = (q << 24) | ((uint64_t)c[j] & kRgbMask);
     }
 #pragma unroll
@@ -180,21 +251,68 @@ __global__ void __launch_bounds__(512) k_raster_min(Pts p, Proj P, uint64_t *__r
         key[j] = same ? lo : key[j];
         live[j - 1] = live[j - 1] && !same;
     }
+
+    bool direct[PPT];
+    Box box{1, 1, 0, 0};
+    uint32_t bw = 0, bh = 0;
+    bool tiled = false;
+    if (BIN) {
+        box = block_box<PPT>(px, py, live, s_box);
+        if (box.x0 > box.x1)
+            return;   // no fragment in this workgroup (uniform)
+        bw = box.x1 - box.x0 + 1;
+        bh = box.y1 - box.y0 + 1;
+        tiled = (uint64_t)bw * bh <= kTileMin;
+    }
+    if (tiled) {
+        const uint32_t area = bw * bh;
+        for (uint32_t i = threadIdx.x; i < area; i += blockDim.x)
+            s_tile[i] = ~0ull;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const uint32_t tx = px[j] - box.x0, ty = py[j] - box.y0;
+            const bool inside = live[j] && tx < bw && ty < bh;
+            direct[j] = live[j] && !inside;
+            if (inside)
+                __hip_atomic_fetch_min(&s_tile[ty * bw + tx], key[j], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < area; i += blockDim.x) {
+            const uint64_t v = s_tile[i];
+            if (v != ~0ull) {
+                const uint32_t r = i / bw;
+                const uint32_t col = i - r * bw;
+                uint64_t *dst = fb + (uint64_t)(box.y0 + r) * (uint32_t)P.width + box.x0 + col;
+                const uint64_t cur = __hip_atomic_load(dst, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                if (v < cur)
+                    __hip_atomic_fetch_min(dst, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j)
+            direct[j] = live[j];
+    }
+
+    // fragments not merged in a tile go straight to the framebuffer
     if (EARLY) {
         uint64_t cur[PPT];
 #pragma unroll
         for (int j = 0; j < PPT; ++j)
-            cur[j] = __hip_atomic_load(fb + (live[j] ? pix[j] : 0u), __ATOMIC_RELAXED,
+            cur[j] = __hip_atomic_load(fb + (direct[j] ? pix[j] : 0u), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
         for (int j = 0; j < PPT; ++j)
-            if (live[j] && key[j] < cur[j])
+            if (direct[j] && key[j] < cur[j])
                 __hip_atomic_fetch_min(fb + pix[j], key[j], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
     } else {
 #pragma unroll
         for (int j = 0; j < PPT; ++j)
-            if (live[j])
+            if (direct[j])
                 __hip_atomic_fetch_min(fb + pix[j], key[j], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -202,15 +320,20 @@ __global__ void __launch_bounds__(512) k_raster_min(Pts p, Proj P, uint64_t *__r
 
 // Accumulation pass of high-quality splatting (section 2.2).  Reprojects
 // every point, compares its depth with the finished depth pass and, inside
-// the eps window, adds its colour and a count with two 64-bit atomic adds:
-// acc[2p] += R + (G << 32), acc[2p+1] += B + (1 << 32).  Consecutive
-// accepted fragments of one thread in the same pixel are summed first.
-template <int PPT, bool VEC, bool XCD>
+// the eps window, adds its colour and a count:
+//   acc[2p] += R + (G << 32),  acc[2p+1] += B + (1 << 32).
+// As in the depth pass, consecutive accepted fragments of a thread in one
+// pixel are summed in registers, and with BIN the workgroup's sums are
+// gathered in an LDS tile (64-bit LDS adds) and flushed once per pixel.
+// Integer sums are order independent, so every variant gives the same bits.
+template <int PPT, bool VEC, bool XCD, bool BIN>
 __global__ void __launch_bounds__(512) k_hq_accum(Pts p, Proj P, uint32_t eps_num,
                                                   uint32_t eps_den,
                                                   const uint64_t *__restrict__ fb,
                                                   uint64_t *__restrict__ acc, int64_t nchunks)
 {
+    __shared__ uint64_t s_tile[BIN ? 2 * kTileHq : 2];
+    __shared__ uint32_t s_box[kMaxWaves][4];
     const int64_t chunk = chunk_index<XCD>();
     if (chunk >= nchunks)
         return;
@@ -220,21 +343,21 @@ __global__ void __launch_bounds__(512) k_hq_accum(Pts p, Proj P, uint32_t eps_nu
     bool in[PPT];
     load_points<PPT, VEC>(p, base, x, y, z, c, in);
 
-    uint32_t pix[PPT];
+    uint32_t px[PPT], py[PPT], pix[PPT];
     uint64_t q[PPT];
     bool ok[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        uint32_t px = 0;
+        uint32_t a = 0, b = 0;
         uint64_t qq = 0;
-        ok[j] = in[j] && fragment(P, x[j], y[j], z[j], px, qq);
-        pix[j] = px;
+        ok[j] = in[j] && fragment(P, x[j], y[j], z[j], a, b, qq);
+        px[j] = a;
+        py[j] = b;
+        pix[j] = b * (uint32_t)P.width + a;
         q[j] = qq;
     }
-    // eps window against the finished depth pass; flags only, no in-branch
-    // updates of the arrays (see k_raster_min)
-    // all loads first (discarded fragments read pixel 0, always in bounds),
-    // so that they are in flight together
+    // eps window against the finished depth pass: all loads first
+    // (discarded fragments read pixel 0, always in bounds), then the tests
     uint64_t fbv[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j)
@@ -258,9 +381,57 @@ __global__ void __launch_bounds__(512) k_hq_accum(Pts p, Proj P, uint32_t eps_nu
         w1[j] += same ? w1[j - 1] : 0ull;
         ok[j - 1] = ok[j - 1] && !same;
     }
+
+    bool direct[PPT];
+    Box box{1, 1, 0, 0};
+    uint32_t bw = 0, bh = 0;
+    bool tiled = false;
+    if (BIN) {
+        box = block_box<PPT>(px, py, ok, s_box);
+        if (box.x0 > box.x1)
+            return;
+        bw = box.x1 - box.x0 + 1;
+        bh = box.y1 - box.y0 + 1;
+        tiled = (uint64_t)bw * bh <= kTileHq;
+    }
+    if (tiled) {
+        const uint32_t area = bw * bh;
+        for (uint32_t i = threadIdx.x; i < 2 * area; i += blockDim.x)
+            s_tile[i] = 0ull;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const uint32_t tx = px[j] - box.x0, ty = py[j] - box.y0;
+            const bool inside = ok[j] && tx < bw && ty < bh;
+            direct[j] = ok[j] && !inside;
+            if (inside) {
+                uint64_t *t = &s_tile[2 * (ty * bw + tx)];
+                __hip_atomic_fetch_add(t, w0[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(t + 1, w1[j], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < area; i += blockDim.x) {
+            const uint64_t a1 = s_tile[2 * i + 1];
+            if (a1 != 0ull) {
+                const uint64_t a0 = s_tile[2 * i];
+                const uint32_t r = i / bw;
+                const uint32_t col = i - r * bw;
+                uint64_t *dst =
+                    acc + 2 * ((uint64_t)(box.y0 + r) * (uint32_t)P.width + box.x0 + col);
+                __hip_atomic_fetch_add(dst, a0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(dst + 1, a1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j)
+            direct[j] = ok[j];
+    }
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        if (ok[j]) {
+        if (direct[j]) {
             uint64_t *a = acc + 2 * (uint64_t)pix[j];
             __hip_atomic_fetch_add(a, w0[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(a + 1, w1[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -355,36 +526,34 @@ bool aligned16(const void *ptr) { return ((uintptr_t)ptr & 15u) == 0; }
 
 int64_t blocks_for(int64_t n, int64_t per) { return (n + per - 1) / per; }
 
-template <int PPT, bool VEC, bool EARLY>
+template <int PPT, bool VEC, bool EARLY, bool BIN>
 hipError_t raster_min_ppt(const Pts &p, const Proj &P, uint64_t *fb, const Tune &t,
                           hipStream_t s)
 {
     const int64_t nchunks = blocks_for(p.n, (int64_t)t.block * PPT);
-    int64_t grid = nchunks;
     if (t.xcd_remap) {
-        grid = (nchunks + kXcds - 1) / kXcds * kXcds;
-        hipLaunchKernelGGL((k_raster_min<PPT, VEC, EARLY, true>), dim3((uint32_t)grid),
+        const int64_t grid = (nchunks + kXcds - 1) / kXcds * kXcds;
+        hipLaunchKernelGGL((k_raster_min<PPT, VEC, EARLY, true, BIN>), dim3((uint32_t)grid),
                            dim3(t.block), 0, s, p, P, fb, nchunks);
     } else {
-        hipLaunchKernelGGL((k_raster_min<PPT, VEC, EARLY, false>), dim3((uint32_t)grid),
+        hipLaunchKernelGGL((k_raster_min<PPT, VEC, EARLY, false, BIN>), dim3((uint32_t)nchunks),
                            dim3(t.block), 0, s, p, P, fb, nchunks);
     }
     return hipGetLastError();
 }
 
-template <int PPT, bool VEC>
+template <int PPT, bool VEC, bool BIN>
 hipError_t hq_accum_ppt(const Pts &p, const Proj &P, uint32_t num, uint32_t den,
                         const uint64_t *fb, uint64_t *acc, const Tune &t, hipStream_t s)
 {
     const int64_t nchunks = blocks_for(p.n, (int64_t)t.block * PPT);
-    int64_t grid = nchunks;
     if (t.xcd_remap) {
-        grid = (nchunks + kXcds - 1) / kXcds * kXcds;
-        hipLaunchKernelGGL((k_hq_accum<PPT, VEC, true>), dim3((uint32_t)grid), dim3(t.block),
-                           0, s, p, P, num, den, fb, acc, nchunks);
+        const int64_t grid = (nchunks + kXcds - 1) / kXcds * kXcds;
+        hipLaunchKernelGGL((k_hq_accum<PPT, VEC, true, BIN>), dim3((uint32_t)grid),
+                           dim3(t.block), 0, s, p, P, num, den, fb, acc, nchunks);
     } else {
-        hipLaunchKernelGGL((k_hq_accum<PPT, VEC, false>), dim3((uint32_t)grid), dim3(t.block),
-                           0, s, p, P, num, den, fb, acc, nchunks);
+        hipLaunchKernelGGL((k_hq_accum<PPT, VEC, false, BIN>), dim3((uint32_t)nchunks),
+                           dim3(t.block), 0, s, p, P, num, den, fb, acc, nchunks);
     }
     return hipGetLastError();
 }
@@ -394,6 +563,33 @@ bool planes_aligned(const Pts &p)
     return aligned16(p.x) && aligned16(p.y) && aligned16(p.z) && aligned16(p.rgb);
 }
 
+template <int PPT>
+hipError_t raster_min_dispatch(const Pts &p, const Proj &P, uint64_t *fb, const Tune &t,
+                               hipStream_t s)
+{
+    const bool vec = planes_aligned(p);
+    if (!vec)   // unaligned planes: scalar loads, one shape
+        return t.bin ? raster_min_ppt<PPT, false, true, true>(p, P, fb, t, s)
+                     : raster_min_ppt<PPT, false, true, false>(p, P, fb, t, s);
+    if (t.bin)
+        return t.early_out ? raster_min_ppt<PPT, true, true, true>(p, P, fb, t, s)
+                           : raster_min_ppt<PPT, true, false, true>(p, P, fb, t, s);
+    return t.early_out ? raster_min_ppt<PPT, true, true, false>(p, P, fb, t, s)
+                       : raster_min_ppt<PPT, true, false, false>(p, P, fb, t, s);
+}
+
+template <int PPT>
+hipError_t hq_accum_dispatch(const Pts &p, const Proj &P, uint32_t num, uint32_t den,
+                             const uint64_t *fb, uint64_t *acc, const Tune &t, hipStream_t s)
+{
+    const bool vec = planes_aligned(p);
+    if (vec)
+        return t.bin ? hq_accum_ppt<PPT, true, true>(p, P, num, den, fb, acc, t, s)
+                     : hq_accum_ppt<PPT, true, false>(p, P, num, den, fb, acc, t, s);
+    return t.bin ? hq_accum_ppt<PPT, false, true>(p, P, num, den, fb, acc, t, s)
+                 : hq_accum_ppt<PPT, false, false>(p, P, num, den, fb, acc, t, s);
+}
+
 }  // namespace
 
 hipError_t launch_raster_min(const Pts &p, const Proj &P, uint64_t *fb, const Tune &t,
@@ -401,22 +597,12 @@ hipError_t launch_raster_min(const Pts &p, const Proj &P, uint64_t *fb, const Tu
 {
     if (p.n == 0)
         return hipSuccess;
-    const bool vec = planes_aligned(p);
-#define RZ_RASTER_CASE(PPT)                                                       \
-    case PPT:                                                                     \
-        if (vec)                                                                  \
-            return t.early_out ? raster_min_ppt<PPT, true, true>(p, P, fb, t, s)  \
-                               : raster_min_ppt<PPT, true, false>(p, P, fb, t, s); \
-        return t.early_out ? raster_min_ppt<PPT, false, true>(p, P, fb, t, s)     \
-                           : raster_min_ppt<PPT, false, false>(p, P, fb, t, s);
     switch (t.ppt) {
-        RZ_RASTER_CASE(4)
-        RZ_RASTER_CASE(8)
-        RZ_RASTER_CASE(16)
-    default:
-        return hipErrorInvalidValue;
+    case 4: return raster_min_dispatch<4>(p, P, fb, t, s);
+    case 8: return raster_min_dispatch<8>(p, P, fb, t, s);
+    case 16: return raster_min_dispatch<16>(p, P, fb, t, s);
+    default: return hipErrorInvalidValue;
     }
-#undef RZ_RASTER_CASE
 }
 
 hipError_t launch_hq_accum(const Pts &p, const Proj &P, uint32_t num, uint32_t den,
@@ -424,19 +610,11 @@ hipError_t launch_hq_accum(const Pts &p, const Proj &P, uint32_t num, uint32_t d
 {
     if (p.n == 0)
         return hipSuccess;
-    const bool vec = planes_aligned(p);
     switch (t.ppt) {
-    case 4:
-        return vec ? hq_accum_ppt<4, true>(p, P, num, den, fb, acc, t, s)
-                   : hq_accum_ppt<4, false>(p, P, num, den, fb, acc, t, s);
-    case 8:
-        return vec ? hq_accum_ppt<8, true>(p, P, num, den, fb, acc, t, s)
-                   : hq_accum_ppt<8, false>(p, P, num, den, fb, acc, t, s);
-    case 16:
-        return vec ? hq_accum_ppt<16, true>(p, P, num, den, fb, acc, t, s)
-                   : hq_accum_ppt<16, false>(p, P, num, den, fb, acc, t, s);
-    default:
-        return hipErrorInvalidValue;
+    case 4: return hq_accum_dispatch<4>(p, P, num, den, fb, acc, t, s);
+    case 8: return hq_accum_dispatch<8>(p, P, num, den, fb, acc, t, s);
+    case 16: return hq_accum_dispatch<16>(p, P, num, den, fb, acc, t, s);
+    default: return hipErrorInvalidValue;
     }
 }
 

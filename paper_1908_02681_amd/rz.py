@@ -288,7 +288,8 @@ def hq_accumulate(points: Points, view, fb, acc, depth=None, eps=(1, 100), strea
     return acc
 
 
-def set_launch(block=256, ppt=8, early_out=1, xcd_remap=1, bin=0):
+def set_launch(block=256, ppt=16, early_out=1, xcd_remap=1, bin=1):
+    """Launch shape of the point kernels (defaults = the library's)."""
     _check(load().rz_set_launch(ctypes.byref(rz_launch(block, ppt, early_out, xcd_remap, bin))),
            "rz_set_launch")
 

@@ -125,7 +125,8 @@ def test_ragged_sizes(rz, oracle, n):
     check_scene(rz, oracle, cloud, view, label=f"ragged n={n}")
 
 
-LAUNCHES = [(b, p, e, x) for b in (64, 256, 512) for p in (4, 8, 16) for e in (0, 1) for x in (0, 1)]
+LAUNCHES = [(b, p, e, x, n) for b in (64, 256, 512) for p in (4, 8, 16) for e in (0, 1)
+            for x in (0, 1) for n in (0, 1)]
 
 
 def test_every_launch_shape_is_bit_identical(rz, oracle):
@@ -137,13 +138,36 @@ def test_every_launch_shape_is_bit_identical(rz, oracle):
                                           view.far, view.width, view.height)
     pts = rz.Points.from_cloud(cloud)
     try:
-        for b, p, e, x in LAUNCHES:
-            say(f"[launch] block={b} ppt={p} early={e} xcd={x}")
-            rz.set_launch(b, p, e, x)
+        for b, p, e, x, n in LAUNCHES:
+            say(f"[launch] block={b} ppt={p} early={e} xcd={x} bin={n}")
+            rz.set_launch(b, p, e, x, n)
             keys, _, _ = gpu_min(rz, pts, view)
             assert np.array_equal(keys, ok_keys)
             _, sums, img, *_ = gpu_hq(rz, pts, view)
             assert np.array_equal(sums, ok_sums) and np.array_equal(img, ok_img)
+    finally:
+        rz.set_launch()
+
+
+@pytest.mark.parametrize("bin_", [0, 1])
+def test_tile_fallback_and_sparse_screens(rz, oracle, bin_):
+    """Workgroups whose fragments span more than one LDS tile (random points
+    over a wide screen) take the direct path; both give the oracle's bits."""
+    rng = np.random.default_rng(12)
+    n = 300_000
+    cloud = gen.Cloud(rng.uniform(-1, 1, n).astype(np.float32), rng.uniform(-1, 1, n).astype(np.float32),
+                      rng.uniform(0, 1, n).astype(np.float32),
+                      rng.integers(0, 1 << 24, n, dtype=np.uint32))
+    vp = np.eye(4)
+    vp[3, :] = [0, 0, 0.5, 1.0]
+    view = gen.View(vp, 0.9, 2.0, 1500, 900)
+    try:
+        rz.set_launch(bin=bin_)
+        check_scene(rz, oracle, cloud, view, label=f"wide random bin={bin_}")
+        # a Morton terrain clipped by the screen edge: tiles at the border
+        t = gen.terrain(400_000, 8, extent=100.0, amplitude=10.0, wavelength=40.0)
+        v2 = gen.terrain_view(300, 200, extent=100.0, distance=60.0, near=0.5, far=400.0)
+        check_scene(rz, oracle, t, v2, label=f"clipped terrain bin={bin_}")
     finally:
         rz.set_launch()
 
