@@ -79,6 +79,241 @@ def cpu_baseline(cloud, view, eps, budget_s=20.0):
     }
 
 
+BATCH_SIZES = [(256, 256), (640, 480), (1280, 720), (1920, 1080)]
+
+
+def bench_batch(a):
+    """64 views of one resident 100M-point terrain: one autotuned, graph-captured
+    batch against the loop of 64 one-view calls (same views, same bits)."""
+    import torch
+    from paper_1908_02681_amd import gen, rz
+
+    n = a.batch_points
+    log(f"[batch] generating terrain {n}")
+    cloud = gen.terrain(n, gen.CONFIG_SEEDS[4])
+    views = gen.orbit_views(a.batch_views, gen.CONFIG_SEEDS[4], BATCH_SIZES)
+    rng = np.random.default_rng([gen.CONFIG_SEEDS[4], 7])
+    modes = rng.integers(0, 2, len(views)).tolist()
+    pts = rz.Points.from_cloud(cloud)
+    del cloud
+    npix = sum(v.width * v.height for v in views)
+    log(f"[batch] {len(views)} views, {npix / 1e6:.1f} Mpx, {sum(modes)} splatting")
+
+    # plain loop: one call per view, buffers allocated once
+    bufs = []
+    for v, m in zip(views, modes):
+        fb, acc = rz.new_framebuffer(v, 0, hq=(m == 1))
+        img = torch.empty(v.width * v.height, dtype=torch.int32, device="cuda")
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        bufs.append((fb, acc, img, st))
+
+    def plain():
+        for v, m, (fb, acc, img, st) in zip(views, modes, bufs):
+            if m == 0:
+                rz.rasterize_atomicmin(pts, v, fb=fb, img=img)
+            else:
+                rz.rasterize_hq_splat(pts, v, fb=fb, acc=acc, img=img, status=st)
+
+    b = rz.Batch(pts, views, modes, use_graph=True)
+    chosen, tuned_ms = b.autotune(reps=2)
+    log(f"[batch] autotuned {chosen} ({tuned_ms:.3f} ms)")
+
+    def timed(fn, steps, warm):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    ms_plain = timed(plain, a.steps, a.warmup)
+    ms_batch = timed(b.run, a.steps, a.warmup)
+    same = all(torch.equal(img, bimg) for (_, _, img, _), bimg in zip(bufs, b.imgs))
+    log(f"[batch] plain {ms_plain:.3f} ms, batched {ms_batch:.3f} ms, identical={same}")
+    if not same:
+        raise SystemExit("batched images differ from the one-view calls")
+    work = n * len(views)
+    out = {
+        "metric": METRIC, "value": round(work / (ms_batch * 1e-3) / 1e9, 3), "unit": "Gpoints/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_batch, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64->u64",
+        "data": "synthetic",
+        "config": {"workload": f"batched multi-view: terrain {n} points (Morton order), "
+                               f"{len(views)} orbit cameras, resolutions {BATCH_SIZES}, "
+                               f"{sum(modes)} splatting / {len(views) - sum(modes)} atomicMin",
+                   "points": n, "views": len(views), "pixels": npix},
+        "detail": {"plain_loop_ms": round(ms_plain, 4),
+                   "plain_loop_gpts": round(work / (ms_plain * 1e-3) / 1e9, 3),
+                   "speedup_vs_plain": round(ms_plain / ms_batch, 3),
+                   "autotuned": chosen, "bit_identical_to_plain": same},
+    }
+    print(json.dumps(out), flush=True)
+
+
+SERVE_SIZES = [(256, 256), (640, 480), (1280, 720), (1920, 1080), (2560, 1440)]
+SERVE_CLOUDS = [1_000_000, 5_000_000, 20_000_000, 50_000_000, 100_000_000, 150_000_000,
+                200_000_000, 300_000_000]
+
+
+def serve_trace(n, rate, seed, nclouds):
+    """Poisson arrivals; each request picks a cloud, a resolution, a method
+    and a random orbit camera uniformly."""
+    from paper_1908_02681_amd import gen
+    rng = np.random.default_rng([seed, int(rate)])
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n))
+    out = []
+    for i in range(n):
+        c = int(rng.integers(0, nclouds))
+        w, h = SERVE_SIZES[int(rng.integers(0, len(SERVE_SIZES)))]
+        if c == 0:
+            v = gen.orbit_views(1, int(rng.integers(1 << 30)), [(w, h)], extent=1.0, rmin=1.5,
+                                rmax=3.0, elev=(-60.0, 60.0), near=0.01, far=10.0)[0]
+        else:
+            v = gen.orbit_views(1, int(rng.integers(1 << 30)), [(w, h)])[0]
+        out.append((float(arrivals[i]), c, v, int(rng.integers(0, 2))))
+    return out
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q)) if len(a) else float("nan")
+
+
+def bench_serve(a):
+    """Continuous-batching server vs the FIFO one-call-per-request loop on the
+    same Poisson traces over 8 resident clouds."""
+    import torch
+    from paper_1908_02681_amd import gen, rz
+
+    clouds = SERVE_CLOUDS[:a.serve_clouds]
+    pts, npts = [], []
+    for i, n in enumerate(clouds):
+        log(f"[serve] generating cloud {i}: {n} points")
+        c = gen.config1(n=n)[0] if i == 0 else gen.terrain(n, gen.CONFIG_SEEDS[5] * 10 + i)
+        pts.append(rz.Points.from_cloud(c))
+        npts.append(n)
+        del c
+    torch.cuda.synchronize()
+    log(f"[serve] {sum(npts) / 1e6:.0f}M points resident")
+    # one reusable output image ring per resolution (requests in flight never share)
+    ring = a.serve_ring
+    imgs = {sz: [torch.empty(sz[0] * sz[1], dtype=torch.int32, device="cuda") for _ in range(ring)]
+            for sz in SERVE_SIZES}
+    # plain loop buffers: one fb/acc per resolution
+    fbs = {sz: rz.new_framebuffer(gen.View(np.eye(4), 1, 2, *sz), 0, hq=True) for sz in SERVE_SIZES}
+    st_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def plain_one(c, v, m, img):
+        fb, acc = fbs[(v.width, v.height)]
+        if m == 0:
+            rz.rasterize_atomicmin(pts[c], v, fb=fb, img=img)
+        else:
+            rz.rasterize_hq_splat(pts[c], v, fb=fb, acc=acc, img=img, status=st_dev)
+
+    def run_plain(trace):
+        lat, done_t = [], []
+        t0 = time.perf_counter()
+        for k, (t_arr, c, v, m) in enumerate(trace):
+            while time.perf_counter() - t0 < t_arr:
+                pass
+            plain_one(c, v, m, imgs[(v.width, v.height)][k % ring])
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            lat.append((t - t_arr) * 1e3)
+            done_t.append(t)
+        return lat, trace[0][0], done_t[-1]
+
+    def run_server(trace):
+        srv = rz.Server(a.serve_budget, streams=a.serve_streams)
+        ids = [srv.add_cloud(p) for p in pts]
+        pending, status = {}, {}
+        slot_owner = {sz: [None] * ring for sz in SERVE_SIZES}
+
+        def reap(block=False):
+            for t in list(pending):
+                st = srv.poll(t)
+                if st["state"] >= rz.RZ_REQ_DONE:
+                    status[t] = st
+                    del pending[t]
+        t0 = time.perf_counter()
+        base_us = None
+        tick = []
+        for k, (t_arr, c, v, m) in enumerate(trace):
+            while time.perf_counter() - t0 < t_arr:
+                if pending:
+                    reap()
+            sz = (v.width, v.height)
+            j = k % ring
+            prev = slot_owner[sz][j]
+            while prev is not None and prev in pending:
+                reap()
+            late = time.perf_counter() - t0 - t_arr   # time spent before submission
+            t = srv.submit(ids[c], v, m, img=imgs[sz][j])
+            slot_owner[sz][j] = t
+            pending[t] = k
+            tick.append((t, late))
+        srv.drain(600)
+        reap()
+        stats = srv.stats()
+        srv.close()
+        sts = [status[t] for t, _ in tick]
+        if any(x["state"] != rz.RZ_REQ_DONE for x in sts):
+            raise SystemExit("server request failed")
+        # latency from arrival: the server's submit-to-done time plus any wait
+        # of the request before it could be submitted
+        lat = [(x["t_done_us"] - x["t_submit_us"]) / 1e3 + late * 1e3
+               for x, (_, late) in zip(sts, tick)]
+        first_arrival_us = sts[0]["t_submit_us"] - tick[0][1] * 1e6
+        span = (max(x["t_done_us"] for x in sts) - first_arrival_us) / 1e6
+        return lat, span, stats
+
+    # capacity of the plain loop: back-to-back requests
+    probe = serve_trace(200, 1e9, gen.CONFIG_SEEDS[5], len(pts))
+    for _ in range(2):
+        run_plain(probe[:20])
+    lat, _, t_end = run_plain(probe)
+    cap = len(probe) / t_end
+    log(f"[serve] plain loop capacity ~{cap:.0f} req/s")
+    rows = []
+    for f in a.serve_loads:
+        rate = f * cap
+        trace = serve_trace(a.serve_requests, rate, gen.CONFIG_SEEDS[5], len(pts))
+        work = sum(npts[c] for _, c, _, _ in trace)
+        lp, _, tp_end = run_plain(trace)
+        ls, span, stats = run_server(trace)
+        row = {"offered_req_s": round(rate, 1),
+               "server": {"req_s": round(len(trace) / span, 1),
+                          "gpts": round(work / span / 1e9, 2),
+                          "p50_ms": round(pct(ls, 50), 3), "p99_ms": round(pct(ls, 99), 3),
+                          "peak_inflight": stats["peak_inflight"],
+                          "peak_fb_MB": round(stats["peak_bytes"] / 1e6, 1)},
+               "plain": {"req_s": round(len(trace) / (tp_end - trace[0][0]), 1),
+                         "gpts": round(work / (tp_end - trace[0][0]) / 1e9, 2),  # same span rule
+                         "p50_ms": round(pct(lp, 50), 3), "p99_ms": round(pct(lp, 99), 3)}}
+        log(f"[serve] load {f:.2f}: {row}")
+        rows.append(row)
+    top = rows[-1]
+    out = {
+        "metric": METRIC, "value": top["server"]["gpts"], "unit": "Gpoints/s", "n_gpus": 1,
+        "steps": a.serve_requests, "warmup": 0,
+        "ms_per_step": round(1e3 / top["server"]["req_s"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64->u64", "data": "synthetic",
+        "config": {"workload": f"serving: {len(pts)} resident clouds "
+                               f"({', '.join(f'{n // 1_000_000}M' for n in npts)} points), Poisson "
+                               f"arrivals, resolutions {SERVE_SIZES}, methods 50/50, "
+                               f"framebuffer budget {a.serve_budget >> 20} MiB, "
+                               f"{a.serve_streams} streams",
+                   "requests_per_rate": a.serve_requests, "plain_capacity_req_s": round(cap, 1)},
+        "detail": {"rates": rows,
+                   "p50_ms": top["server"]["p50_ms"], "p99_ms": top["server"]["p99_ms"],
+                   "plain_p50_ms": top["plain"]["p50_ms"], "plain_p99_ms": top["plain"]["p99_ms"],
+                   "throughput_vs_plain": round(top["server"]["req_s"] / top["plain"]["req_s"], 3)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +322,14 @@ def main():
     ap.add_argument("--workload", default="terrain50m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="verify one frame against the oracle")
+    ap.add_argument("--batch-points", type=int, default=100_000_000)
+    ap.add_argument("--batch-views", type=int, default=64)
+    ap.add_argument("--serve-clouds", type=int, default=8)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-budget", type=int, default=4 << 30)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-ring", type=int, default=96)
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 1.0, 1.3, 2.0])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="after the timed region, copy BYTES between two device buffers "
                          "(a plain copy kernel of known size for scaling HBM counters)")
@@ -100,6 +343,10 @@ def main():
     from paper_1908_02681_amd import rz
 
     assert torch.cuda.is_available(), "bench needs a HIP device"
+    if a.workload == "batch64":
+        return bench_batch(a)
+    if a.workload == "serve":
+        return bench_serve(a)
     eps = (1, 100)
     log(f"[bench] generating {a.workload}")
     cloud, view, desc = workload(a.workload)

@@ -186,8 +186,10 @@ int rz_resolve_hq(uint64_t *fb, uint64_t *acc, int64_t npix,
  *   ppt        points per thread: 4, 8 or 16.
  *   early_out  1: read the framebuffer and skip atomics that cannot lower it.
  *   xcd_remap  1: give each of the 8 XCDs one contiguous eighth of the points.
- *   bin        1: merge fragments of a workgroup in an LDS tile first (when
- *              they fall in a small screen rectangle); 0: direct atomics.
+ *   bin        how fragments are merged before the global atomics:
+ *              0: none (direct atomics); 1: one LDS tile per workgroup (when
+ *              its fragments fall in a small screen rectangle); 2: one LDS
+ *              tile per wave (no workgroup barrier).
  */
 typedef struct rz_launch {
     int32_t block;
@@ -198,6 +200,148 @@ typedef struct rz_launch {
 } rz_launch;
 int rz_set_launch(const rz_launch *launch);   /* RZ_EINVAL if out of range */
 int rz_get_launch(rz_launch *launch);
+
+/* ---- batched multi-view rendering ------------------------------------ */
+/*
+ * Many views of one resident cloud in one submission.  Views are taken in
+ * groups of K: a group's depth passes (section 2.1) read every point once and
+ * project it into all K views; the splatting views of the group then share
+ * one accumulate pass (section 2.2); one kernel resolves every view.  Each
+ * view's fb, acc and img are bit-identical to those of the one-view calls.
+ */
+#define RZ_MODE_ATOMICMIN 0
+#define RZ_MODE_HQ 1
+
+typedef struct rz_batch_view {
+    rz_view view;          /* camera and size, as for the one-view calls       */
+    rz_depth_map depth;
+    int32_t mode;          /* RZ_MODE_ATOMICMIN or RZ_MODE_HQ                 */
+    rz_hq_params hq;       /* RZ_MODE_HQ only; eps_den == 0 means 1/100        */
+    uint32_t background;
+    uint64_t *fb;          /* device, width*height, cleared on entry; cleared
+                              again by every run                               */
+    uint64_t *acc;         /* device, 2*width*height, zero; RZ_MODE_HQ only    */
+    uint32_t *img;         /* device, width*height, written by every run       */
+} rz_batch_view;
+
+typedef struct rz_batch_opts {
+    int32_t views_per_group;  /* K in 1..8; 0 = 4                              */
+    rz_launch launch;         /* launch shape; block == 0 = library default   */
+    int32_t use_graph;        /* 1: runs replay one captured hipGraph          */
+    uint32_t *status;         /* device or NULL: RZ_STATUS_HQ_OVERFLOW, as for
+                                 rasterize_hq_splat                            */
+} rz_batch_opts;
+
+typedef struct rz_batch rz_batch;   /* opaque; owns a small device table and,
+                                       once captured, a hipGraph */
+
+/* Validates every view (RZ_EINVAL / RZ_EDEPTHRANGE as the one-view calls),
+   uploads the view table (one hipMalloc, synchronous) and returns the
+   batch.  The points and the caller's buffers must outlive the batch.
+   1 <= nviews <= 4096.  opts may be NULL (defaults, no graph). */
+int rz_batch_plan(const rz_points *pts, const rz_batch_view *views,
+                  int32_t nviews, const rz_batch_opts *opts, rz_batch **out);
+/* Records the batch's kernels into a hipGraph (on an internal stream) and
+   instantiates it; later runs replay it on the caller's stream. */
+int rz_batch_capture(rz_batch *b);
+/* Renders every view, asynchronously on `stream`. */
+int rz_batch_run(rz_batch *b, void *stream);
+/* Times the batch under candidate launch shapes and group sizes (reps runs
+   each, median), keeps the fastest whose images hash to the same value as
+   the first candidate's, and re-captures if the batch had a graph.  Runs
+   synchronously on `stream`.  chosen may be NULL. */
+int rz_batch_autotune(rz_batch *b, void *stream, int32_t reps, rz_batch_opts *chosen,
+                      float *best_ms);
+/* Current options of the batch. */
+int rz_batch_get_opts(const rz_batch *b, rz_batch_opts *opts);
+/* Frees the table and the graph (waits for nothing: the caller must not
+   destroy a batch whose run is still in flight). */
+int rz_batch_destroy(rz_batch *b);
+
+/* ---- serving: continuous batching of render requests ----------------- */
+/*
+ * A render server keeps point clouds resident and runs requests (one view of
+ * one cloud, either method) as they arrive.  A scheduler thread admits
+ * queued requests in arrival order whenever the framebuffer memory they need
+ * (fb, plus acc for splatting) fits the server's device budget and an
+ * in-flight slot is free, and spreads admitted requests over several HIP
+ * streams so that their kernels overlap on the device.  A request's image is
+ * bit-identical to the one-view call's, whatever else runs beside it.
+ */
+#define RZ_REQ_QUEUED 0
+#define RZ_REQ_RUNNING 1
+#define RZ_REQ_DONE 2
+#define RZ_REQ_FAILED 3
+
+/* rz_request.flags: the scheduler fails this request on purpose, as if its
+   launch had failed (host-side fault injection for tests of error
+   isolation; the device never sees the request). */
+#define RZ_REQ_INJECT_FAILURE 1u
+
+typedef struct rz_server_opts {
+    uint64_t budget_bytes;   /* device memory for framebuffers; allocated once
+                                at creation (>= 1 MiB)                         */
+    int32_t streams;         /* HIP streams, 1..16; 0 = 4                     */
+    int32_t max_inflight;    /* admitted and unfinished requests; 0 = 4*streams */
+    int32_t dry_run;         /* 1: no device work at all; a request "runs" for
+                                dry_run_us on the host (tests of admission and
+                                error handling without a GPU)                  */
+    int32_t dry_run_us;
+} rz_server_opts;
+
+typedef struct rz_request {
+    int32_t cloud;           /* id returned by rz_server_add_cloud             */
+    int32_t mode;            /* RZ_MODE_ATOMICMIN or RZ_MODE_HQ                */
+    rz_view view;
+    rz_depth_map depth;
+    rz_hq_params hq;         /* RZ_MODE_HQ; eps_den == 0 means 1/100           */
+    uint32_t background;
+    uint32_t flags;          /* 0 or RZ_REQ_INJECT_FAILURE                     */
+    uint32_t *img;           /* device, width*height, caller-owned; written by
+                                the time the request is RZ_REQ_DONE            */
+} rz_request;
+
+typedef struct rz_request_status {
+    int32_t state;           /* RZ_REQ_*                                      */
+    int32_t error;           /* RZ_OK, or the RZ_E* code of a failed request  */
+    uint32_t hq_status;      /* RZ_STATUS_HQ_OVERFLOW bits (RZ_MODE_HQ)        */
+    uint32_t stream;         /* stream index the request ran on               */
+    double t_submit_us;      /* host steady clock, microseconds since the
+                                server was created                            */
+    double t_admit_us;
+    double t_done_us;        /* when the scheduler saw the request complete   */
+} rz_request_status;
+
+typedef struct rz_server_stats {
+    uint64_t submitted, completed, failed;
+    uint64_t peak_bytes;     /* largest framebuffer memory in use at once     */
+    int32_t peak_inflight;
+    int32_t queued;          /* waiting for admission now                     */
+    int32_t inflight;        /* admitted and unfinished now                   */
+    int32_t pad;
+} rz_server_stats;
+
+typedef struct rz_server rz_server;
+
+/* Creates the server: one device allocation of budget_bytes (none with
+   dry_run), the streams, and the scheduler thread. */
+int rz_server_create(const rz_server_opts *opts, rz_server **out);
+/* Registers a resident cloud (device planes, caller-owned, must outlive the
+   server).  Ids are 0, 1, 2, ... */
+int rz_server_add_cloud(rz_server *s, const rz_points *pts, int32_t *id);
+/* Queues a request; returns at once with a ticket.  RZ_EBUDGET if the
+   request could never fit the budget; RZ_EINVAL / RZ_EDEPTHRANGE as the
+   one-view calls.  Thread-safe. */
+int rz_server_submit(rz_server *s, const rz_request *req, uint64_t *ticket);
+/* State of a ticket (non-blocking).  A finished ticket is forgotten after
+   it has been reported once as RZ_REQ_DONE or RZ_REQ_FAILED. */
+int rz_server_poll(rz_server *s, uint64_t ticket, rz_request_status *st);
+/* Waits until every submitted request has finished (or timeout_s passed:
+   RZ_ESTATE). */
+int rz_server_drain(rz_server *s, double timeout_s);
+int rz_server_get_stats(rz_server *s, rz_server_stats *st);
+/* Drains, stops the scheduler, frees the streams and the budget. */
+int rz_server_destroy(rz_server *s);
 
 /* Name of an RZ_* return code (static string). */
 const char *rz_error_string(int code);

@@ -220,7 +220,7 @@ int rz_set_launch(const rz_launch *l)
         return RZ_EINVAL;
     if (!(l->ppt == 4 || l->ppt == 8 || l->ppt == 16))
         return RZ_EINVAL;
-    if ((l->early_out & ~1) || (l->xcd_remap & ~1) || (l->bin & ~1))
+    if ((l->early_out & ~1) || (l->xcd_remap & ~1) || l->bin < 0 || l->bin > 2)
         return RZ_EINVAL;
     g_tune.block = l->block;
     g_tune.ppt = l->ppt;

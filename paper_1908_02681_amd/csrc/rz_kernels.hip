@@ -1,442 +1,68 @@
-// HIP kernels of the point rasterizer for gfx950 (MI355X).
+// Single-view HIP kernels of the point rasterizer for gfx950 (MI355X) and
+// their launchers: the depth pass (k_raster_min), the accumulate pass of
+// high-quality splatting (k_hq_accum), the two resolve passes and clear.
 //
 // Method: Schuetz & Wimmer, "Rendering Point Clouds with Compute Shaders"
-// (arXiv 1908.02681), section 2.1 (atomicMin rasterization, resolve/clear)
-// and section 2.2 (high-quality splatting: depth pass, eps-window
-// accumulation, normalisation).
-//
-// Floating point: this file must be compiled with -ffp-contract=off (and
-// the pragma below repeats it), so that the projection is the exact IEEE
-// sequence of operations stated in include/rz.h: no fused multiply-add,
-// correctly rounded f32 division, no flush of denormals.
+// (arXiv 1908.02681), section 2.1 and section 2.2.  The per-chunk bodies
+// live in rz_device.h, shared with the multi-view batch kernels.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "rz.h"
+#include "rz_device.h"
 #include "rz_internal.h"
-
-#pragma clang fp contract(off)
 
 namespace rz {
 namespace {
 
-constexpr double kQMax = 1099511627774.0;   // 2^40 - 2
-constexpr int kXcds = 8;                     // XCDs of an MI355X
+using namespace dev;
 
-// The fragment of one point: pixel coordinates and 40-bit depth (section
-// 2.1).  Returns false when the point is discarded.
-__device__ __forceinline__ bool fragment(const Proj &P, float x, float y, float z,
-                                         uint32_t &px, uint32_t &py, uint64_t &q)
-{
-    float cx = P.m[0] * x;
-    cx = cx + P.m[1] * y;
-    cx = cx + P.m[2] * z;
-    cx = cx + P.m[3];
-    float cy = P.m[4] * x;
-    cy = cy + P.m[5] * y;
-    cy = cy + P.m[6] * z;
-    cy = cy + P.m[7];
-    float cw = P.m[8] * x;
-    cw = cw + P.m[9] * y;
-    cw = cw + P.m[10] * z;
-    cw = cw + P.m[11];
-    if (!(cw > 0.0f))
-        return false;
-    const float nx = cx / cw;
-    const float ny = cy / cw;
-    const float fx = (nx + 1.0f) * P.hw;
-    const float fy = (ny + 1.0f) * P.hh;
-    if (!(fx >= 0.0f && fx < P.fw && fy >= 0.0f && fy < P.fh))
-        return false;
-    px = (uint32_t)(int32_t)fx;
-    py = (uint32_t)(int32_t)fy;
-
-    // depth in double precision (section 1, section 2.1)
-    double d = P.v[0] * (double)x;
-    d = d + P.v[1] * (double)y;
-    d = d + P.v[2] * (double)z;
-    d = d + P.v[3];
-    if (!(d >= P.near_ && d < P.far_))
-        return false;
-    double tf = floor((d - P.o) * P.s);
-    if (tf > kQMax)
-        tf = kQMax;
-    // 0 <= tf < 2^40: split into two exact 32-bit halves
-    const uint32_t hi = (uint32_t)(tf * 0x1p-32);
-    const uint32_t lo = (uint32_t)(tf - (double)hi * 0x1p32);
-    q = ((uint64_t)hi << 32) | lo;
-    return true;
-}
-
-// Workgroup -> chunk of points.  Workgroups are dealt round-robin to the 8
-// XCDs; with the remap, XCD k works through the k-th eighth of the point
-// array, so spatially coherent (e.g. Morton-ordered) ranges share one L2.
-template <bool XCD>
-__device__ __forceinline__ int64_t chunk_index()
-{
-    const int64_t b = blockIdx.x;
-    if (!XCD)
-        return b;
-    const int64_t per = gridDim.x / kXcds;   // grid is a multiple of 8
-    return (b % kXcds) * per + b / kXcds;
-}
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
-
-// Streaming (non-temporal) access: the data is touched once.
-template <typename T>
-__device__ __forceinline__ T ldnt(const T *p) { return __builtin_nontemporal_load(p); }
-template <typename T>
-__device__ __forceinline__ void stnt(T v, T *p) { __builtin_nontemporal_store(v, p); }
-
-// Loads the PPT points of this thread.  Vector form: PPT/4 groups of four
-// consecutive points, group g at chunk + g*4*blockDim + 4*tid, so every
-// load instruction of a wave reads one contiguous 1 KiB span per plane.
-// Scalar form (tail chunk or unaligned planes): same point indices, bounds
-// checked one by one.
-template <int PPT, bool VEC>
-__device__ __forceinline__ void load_points(const Pts &p, int64_t base, float (&x)[PPT],
-                                            float (&y)[PPT], float (&z)[PPT],
-                                            uint32_t (&c)[PPT], bool (&in)[PPT])
-{
-    const int64_t stride = 4 * (int64_t)blockDim.x;
-    const int64_t first = base + 4 * (int64_t)threadIdx.x;
-    const bool full = VEC && base + stride * (PPT / 4) <= p.n;
-    if (full) {
-#pragma unroll
-        for (int g = 0; g < PPT / 4; ++g) {
-            const int64_t i = first + g * stride;
-            const f32x4 vx = ldnt(reinterpret_cast<const f32x4 *>(p.x + i));
-            const f32x4 vy = ldnt(reinterpret_cast<const f32x4 *>(p.y + i));
-            const f32x4 vz = ldnt(reinterpret_cast<const f32x4 *>(p.z + i));
-            const u32x4 vc = ldnt(reinterpret_cast<const u32x4 *>(p.rgb + i));
-            x[4 * g + 0] = vx.x; x[4 * g + 1] = vx.y; x[4 * g + 2] = vx.z; x[4 * g + 3] = vx.w;
-            y[4 * g + 0] = vy.x; y[4 * g + 1] = vy.y; y[4 * g + 2] = vy.z; y[4 * g + 3] = vy.w;
-            z[4 * g + 0] = vz.x; z[4 * g + 1] = vz.y; z[4 * g + 2] = vz.z; z[4 * g + 3] = vz.w;
-            c[4 * g + 0] = vc.x; c[4 * g + 1] = vc.y; c[4 * g + 2] = vc.z; c[4 * g + 3] = vc.w;
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                in[4 * g + k] = true;
-        }
-    } else {
-#pragma unroll
-        for (int g = 0; g < PPT / 4; ++g) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int64_t i = first + g * stride + k;
-                const bool ok = i < p.n;
-                in[4 * g + k] = ok;
-                x[4 * g + k] = ok ? p.x[i] : 0.0f;
-                y[4 * g + k] = ok ? p.y[i] : 0.0f;
-                z[4 * g + k] = ok ? p.z[i] : 0.0f;
-                c[4 * g + k] = ok ? p.rgb[i] : 0u;
-            }
-        }
-    }
-}
-
-// Minimum over the 64 lanes of a wave with DPP moves (all lanes active):
-// quads, 8-lane halves, 16-lane rows, then row broadcasts into lane 63.
-__device__ __forceinline__ uint32_t wave_min(uint32_t v)
-{
-#define RZ_DPP_MIN(ctrl, rows)                                                             \
-    {                                                                                      \
-        const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, ctrl,     \
-                                                                 rows, 0xF, false);        \
-        v = v < t ? v : t;                                                                 \
-    }
-    RZ_DPP_MIN(0xB1, 0xF)    // quad_perm [1,0,3,2]
-    RZ_DPP_MIN(0x4E, 0xF)    // quad_perm [2,3,0,1]
-    RZ_DPP_MIN(0x141, 0xF)   // row_half_mirror
-    RZ_DPP_MIN(0x140, 0xF)   // row_mirror
-    RZ_DPP_MIN(0x142, 0xA)   // row_bcast:15 into rows 1 and 3
-    RZ_DPP_MIN(0x143, 0xC)   // row_bcast:31 into rows 2 and 3
-#undef RZ_DPP_MIN
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
-}
-
-// Screen rectangle of the live fragments of the workgroup.  Every thread
-// must call it (it synchronises the workgroup); every thread gets the same
-// answer.  Empty when x0 > x1.
-struct Box {
-    uint32_t x0, y0, x1, y1;
-};
-
-template <int PPT>
-__device__ __forceinline__ Box block_box(const uint32_t (&px)[PPT], const uint32_t (&py)[PPT],
-                                         const bool (&live)[PPT], uint32_t (*s_box)[4])
-{
-    uint32_t m[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        const uint32_t a = live[j] ? px[j] : 0xFFFFFFFFu;
-        const uint32_t b = live[j] ? py[j] : 0xFFFFFFFFu;
-        const uint32_t c = live[j] ? ~px[j] : 0xFFFFFFFFu;
-        const uint32_t d = live[j] ? ~py[j] : 0xFFFFFFFFu;
-        m[0] = a < m[0] ? a : m[0];
-        m[1] = b < m[1] ? b : m[1];
-        m[2] = c < m[2] ? c : m[2];
-        m[3] = d < m[3] ? d : m[3];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        m[k] = wave_min(m[k]);
-    const uint32_t wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            s_box[wave][k] = m[k];
-    }
-    __syncthreads();
-    const uint32_t nw = blockDim.x >> 6;
-    for (uint32_t w = 0; w < nw; ++w) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-            m[k] = s_box[w][k] < m[k] ? s_box[w][k] : m[k];
-    }
-    return Box{m[0], m[1], ~m[2], ~m[3]};
-}
-
-constexpr int kMaxWaves = 512 / 64;
-constexpr uint32_t kTileMin = 4096;   // LDS tile of the depth pass: 32 KiB
-constexpr uint32_t kTileHq = 2048;    // LDS tile of the accumulate pass: 32 KiB
-
-// Depth pass (section 2.1): every surviving fragment takes part in a 64-bit
-// minimum per pixel.  None of the refinements below changes the result,
-// because min is order independent and the framebuffer only decreases:
-//  - consecutive fragments of a thread in one pixel are merged in registers;
-//  - BIN: when the workgroup's fragments fall in a small screen rectangle,
-//    they are merged with LDS atomics in a tile first, and the tile is
-//    flushed row by row (coalesced global atomics, one per touched pixel);
-//  - EARLY: the framebuffer is read first and the atomic skipped when it is
-//    already <= the key (a stale read can only be larger than the true
-//    value, so the skip is always safe).
-// Straight-line selects only: no array element is updated inside a
-// divergent branch (a form this compiler has been seen to mis-allocate).
-template <int PPT, bool VEC, bool EARLY, bool XCD, bool BIN>
+// Depth pass of section 2.1 for one view: one workgroup per chunk of
+// blockDim * PPT consecutive points.
+template <int PPT, bool VEC, bool EARLY, bool XCD, int BIN>
 __global__ void __launch_bounds__(512) k_raster_min(Pts p, Proj P, uint64_t *__restrict__ fb,
                                                     int64_t nchunks)
 {
-    __shared__ uint64_t s_tile[BIN ? kTileMin : 1];
+    __shared__ uint64_t s_tile[BIN == kBinBlock ? kTileMin : 1];
     __shared__ uint32_t s_box[kMaxWaves][4];
+    extern __shared__ uint64_t s_waves[];   // kBinWave: kWaveTileWords per wave
     const int64_t chunk = chunk_index<XCD>();
     if (chunk >= nchunks)
         return;
-    const int64_t base = chunk * (int64_t)blockDim.x * PPT;
     float x[PPT], y[PPT], z[PPT];
     uint32_t c[PPT];
     bool in[PPT];
-    load_points<PPT, VEC>(p, base, x, y, z, c, in);
-
-    uint32_t px[PPT], py[PPT], pix[PPT];
-    uint64_t key[PPT];
-    bool live[PPT];
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        uint64_t q = 0;
-        uint32_t a = 0, b = 0;
-        live[j] = in[j] && fragment(P, x[j], y[j], z[j], a, b, q);
-        px[j] = a;
-        py[j] = b;
-        pix[j] = b * (uint32_t)P.width + a;
-        key[j] = (q << 24) | ((uint64_t)c[j] & kRgbMask);
-    }
-#pragma unroll
-    for (int j = 1; j < PPT; ++j) {
-        const bool same = live[j] && live[j - 1] && pix[j] == pix[j - 1];
-        const uint64_t lo = key[j] < key[j - 1] ? key[j] : key[j - 1];
-        key[j] = same ? lo : key[j];
-        live[j - 1] = live[j - 1] && !same;
-    }
-
-    bool direct[PPT];
-    Box box{1, 1, 0, 0};
-    uint32_t bw = 0, bh = 0;
-    bool tiled = false;
-    if (BIN) {
-        box = block_box<PPT>(px, py, live, s_box);
-        if (box.x0 > box.x1)
-            return;   // no fragment in this workgroup (uniform)
-        bw = box.x1 - box.x0 + 1;
-        bh = box.y1 - box.y0 + 1;
-        tiled = (uint64_t)bw * bh <= kTileMin;
-    }
-    if (tiled) {
-        const uint32_t area = bw * bh;
-        for (uint32_t i = threadIdx.x; i < area; i += blockDim.x)
-            s_tile[i] = ~0ull;
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-            const uint32_t tx = px[j] - box.x0, ty = py[j] - box.y0;
-            const bool inside = live[j] && tx < bw && ty < bh;
-            direct[j] = live[j] && !inside;
-            if (inside)
-                __hip_atomic_fetch_min(&s_tile[ty * bw + tx], key[j], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < area; i += blockDim.x) {
-            const uint64_t v = s_tile[i];
-            if (v != ~0ull) {
-                const uint32_t r = i / bw;
-                const uint32_t col = i - r * bw;
-                uint64_t *dst = fb + (uint64_t)(box.y0 + r) * (uint32_t)P.width + box.x0 + col;
-                const uint64_t cur = __hip_atomic_load(dst, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-                if (v < cur)
-                    __hip_atomic_fetch_min(dst, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < PPT; ++j)
-            direct[j] = live[j];
-    }
-
-    // fragments not merged in a tile go straight to the framebuffer
-    if (EARLY) {
-        uint64_t cur[PPT];
-#pragma unroll
-        for (int j = 0; j < PPT; ++j)
-            cur[j] = __hip_atomic_load(fb + (direct[j] ? pix[j] : 0u), __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-        for (int j = 0; j < PPT; ++j)
-            if (direct[j] && key[j] < cur[j])
-                __hip_atomic_fetch_min(fb + pix[j], key[j], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-#pragma unroll
-        for (int j = 0; j < PPT; ++j)
-            if (direct[j])
-                __hip_atomic_fetch_min(fb + pix[j], key[j], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-    }
+    load_points<PPT, VEC>(p, chunk * (int64_t)blockDim.x * PPT, x, y, z, c, in);
+    if (BIN == kBinWave)
+        raster_chunk_wave<PPT>(P, fb, x, y, z, c, in,
+                               s_waves + (threadIdx.x >> 6) * kWaveTileWords);
+    else
+        raster_chunk<PPT, EARLY, BIN == kBinBlock>(P, fb, x, y, z, c, in, s_tile, s_box);
 }
 
-// Accumulation pass of high-quality splatting (section 2.2).  Reprojects
-// every point, compares its depth with the finished depth pass and, inside
-// the eps window, adds its colour and a count:
-//   acc[2p] += R + (G << 32),  acc[2p+1] += B + (1 << 32).
-// As in the depth pass, consecutive accepted fragments of a thread in one
-// pixel are summed in registers, and with BIN the workgroup's sums are
-// gathered in an LDS tile (64-bit LDS adds) and flushed once per pixel.
-// Integer sums are order independent, so every variant gives the same bits.
-template <int PPT, bool VEC, bool XCD, bool BIN>
+// Accumulation pass of section 2.2 for one view.
+template <int PPT, bool VEC, bool XCD, int BIN>
 __global__ void __launch_bounds__(512) k_hq_accum(Pts p, Proj P, uint32_t eps_num,
                                                   uint32_t eps_den,
                                                   const uint64_t *__restrict__ fb,
                                                   uint64_t *__restrict__ acc, int64_t nchunks)
 {
-    __shared__ uint64_t s_tile[BIN ? 2 * kTileHq : 2];
+    __shared__ uint64_t s_tile[BIN == kBinBlock ? 2 * kTileHq : 2];
     __shared__ uint32_t s_box[kMaxWaves][4];
+    extern __shared__ uint64_t s_waves[];
     const int64_t chunk = chunk_index<XCD>();
     if (chunk >= nchunks)
         return;
-    const int64_t base = chunk * (int64_t)blockDim.x * PPT;
     float x[PPT], y[PPT], z[PPT];
     uint32_t c[PPT];
     bool in[PPT];
-    load_points<PPT, VEC>(p, base, x, y, z, c, in);
-
-    uint32_t px[PPT], py[PPT], pix[PPT];
-    uint64_t q[PPT];
-    bool ok[PPT];
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        uint32_t a = 0, b = 0;
-        uint64_t qq = 0;
-        ok[j] = in[j] && fragment(P, x[j], y[j], z[j], a, b, qq);
-        px[j] = a;
-        py[j] = b;
-        pix[j] = b * (uint32_t)P.width + a;
-        q[j] = qq;
-    }
-    // eps window against the finished depth pass: all loads first
-    // (discarded fragments read pixel 0, always in bounds), then the tests
-    uint64_t fbv[PPT];
-#pragma unroll
-    for (int j = 0; j < PPT; ++j)
-        fbv[j] = fb[ok[j] ? pix[j] : 0u];
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        const uint64_t qmin = fbv[j] >> 24;
-        ok[j] = ok[j] &&
-                (uint64_t)eps_den * (q[j] - qmin) <= (uint64_t)eps_num * (qmin + P.z0);
-    }
-    uint64_t w0[PPT], w1[PPT];
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        w0[j] = (uint64_t)(c[j] & 0xFFu) | ((uint64_t)((c[j] >> 8) & 0xFFu) << 32);
-        w1[j] = (uint64_t)((c[j] >> 16) & 0xFFu) | (1ull << 32);
-    }
-#pragma unroll
-    for (int j = 1; j < PPT; ++j) {
-        const bool same = ok[j] && ok[j - 1] && pix[j] == pix[j - 1];
-        w0[j] += same ? w0[j - 1] : 0ull;
-        w1[j] += same ? w1[j - 1] : 0ull;
-        ok[j - 1] = ok[j - 1] && !same;
-    }
-
-    bool direct[PPT];
-    Box box{1, 1, 0, 0};
-    uint32_t bw = 0, bh = 0;
-    bool tiled = false;
-    if (BIN) {
-        box = block_box<PPT>(px, py, ok, s_box);
-        if (box.x0 > box.x1)
-            return;
-        bw = box.x1 - box.x0 + 1;
-        bh = box.y1 - box.y0 + 1;
-        tiled = (uint64_t)bw * bh <= kTileHq;
-    }
-    if (tiled) {
-        const uint32_t area = bw * bh;
-        for (uint32_t i = threadIdx.x; i < 2 * area; i += blockDim.x)
-            s_tile[i] = 0ull;
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-            const uint32_t tx = px[j] - box.x0, ty = py[j] - box.y0;
-            const bool inside = ok[j] && tx < bw && ty < bh;
-            direct[j] = ok[j] && !inside;
-            if (inside) {
-                uint64_t *t = &s_tile[2 * (ty * bw + tx)];
-                __hip_atomic_fetch_add(t, w0[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                __hip_atomic_fetch_add(t + 1, w1[j], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
-        }
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < area; i += blockDim.x) {
-            const uint64_t a1 = s_tile[2 * i + 1];
-            if (a1 != 0ull) {
-                const uint64_t a0 = s_tile[2 * i];
-                const uint32_t r = i / bw;
-                const uint32_t col = i - r * bw;
-                uint64_t *dst =
-                    acc + 2 * ((uint64_t)(box.y0 + r) * (uint32_t)P.width + box.x0 + col);
-                __hip_atomic_fetch_add(dst, a0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_add(dst + 1, a1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < PPT; ++j)
-            direct[j] = ok[j];
-    }
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        if (direct[j]) {
-            uint64_t *a = acc + 2 * (uint64_t)pix[j];
-            __hip_atomic_fetch_add(a, w0[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(a + 1, w1[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    load_points<PPT, VEC>(p, chunk * (int64_t)blockDim.x * PPT, x, y, z, c, in);
+    if (BIN == kBinWave)
+        accum_chunk_wave<PPT>(P, eps_num, eps_den, fb, acc, x, y, z, c, in,
+                              s_waves + (threadIdx.x >> 6) * kWaveTileWords);
+    else
+        accum_chunk<PPT, BIN == kBinBlock>(P, eps_num, eps_den, fb, acc, x, y, z, c, in, s_tile,
+                                           s_box);
 }
 
 // Resolve of section 2.1: colour bits to the image, framebuffer cleared.
@@ -461,21 +87,6 @@ __global__ void __launch_bounds__(256) k_resolve_min(uint64_t *__restrict__ fb, 
             fb[k] = clear;
         }
     }
-}
-
-__device__ __forceinline__ uint32_t hq_colour(uint64_t w0, uint64_t w1, uint32_t bg,
-                                              bool &overflow)
-{
-    const uint64_t cnt = w1 >> 32;
-    if (cnt == 0)
-        return bg;
-    overflow = cnt > kHqCountMax;
-    const double den = 2.0 * (double)cnt;
-    // numerators < 2^34: the double quotient floors exactly
-    const uint32_t r = (uint32_t)floor((2.0 * (double)(w0 & 0xFFFFFFFFull) + (double)cnt) / den);
-    const uint32_t g = (uint32_t)floor((2.0 * (double)(w0 >> 32) + (double)cnt) / den);
-    const uint32_t b = (uint32_t)floor((2.0 * (double)(w1 & 0xFFFFFFFFull) + (double)cnt) / den);
-    return (r & 0xFFu) | ((g & 0xFFu) << 8) | ((b & 0xFFu) << 16);
 }
 
 // Third pass of section 2.2: average colour (or background), then fb and
@@ -526,34 +137,42 @@ bool aligned16(const void *ptr) { return ((uintptr_t)ptr & 15u) == 0; }
 
 int64_t blocks_for(int64_t n, int64_t per) { return (n + per - 1) / per; }
 
-template <int PPT, bool VEC, bool EARLY, bool BIN>
+// Dynamic LDS of a launch: the per-wave tiles of kBinWave.
+size_t wave_lds(int bin, int block)
+{
+    return bin == kBinWave ? (size_t)(block / 64) * kWaveTileWords * sizeof(uint64_t) : 0;
+}
+
+template <int PPT, bool VEC, bool EARLY, int BIN>
 hipError_t raster_min_ppt(const Pts &p, const Proj &P, uint64_t *fb, const Tune &t,
                           hipStream_t s)
 {
     const int64_t nchunks = blocks_for(p.n, (int64_t)t.block * PPT);
+    const size_t lds = wave_lds(BIN, t.block);
     if (t.xcd_remap) {
         const int64_t grid = (nchunks + kXcds - 1) / kXcds * kXcds;
         hipLaunchKernelGGL((k_raster_min<PPT, VEC, EARLY, true, BIN>), dim3((uint32_t)grid),
-                           dim3(t.block), 0, s, p, P, fb, nchunks);
+                           dim3(t.block), lds, s, p, P, fb, nchunks);
     } else {
         hipLaunchKernelGGL((k_raster_min<PPT, VEC, EARLY, false, BIN>), dim3((uint32_t)nchunks),
-                           dim3(t.block), 0, s, p, P, fb, nchunks);
+                           dim3(t.block), lds, s, p, P, fb, nchunks);
     }
     return hipGetLastError();
 }
 
-template <int PPT, bool VEC, bool BIN>
+template <int PPT, bool VEC, int BIN>
 hipError_t hq_accum_ppt(const Pts &p, const Proj &P, uint32_t num, uint32_t den,
                         const uint64_t *fb, uint64_t *acc, const Tune &t, hipStream_t s)
 {
     const int64_t nchunks = blocks_for(p.n, (int64_t)t.block * PPT);
+    const size_t lds = wave_lds(BIN, t.block);
     if (t.xcd_remap) {
         const int64_t grid = (nchunks + kXcds - 1) / kXcds * kXcds;
         hipLaunchKernelGGL((k_hq_accum<PPT, VEC, true, BIN>), dim3((uint32_t)grid),
-                           dim3(t.block), 0, s, p, P, num, den, fb, acc, nchunks);
+                           dim3(t.block), lds, s, p, P, num, den, fb, acc, nchunks);
     } else {
         hipLaunchKernelGGL((k_hq_accum<PPT, VEC, false, BIN>), dim3((uint32_t)nchunks),
-                           dim3(t.block), 0, s, p, P, num, den, fb, acc, nchunks);
+                           dim3(t.block), lds, s, p, P, num, den, fb, acc, nchunks);
     }
     return hipGetLastError();
 }
@@ -563,31 +182,44 @@ bool planes_aligned(const Pts &p)
     return aligned16(p.x) && aligned16(p.y) && aligned16(p.z) && aligned16(p.rgb);
 }
 
+template <int PPT, bool VEC>
+hipError_t raster_min_vec(const Pts &p, const Proj &P, uint64_t *fb, const Tune &t,
+                          hipStream_t s)
+{
+    switch (t.bin) {
+    case kBinBlock: return raster_min_ppt<PPT, VEC, true, kBinBlock>(p, P, fb, t, s);
+    case kBinWave: return raster_min_ppt<PPT, VEC, true, kBinWave>(p, P, fb, t, s);
+    default:
+        return t.early_out ? raster_min_ppt<PPT, VEC, true, kBinNone>(p, P, fb, t, s)
+                           : raster_min_ppt<PPT, VEC, false, kBinNone>(p, P, fb, t, s);
+    }
+}
+
 template <int PPT>
 hipError_t raster_min_dispatch(const Pts &p, const Proj &P, uint64_t *fb, const Tune &t,
                                hipStream_t s)
 {
-    const bool vec = planes_aligned(p);
-    if (!vec)   // unaligned planes: scalar loads, one shape
-        return t.bin ? raster_min_ppt<PPT, false, true, true>(p, P, fb, t, s)
-                     : raster_min_ppt<PPT, false, true, false>(p, P, fb, t, s);
-    if (t.bin)
-        return t.early_out ? raster_min_ppt<PPT, true, true, true>(p, P, fb, t, s)
-                           : raster_min_ppt<PPT, true, false, true>(p, P, fb, t, s);
-    return t.early_out ? raster_min_ppt<PPT, true, true, false>(p, P, fb, t, s)
-                       : raster_min_ppt<PPT, true, false, false>(p, P, fb, t, s);
+    return planes_aligned(p) ? raster_min_vec<PPT, true>(p, P, fb, t, s)
+                             : raster_min_vec<PPT, false>(p, P, fb, t, s);
+}
+
+template <int PPT, bool VEC>
+hipError_t hq_accum_vec(const Pts &p, const Proj &P, uint32_t num, uint32_t den,
+                        const uint64_t *fb, uint64_t *acc, const Tune &t, hipStream_t s)
+{
+    switch (t.bin) {
+    case kBinBlock: return hq_accum_ppt<PPT, VEC, kBinBlock>(p, P, num, den, fb, acc, t, s);
+    case kBinWave: return hq_accum_ppt<PPT, VEC, kBinWave>(p, P, num, den, fb, acc, t, s);
+    default: return hq_accum_ppt<PPT, VEC, kBinNone>(p, P, num, den, fb, acc, t, s);
+    }
 }
 
 template <int PPT>
 hipError_t hq_accum_dispatch(const Pts &p, const Proj &P, uint32_t num, uint32_t den,
                              const uint64_t *fb, uint64_t *acc, const Tune &t, hipStream_t s)
 {
-    const bool vec = planes_aligned(p);
-    if (vec)
-        return t.bin ? hq_accum_ppt<PPT, true, true>(p, P, num, den, fb, acc, t, s)
-                     : hq_accum_ppt<PPT, true, false>(p, P, num, den, fb, acc, t, s);
-    return t.bin ? hq_accum_ppt<PPT, false, true>(p, P, num, den, fb, acc, t, s)
-                 : hq_accum_ppt<PPT, false, false>(p, P, num, den, fb, acc, t, s);
+    return planes_aligned(p) ? hq_accum_vec<PPT, true>(p, P, num, den, fb, acc, t, s)
+                             : hq_accum_vec<PPT, false>(p, P, num, den, fb, acc, t, s);
 }
 
 }  // namespace

@@ -64,6 +64,41 @@ class rz_launch(ctypes.Structure):
                 ("xcd_remap", c_int32), ("bin", c_int32)]
 
 
+class rz_batch_view(ctypes.Structure):
+    _fields_ = [("view", rz_view), ("depth", rz_depth_map), ("mode", c_int32),
+                ("hq", rz_hq_params), ("background", c_uint32), ("fb", c_void_p),
+                ("acc", c_void_p), ("img", c_void_p)]
+
+
+class rz_batch_opts(ctypes.Structure):
+    _fields_ = [("views_per_group", c_int32), ("launch", rz_launch), ("use_graph", c_int32),
+                ("status", c_void_p)]
+
+
+class rz_server_opts(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("streams", c_int32), ("max_inflight", c_int32),
+                ("dry_run", c_int32), ("dry_run_us", c_int32)]
+
+
+class rz_request(ctypes.Structure):
+    _fields_ = [("cloud", c_int32), ("mode", c_int32), ("view", rz_view), ("depth", rz_depth_map),
+                ("hq", rz_hq_params), ("background", c_uint32), ("flags", c_uint32),
+                ("img", c_void_p)]
+
+
+class rz_request_status(ctypes.Structure):
+    _fields_ = [("state", c_int32), ("error", c_int32), ("hq_status", c_uint32),
+                ("stream", c_uint32), ("t_submit_us", c_double), ("t_admit_us", c_double),
+                ("t_done_us", c_double)]
+
+
+class rz_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
+                ("peak_inflight", c_int32), ("queued", c_int32), ("inflight", c_int32),
+                ("pad", c_int32)]
+
+
 P = ctypes.POINTER
 SIGNATURES = {
     "rasterize_atomicmin": ([P(rz_points), P(rz_view), P(rz_depth_map), c_uint32, c_void_p,
@@ -82,7 +117,28 @@ SIGNATURES = {
     "rz_error_string": ([ctypes.c_int], ctypes.c_char_p),
     "rz_last_hip_error": ([], ctypes.c_int),
     "rz_version": ([], ctypes.c_int),
+    "rz_batch_plan": ([P(rz_points), P(rz_batch_view), c_int32, P(rz_batch_opts), P(c_void_p)],
+                      ctypes.c_int),
+    "rz_batch_capture": ([c_void_p], ctypes.c_int),
+    "rz_batch_run": ([c_void_p, c_void_p], ctypes.c_int),
+    "rz_batch_autotune": ([c_void_p, c_void_p, c_int32, P(rz_batch_opts), P(ctypes.c_float)],
+                          ctypes.c_int),
+    "rz_batch_get_opts": ([c_void_p, P(rz_batch_opts)], ctypes.c_int),
+    "rz_batch_destroy": ([c_void_p], ctypes.c_int),
+    "rz_server_create": ([P(rz_server_opts), P(c_void_p)], ctypes.c_int),
+    "rz_server_add_cloud": ([c_void_p, P(rz_points), P(c_int32)], ctypes.c_int),
+    "rz_server_submit": ([c_void_p, P(rz_request), P(ctypes.c_uint64)], ctypes.c_int),
+    "rz_server_poll": ([c_void_p, ctypes.c_uint64, P(rz_request_status)], ctypes.c_int),
+    "rz_server_drain": ([c_void_p, c_double], ctypes.c_int),
+    "rz_server_get_stats": ([c_void_p, P(rz_server_stats)], ctypes.c_int),
+    "rz_server_destroy": ([c_void_p], ctypes.c_int),
 }
+
+RZ_REQ_QUEUED, RZ_REQ_RUNNING, RZ_REQ_DONE, RZ_REQ_FAILED = 0, 1, 2, 3
+RZ_REQ_INJECT_FAILURE = 1
+
+RZ_MODE_ATOMICMIN = 0
+RZ_MODE_HQ = 1
 
 _lock = threading.Lock()
 _lib = None
@@ -318,3 +374,160 @@ def unpack_acc(acc) -> np.ndarray:
     lo = np.uint64(0xFFFFFFFF)
     return np.stack([a[:, 0] & lo, a[:, 0] >> np.uint64(32), a[:, 1] & lo,
                      a[:, 1] >> np.uint64(32)], axis=1)
+
+
+# --------------------------------------------------------------------------
+# batched multi-view rendering
+# --------------------------------------------------------------------------
+
+def _opts_dict(o: rz_batch_opts) -> dict:
+    return {"views_per_group": o.views_per_group, "use_graph": o.use_graph,
+            **{f: getattr(o.launch, f) for f, _ in rz_launch._fields_}}
+
+
+class Batch:
+    """Many views of one resident cloud (rz_batch_* in include/rz.h).
+
+    views: objects with vp, near, far, width, height; modes: RZ_MODE_* per
+    view.  Allocates (torch) and clears each view's fb / acc / img once; the
+    library owns only its view table and graph.  Every run renders all views
+    and leaves fb/acc cleared again."""
+
+    def __init__(self, points: Points, views, modes, depth=None, eps=(1, 100), backgrounds=None,
+                 views_per_group=0, launch=None, use_graph=False, status=None):
+        torch = _torch()
+        _require_gpu(points.x, status)
+        self.points = points
+        self.views = list(views)
+        self.modes = [int(m) for m in modes]
+        n = len(self.views)
+        if len(self.modes) != n:
+            raise RzError(RZ_EINVAL, "one mode per view")
+        bgs = [0] * n if backgrounds is None else [int(b) for b in backgrounds]
+        self.backgrounds = bgs
+        self.fbs, self.accs, self.imgs = [], [], []
+        arr = (rz_batch_view * n)()
+        ds = depth if isinstance(depth, rz_depth_map) else depth_struct(*(depth or (DEPTH_LINEAR, 0.0)))
+        for i, (v, m) in enumerate(zip(self.views, self.modes)):
+            fb, acc = new_framebuffer(v, bgs[i], hq=(m == RZ_MODE_HQ))
+            img = torch.empty(_npix(v), dtype=torch.int32, device="cuda")
+            self.fbs.append(fb)
+            self.accs.append(acc)
+            self.imgs.append(img)
+            arr[i] = rz_batch_view(view_struct(v), ds, m, rz_hq_params(int(eps[0]), int(eps[1])),
+                                   bgs[i] & 0xFFFFFFFF, fb.data_ptr(),
+                                   acc.data_ptr() if acc is not None else None, img.data_ptr())
+        self.status = status
+        opts = rz_batch_opts()
+        opts.views_per_group = int(views_per_group)
+        if launch is not None:
+            opts.launch = rz_launch(*launch) if not isinstance(launch, dict) else rz_launch(
+                **{k: launch[k] for k, _ in rz_launch._fields_})
+        opts.use_graph = 1 if use_graph else 0
+        opts.status = status.data_ptr() if status is not None else None
+        self._ps = points.struct()
+        self._arr = arr
+        h = c_void_p()
+        torch.cuda.synchronize()
+        _check(load().rz_batch_plan(ctypes.byref(self._ps), arr, n, ctypes.byref(opts),
+                                    ctypes.byref(h)), "rz_batch_plan")
+        self._h = h
+
+    def run(self, stream=None):
+        _check(load().rz_batch_run(self._h, _stream(stream)), "rz_batch_run")
+
+    def capture(self):
+        _check(load().rz_batch_capture(self._h), "rz_batch_capture")
+
+    def autotune(self, reps=3, stream=None):
+        o = rz_batch_opts()
+        ms = ctypes.c_float()
+        _check(load().rz_batch_autotune(self._h, _stream(stream), int(reps), ctypes.byref(o),
+                                        ctypes.byref(ms)), "rz_batch_autotune")
+        return _opts_dict(o), float(ms.value)
+
+    def opts(self) -> dict:
+        o = rz_batch_opts()
+        _check(load().rz_batch_get_opts(self._h, ctypes.byref(o)), "rz_batch_get_opts")
+        return _opts_dict(o)
+
+    def images(self):
+        return [to_u32(i) for i in self.imgs]
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(load().rz_batch_destroy(self._h), "rz_batch_destroy")
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------------------
+# serving
+# --------------------------------------------------------------------------
+
+class Server:
+    """Continuous-batching render server (rz_server_* in include/rz.h).
+
+    Clouds stay resident (the caller keeps the Points alive); each request
+    renders one view into a caller-owned device image.  dry_run=True runs
+    the scheduler without any device work (requests take dry_run_us)."""
+
+    def __init__(self, budget_bytes, streams=4, max_inflight=0, dry_run=False, dry_run_us=0):
+        if not dry_run:
+            _require_gpu()
+        o = rz_server_opts(int(budget_bytes), int(streams), int(max_inflight), 1 if dry_run else 0,
+                           int(dry_run_us))
+        h = c_void_p()
+        _check(load().rz_server_create(ctypes.byref(o), ctypes.byref(h)), "rz_server_create")
+        self._h = h
+        self._clouds = []
+        self.dry_run = dry_run
+
+    def add_cloud(self, points) -> int:
+        ps = points.struct() if isinstance(points, Points) else points
+        cid = c_int32()
+        _check(load().rz_server_add_cloud(self._h, ctypes.byref(ps), ctypes.byref(cid)),
+               "rz_server_add_cloud")
+        self._clouds.append(points)
+        return cid.value
+
+    def submit(self, cloud, view, mode, img=None, depth=None, eps=(1, 100), background=0,
+               inject_failure=False) -> int:
+        ds = depth if isinstance(depth, rz_depth_map) else depth_struct(*(depth or (DEPTH_LINEAR, 0.0)))
+        r = rz_request(int(cloud), int(mode), view_struct(view), ds,
+                       rz_hq_params(int(eps[0]), int(eps[1])), int(background) & 0xFFFFFFFF,
+                       RZ_REQ_INJECT_FAILURE if inject_failure else 0,
+                       img.data_ptr() if img is not None else None)
+        t = ctypes.c_uint64()
+        _check(load().rz_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)),
+               "rz_server_submit")
+        return t.value
+
+    def poll(self, ticket) -> dict:
+        st = rz_request_status()
+        _check(load().rz_server_poll(self._h, int(ticket), ctypes.byref(st)), "rz_server_poll")
+        return {f: getattr(st, f) for f, _ in rz_request_status._fields_}
+
+    def drain(self, timeout_s=60.0):
+        _check(load().rz_server_drain(self._h, float(timeout_s)), "rz_server_drain")
+
+    def stats(self) -> dict:
+        st = rz_server_stats()
+        _check(load().rz_server_get_stats(self._h, ctypes.byref(st)), "rz_server_get_stats")
+        return {f: getattr(st, f) for f, _ in rz_server_stats._fields_ if f != "pad"}
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _check(load().rz_server_destroy(self._h), "rz_server_destroy")
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -133,3 +133,37 @@ def test_binding_refuses_without_gpu(rz):
         pytest.skip("a GPU is present")
     with pytest.raises(rz.RzError):
         rz.new_framebuffer(_View())
+
+
+def test_batch_plan_validation(rz):
+    """rz_batch_plan rejects bad batches before it allocates anything."""
+    lib = rz.load()
+    ps = rz.rz_points(1, 1, 1, 1, 10)
+
+    def view(mode=0, fb=16, acc=32, img=48, w=64):
+        return rz.rz_batch_view(rz.view_struct(_View(w=w)), rz.depth_struct(), mode,
+                                rz.rz_hq_params(1, 100), 0, fb, acc, img)
+
+    def plan(views, k=0, block=0):
+        arr = (rz.rz_batch_view * max(1, len(views)))(*views)
+        opts = rz.rz_batch_opts()
+        opts.views_per_group = k
+        opts.launch.block = block
+        if block:
+            opts.launch.ppt = 8
+        h = ctypes.c_void_p()
+        return lib.rz_batch_plan(ctypes.byref(ps), arr, len(views), ctypes.byref(opts),
+                                 ctypes.byref(h))
+
+    assert plan([]) == rz.RZ_EINVAL
+    assert plan([view(mode=2)]) == rz.RZ_EINVAL
+    assert plan([view(fb=0)]) == rz.RZ_EINVAL
+    assert plan([view(mode=1, acc=0)]) == rz.RZ_EINVAL
+    assert plan([view(), view(fb=16, img=80)]) == rz.RZ_EINVAL        # shared fb
+    assert plan([view(), view(fb=96, img=48)]) == rz.RZ_EINVAL        # shared img
+    assert plan([view(w=0)]) == rz.RZ_EINVAL
+    assert plan([view()], k=9) == rz.RZ_EINVAL
+    assert plan([view()], block=96) == rz.RZ_EINVAL
+    for fn in ("rz_batch_run", "rz_batch_capture", "rz_batch_destroy"):
+        args = (None, None) if fn == "rz_batch_run" else (None,)
+        assert getattr(lib, fn)(*args) == rz.RZ_EINVAL

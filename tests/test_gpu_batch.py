@@ -1,0 +1,154 @@
+"""Batched multi-view rendering: every view of a batch is bit-identical to the
+oracle and to its one-view call, with and without a captured graph, for any
+group size and launch shape, before and after autotuning."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1908_02681_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rz():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1908_02681_amd import rz as binding
+    binding.load()
+    yield binding
+    binding.set_launch()
+
+
+SIZES = [(64, 48), (160, 120), (97, 61), (200, 150), (33, 257)]
+
+
+@pytest.fixture(scope="module")
+def scene():
+    cloud = gen.terrain(600_000, 21, extent=100.0, amplitude=10.0, wavelength=40.0)
+    views = gen.orbit_views(11, 5, SIZES, extent=100.0, rmin=60.0, rmax=120.0, near=0.5, far=400.0)
+    rng = np.random.default_rng(3)
+    modes = rng.integers(0, 2, len(views)).tolist()
+    modes[0], modes[1] = 0, 1
+    bgs = rng.integers(0, 1 << 24, len(views)).tolist()
+    return cloud, views, modes, bgs
+
+
+@pytest.fixture(scope="module")
+def expected(scene, oracle):
+    cloud, views, modes, bgs = scene
+    out = []
+    for v, m, bg in zip(views, modes, bgs):
+        if m == 0:
+            _, img = oracle.render_atomicmin(cloud.x, cloud.y, cloud.z, cloud.rgb, v.vp, v.near,
+                                             v.far, v.width, v.height, bg=bg)
+        else:
+            _, _, img = oracle.render_hq(cloud.x, cloud.y, cloud.z, cloud.rgb, v.vp, v.near,
+                                         v.far, v.width, v.height, bg=bg)
+        out.append(img)
+    return out
+
+
+def check_images(rz, batch, expected, label):
+    import torch
+    torch.cuda.synchronize()
+    for i, (got, want) in enumerate(zip(batch.images(), expected)):
+        assert np.array_equal(got, want), f"{label}: view {i} differs"
+    for fb, acc, bg in zip(batch.fbs, batch.accs, batch.backgrounds):
+        assert (rz.to_u64(fb) == np.uint64(0xFFFFFFFFFF000000 | (bg & 0xFFFFFF))).all()
+        if acc is not None:
+            assert (rz.to_u64(acc) == 0).all()
+
+
+def test_batch_matches_oracle(rz, scene, expected):
+    cloud, views, modes, bgs = scene
+    pts = rz.Points.from_cloud(cloud)
+    b = rz.Batch(pts, views, modes, backgrounds=bgs)
+    b.run()
+    check_images(rz, b, expected, "plain batch")
+    b.run()   # the buffers are cleared again: a second run gives the same bits
+    check_images(rz, b, expected, "second run")
+    b.close()
+
+
+def test_one_view_calls_match(rz, scene, expected):
+    import torch
+    cloud, views, modes, bgs = scene
+    pts = rz.Points.from_cloud(cloud)
+    for v, m, bg, want in zip(views, modes, bgs, expected):
+        if m == 0:
+            _, img = rz.rasterize_atomicmin(pts, v, background=bg)
+        else:
+            _, _, img, _ = rz.rasterize_hq_splat(pts, v, background=bg)
+        torch.cuda.synchronize()
+        assert np.array_equal(rz.to_u32(img), want)
+
+
+@pytest.mark.parametrize("k", [1, 3, 8])
+@pytest.mark.parametrize("launch", [(256, 4, 1, 1, 1), (512, 8, 1, 0, 1), (128, 16, 1, 1, 0),
+                                    (256, 8, 1, 1, 2), (512, 16, 1, 0, 2)])
+def test_group_sizes_and_shapes(rz, scene, expected, k, launch):
+    cloud, views, modes, bgs = scene
+    say(f"[batch] K={k} launch={launch}")
+    pts = rz.Points.from_cloud(cloud)
+    b = rz.Batch(pts, views, modes, backgrounds=bgs, views_per_group=k, launch=launch)
+    b.run()
+    check_images(rz, b, expected, f"K={k} {launch}")
+    b.close()
+
+
+def test_graph_replays_match_eager(rz, scene, expected):
+    """The captured graph holds kernels only (no memset nodes); every replay,
+    with unrelated eager GPU work and synchronisations in between, gives the
+    eager result."""
+    import torch
+    cloud, views, modes, bgs = scene
+    pts = rz.Points.from_cloud(cloud)
+    b = rz.Batch(pts, views, modes, backgrounds=bgs, use_graph=True)
+    scratch = torch.zeros(1 << 20, device="cuda")
+    for r in range(4):
+        say(f"[graph] replay {r}")
+        b.run()
+        check_images(rz, b, expected, f"replay {r}")
+        scratch.add_(1.0)
+        torch.cuda.synchronize()
+        assert float(scratch[0].item()) == r + 1
+    b.close()
+
+
+def test_autotune_keeps_bits(rz, scene, expected):
+    cloud, views, modes, bgs = scene
+    pts = rz.Points.from_cloud(cloud)
+    b = rz.Batch(pts, views, modes, backgrounds=bgs, use_graph=True)
+    opts, ms = b.autotune(reps=2)
+    say(f"[autotune] chosen {opts} {ms:.3f} ms")
+    assert 1 <= opts["views_per_group"] <= 8 and opts["use_graph"] == 1 and ms > 0
+    assert b.opts() == opts
+    b.run()
+    check_images(rz, b, expected, "after autotune")
+    b.close()
+
+
+def test_batch_status_flags_overflow(rz):
+    """The fused resolve reports splat counts beyond the exact range like the
+    one-view call does."""
+    import torch
+    n = 16_843_010
+    view = gen.View(np.diag([1.0, 1.0, 0.0, 0.0]) + np.array(
+        [[0, 0, 0, 0], [0, 0, 0, 0], [0, 0, 0, 0], [0, 0, -1.0, 0]]), 1.0, 100.0, 2, 2)
+    pts = rz.Points(torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"),
+                    torch.full((n,), -10.0, device="cuda"),
+                    torch.full((n,), 0x00FF00, dtype=torch.int32, device="cuda"))
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    b = rz.Batch(pts, [view, view], [1, 0], status=status)
+    b.run()
+    torch.cuda.synchronize()
+    assert int(status.item()) & rz.RZ_STATUS_HQ_OVERFLOW
+    assert b.images()[1][3] == 0x00FF00
+    b.close()

@@ -126,7 +126,7 @@ def test_ragged_sizes(rz, oracle, n):
 
 
 LAUNCHES = [(b, p, e, x, n) for b in (64, 256, 512) for p in (4, 8, 16) for e in (0, 1)
-            for x in (0, 1) for n in (0, 1)]
+            for x in (0, 1) for n in (0, 1, 2)]
 
 
 def test_every_launch_shape_is_bit_identical(rz, oracle):
@@ -149,7 +149,7 @@ def test_every_launch_shape_is_bit_identical(rz, oracle):
         rz.set_launch()
 
 
-@pytest.mark.parametrize("bin_", [0, 1])
+@pytest.mark.parametrize("bin_", [0, 1, 2])
 def test_tile_fallback_and_sparse_screens(rz, oracle, bin_):
     """Workgroups whose fragments span more than one LDS tile (random points
     over a wide screen) take the direct path; both give the oracle's bits."""

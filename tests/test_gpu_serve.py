@@ -1,0 +1,119 @@
+"""Render server on the GPU: every request's image is bit-identical alone and
+in the mix (mixed clouds, resolutions, methods, overlapping streams, a tight
+memory budget), and an injected failure leaves the other requests intact."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1908_02681_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rz():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1908_02681_amd import rz as binding
+    binding.load()
+    return binding
+
+
+SIZES = [(64, 48), (256, 256), (320, 200), (97, 61)]
+
+
+@pytest.fixture(scope="module")
+def world(rz):
+    clouds = [gen.config1(n=200_000)[0],
+              gen.terrain(1_000_000, 31, extent=100.0, amplitude=10.0, wavelength=40.0),
+              gen.terrain(3_000_003, 32, extent=100.0, amplitude=10.0, wavelength=40.0)]
+    pts = [rz.Points.from_cloud(c) for c in clouds]
+    rng = np.random.default_rng(9)
+    reqs = []
+    for i in range(30):
+        c = int(rng.integers(0, 3))
+        if c == 0:
+            v = gen.make_view((0.5, 0.5, 2.5), (0.5, 0.5, 0.5), (0, 1, 0), 60.0,
+                              *SIZES[i % len(SIZES)], 0.01, 10.0)
+        else:
+            v = gen.orbit_views(1, 100 + i, [SIZES[i % len(SIZES)]], extent=100.0, rmin=60.0,
+                                rmax=150.0, near=0.5, far=400.0)[0]
+        reqs.append((c, v, int(rng.integers(0, 2)), int(rng.integers(0, 1 << 24))))
+    return clouds, pts, reqs
+
+
+@pytest.fixture(scope="module")
+def alone(rz, world):
+    """Each request rendered by itself with the one-view calls."""
+    import torch
+    clouds, pts, reqs = world
+    out = []
+    for c, v, m, bg in reqs:
+        if m == 0:
+            _, img = rz.rasterize_atomicmin(pts[c], v, background=bg)
+        else:
+            _, _, img, _ = rz.rasterize_hq_splat(pts[c], v, background=bg)
+        torch.cuda.synchronize()
+        out.append(rz.to_u32(img))
+    return out
+
+
+def serve(rz, pts, reqs, budget, streams, fail=()):
+    import torch
+    s = rz.Server(budget, streams=streams)
+    ids = [s.add_cloud(p) for p in pts]
+    imgs, tickets = [], []
+    for i, (c, v, m, bg) in enumerate(reqs):
+        img = torch.full((v.width * v.height,), -1, dtype=torch.int32, device="cuda")
+        imgs.append(img)
+        tickets.append(s.submit(ids[c], v, m, img=img, background=bg, inject_failure=i in fail))
+    s.drain(120)
+    st = [s.poll(t) for t in tickets]
+    stats = s.stats()
+    s.close()
+    return [rz.to_u32(i) for i in imgs], st, stats
+
+
+def test_small_requests_match_oracle(rz, oracle, world, alone):
+    clouds, pts, reqs = world
+    for (c, v, m, bg), img in list(zip(reqs, alone))[:6]:
+        cl = clouds[c]
+        if m == 0:
+            _, want = oracle.render_atomicmin(cl.x, cl.y, cl.z, cl.rgb, v.vp, v.near, v.far,
+                                              v.width, v.height, bg=bg)
+        else:
+            _, _, want = oracle.render_hq(cl.x, cl.y, cl.z, cl.rgb, v.vp, v.near, v.far, v.width,
+                                          v.height, bg=bg)
+        assert np.array_equal(img, want)
+
+
+@pytest.mark.parametrize("budget_mb,streams", [(512, 4), (2, 2), (64, 16)])
+def test_mix_equals_alone(rz, world, alone, budget_mb, streams):
+    clouds, pts, reqs = world
+    say(f"[serve] budget {budget_mb} MiB, {streams} streams")
+    imgs, st, stats = serve(rz, pts, reqs, budget_mb << 20, streams)
+    assert all(x["state"] == rz.RZ_REQ_DONE and x["error"] == 0 for x in st)
+    for i, (got, want) in enumerate(zip(imgs, alone)):
+        assert np.array_equal(got, want), f"request {i} differs in the mix"
+    assert stats["completed"] == len(reqs) and stats["peak_bytes"] <= budget_mb << 20
+    if budget_mb >= 64:
+        assert stats["peak_inflight"] > 1      # the requests did overlap
+
+
+def test_failed_request_is_isolated(rz, world, alone):
+    clouds, pts, reqs = world
+    fail = {3, 11, 12}
+    imgs, st, stats = serve(rz, pts, reqs, 256 << 20, 4, fail=fail)
+    for i, (x, got, want) in enumerate(zip(st, imgs, alone)):
+        if i in fail:
+            assert x["state"] == rz.RZ_REQ_FAILED and x["error"] == rz.RZ_EHIP
+            assert (got == 0xFFFFFFFF).all()          # never touched
+        else:
+            assert x["state"] == rz.RZ_REQ_DONE and np.array_equal(got, want)
+    assert stats["failed"] == len(fail)

@@ -1,0 +1,154 @@
+"""Render-server scheduling on the host (dry-run backend: no device work):
+admission by memory budget and in-flight slots, arrival order, continuous
+admission as memory frees up, error isolation of failed requests."""
+import time
+
+import numpy as np
+import pytest
+
+
+@pytest.fixture(scope="module")
+def rz():
+    import os
+    from paper_1908_02681_amd import build, rz as binding
+    if not os.path.exists(binding.LIB_PATH):
+        build.build()
+    binding.load()
+    return binding
+
+
+class _View:
+    def __init__(self, w, h):
+        self.vp = np.eye(4)
+        self.vp[3] = [0, 0, 0, 1]
+        self.near, self.far, self.width, self.height = 0.5, 2.0, w, h
+
+
+def _server(rz, budget, us, streams=2, inflight=0):
+    s = rz.Server(budget, streams=streams, max_inflight=inflight, dry_run=True, dry_run_us=us)
+    cid = s.add_cloud(rz.rz_points(1, 1, 1, 1, 1000))
+    return s, cid
+
+
+def _wait(s, tickets, timeout=20.0):
+    s.drain(timeout)
+    return [s.poll(t) for t in tickets]
+
+
+def _fb_bytes(w, h, hq):
+    a = lambda v: (v + 255) // 256 * 256
+    return a(8 * w * h) + (a(16 * w * h) if hq else 0) + 256
+
+
+def test_budget_admits_one_at_a_time(rz):
+    need = _fb_bytes(640, 480, False)
+    s, cid = _server(rz, need + need // 2, 3000)
+    ts = [s.submit(cid, _View(640, 480), 0) for _ in range(5)]
+    st = _wait(s, ts)
+    assert all(x["state"] == rz.RZ_REQ_DONE and x["error"] == 0 for x in st)
+    stats = s.stats()
+    assert stats["peak_inflight"] == 1 and stats["completed"] == 5
+    assert stats["peak_bytes"] == need
+    # arrival order, and each admitted only once the previous one finished
+    for a, b in zip(st, st[1:]):
+        assert b["t_admit_us"] >= a["t_done_us"] - 1.0
+        assert b["t_admit_us"] >= a["t_admit_us"]
+    for x in st:
+        assert x["t_done_us"] - x["t_admit_us"] >= 3000 * 0.95
+    s.close()
+
+
+def test_slots_bound_concurrency(rz):
+    s, cid = _server(rz, 512 << 20, 5000, streams=2, inflight=3)
+    ts = [s.submit(cid, _View(256, 256), i % 2) for i in range(9)]
+    st = _wait(s, ts)
+    assert all(x["state"] == rz.RZ_REQ_DONE for x in st)
+    assert s.stats()["peak_inflight"] == 3
+    assert {x["stream"] for x in st} == {0, 1}
+    s.close()
+
+
+def test_continuous_admission_while_others_run(rz):
+    """A request that arrives while others run starts as soon as memory
+    frees up, not when the whole earlier batch has finished."""
+    big = _fb_bytes(1920, 1080, True)
+    small = _fb_bytes(256, 256, False)
+    s, cid = _server(rz, big + small, 20000, streams=4)
+    t_big = s.submit(cid, _View(1920, 1080), 1)
+    t_small = [s.submit(cid, _View(256, 256), 0) for _ in range(3)]
+    st_small = _wait(s, t_small)
+    st_big = s.poll(t_big)
+    assert st_big["state"] == rz.RZ_REQ_DONE
+    # the first small request ran beside the big one; the remaining memory
+    # holds one small framebuffer only, so never more than two at once and
+    # never more memory than the budget
+    assert st_small[0]["t_admit_us"] < st_big["t_admit_us"] + 5000
+    assert st_small[0]["t_admit_us"] < st_big["t_done_us"]
+    assert st_small[1]["t_admit_us"] >= min(st_small[0]["t_done_us"], st_big["t_done_us"]) - 1.0
+    stats = s.stats()
+    assert stats["peak_inflight"] >= 2 and stats["peak_bytes"] == big + small
+    s.close()
+
+
+def test_request_larger_than_budget_is_refused(rz):
+    s, cid = _server(rz, 4 << 20, 10)
+    with pytest.raises(rz.RzError) as e:
+        s.submit(cid, _View(2560, 1440), 1)
+    assert e.value.code == rz.RZ_EBUDGET
+    with pytest.raises(rz.RzError) as e:
+        s.submit(cid + 5, _View(64, 64), 0)
+    assert e.value.code == rz.RZ_EINVAL
+    with pytest.raises(rz.RzError) as e:
+        s.submit(cid, _View(64, 64), 3)
+    assert e.value.code == rz.RZ_EINVAL
+    s.close()
+
+
+def test_injected_failure_fails_only_that_request(rz):
+    s, cid = _server(rz, 64 << 20, 500)
+    inject = [False, True, False, True, False, False]
+    ts = [s.submit(cid, _View(320, 240), i % 2, inject_failure=f) for i, f in enumerate(inject)]
+    st = _wait(s, ts)
+    for x, f in zip(st, inject):
+        if f:
+            assert x["state"] == rz.RZ_REQ_FAILED and x["error"] == rz.RZ_EHIP
+        else:
+            assert x["state"] == rz.RZ_REQ_DONE and x["error"] == 0
+    stats = s.stats()
+    assert stats["failed"] == 2 and stats["completed"] == 4
+    assert stats["inflight"] == 0 and stats["queued"] == 0
+    # the memory of failed requests came back: a request needing all of it fits
+    t = s.submit(cid, _View(1600, 1600), 1)   # 91% of the budget
+    assert _wait(s, [t])[0]["state"] == rz.RZ_REQ_DONE
+    s.close()
+
+
+def test_poll_forgets_finished_tickets(rz):
+    s, cid = _server(rz, 64 << 20, 100)
+    t = s.submit(cid, _View(64, 64), 0)
+    s.drain(10)
+    assert s.poll(t)["state"] == rz.RZ_REQ_DONE
+    with pytest.raises(rz.RzError):
+        s.poll(t)
+    s.close()
+
+
+def test_many_requests_from_threads(rz):
+    import threading
+    s, cid = _server(rz, 64 << 20, 200, streams=4)
+    out, lock = [], threading.Lock()
+
+    def worker(k):
+        for i in range(50):
+            t = s.submit(cid, _View(128 + k, 96), (i + k) % 2)
+            with lock:
+                out.append(t)
+
+    th = [threading.Thread(target=worker, args=(k,)) for k in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    st = _wait(s, out, timeout=60)
+    assert len(set(out)) == 200 and all(x["state"] == rz.RZ_REQ_DONE for x in st)
+    s.close()
