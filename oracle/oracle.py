@@ -23,6 +23,7 @@ CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
 
 LINEAR = 0
 SCALE = 1
+PIECEWISE = 2
 
 _lock = threading.Lock()
 _lib = None
@@ -41,7 +42,7 @@ def configure(lib):
     """Declare the C signatures on a loaded oracle library."""
     P = ctypes.c_void_p
     i64, i32, u32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
-    cam = [P, f64, f64, i32, i32, i32, f64]
+    cam = [P, f64, f64, i32, i32, i32, f64, i32, P, P]
     lib.rzo_depth_constants.argtypes = cam + [P, P, P]
     lib.rzo_fragments.argtypes = [P, P, P, i64] + cam + [P, P]
     lib.rzo_clear.argtypes = [P, i64, u32]
@@ -76,9 +77,21 @@ def _u32(a):
     return np.ascontiguousarray(a, np.uint32)
 
 
+_KEEP = []
+
+
 def _cam_args(vp, near, far, width, height, kind, scale):
+    """kind LINEAR / SCALE with a number scale, or PIECEWISE with
+    scale = ((start_0, values_per_unit_0), (start_1, ...), ...)."""
     vp = np.ascontiguousarray(vp, np.float64).reshape(16)
-    return vp, [_ptr(vp), float(near), float(far), int(width), int(height), int(kind), float(scale)]
+    if int(kind) == PIECEWISE:
+        rng = np.asarray(scale, np.float64).reshape(-1, 2)
+        rb, rs = np.ascontiguousarray(rng[:, 0]), np.ascontiguousarray(rng[:, 1])
+        _KEEP[:] = [rb, rs]
+        return vp, [_ptr(vp), float(near), float(far), int(width), int(height), int(kind), 0.0,
+                    int(rb.size), _ptr(rb), _ptr(rs)]
+    return vp, [_ptr(vp), float(near), float(far), int(width), int(height), int(kind),
+                float(scale), 0, None, None]
 
 
 def depth_constants(vp, near, far, width, height, kind=LINEAR, scale=0.0):

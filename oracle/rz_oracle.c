@@ -42,7 +42,13 @@
  *  - the eps window is tested exactly in integers:
  *    den * (q - qmin) <= num * (qmin + z0) with z0 = floor(o * s), so that
  *    q + z0 is proportional to d;
- *  - the splat average rounds half up: (2 * sum + count) / (2 * count).
+ *  - the splat average rounds half up: (2 * sum + count) / (2 * count);
+ *  - piecewise map (section 2.1's sub-ranges): range k starts at b[k] with
+ *    sb[k] values per unit; q = base[k] + floor((d - b[k]) sb[k]),
+ *    base[k+1] = base[k] + floor((b[k+1] - b[k]) sb[k]) + 1;
+ *    its eps window compares the linear depths of q and qmin in double:
+ *    den * (d(q) - d(qmin)) <= num * d(qmin), d(q) = b[k] + (q - base[k]) / sb[k]
+ *    (the reciprocal of sb[k] computed once).
  */
 #include <math.h>
 #include <stddef.h>
@@ -53,7 +59,8 @@
 #define RZO_Q_MAX ((double)((1ull << 40) - 2)) /* largest fragment depth   */
 #define RZO_Q_RANGE ((double)((1ull << 40) - 1))
 
-enum { RZO_LINEAR = 0, RZO_SCALE = 1 };
+enum { RZO_LINEAR = 0, RZO_SCALE = 1, RZO_PIECEWISE = 2 };
+#define RZO_MAX_RANGES 8
 
 typedef struct {
     float m[16];       /* view-projection rounded to float, row-major */
@@ -64,12 +71,20 @@ typedef struct {
     float fw, fh;      /* framebuffer size as float                   */
     float hw, hh;      /* half of it                                  */
     int32_t w, h;
+    /* piecewise map (section 2.1, sub-ranges with their own precision):
+       range k starts at depth b[k] with sb[k] values per unit and first
+       integer base[k]; it ends where range k + 1 starts */
+    int32_t kind, nr;
+    double b[RZO_MAX_RANGES], sb[RZO_MAX_RANGES], inv[RZO_MAX_RANGES];
+    uint64_t base[RZO_MAX_RANGES + 1];
 } rzo_cam;
 
 static int rzo_cam_init(rzo_cam *c, const double *vp, double near_, double far_,
                         int32_t w, int32_t h, int32_t kind, double scale)
 {
     int i;
+    c->kind = kind;
+    c->nr = 0;
     if (w < 1 || h < 1 || !(near_ > 0.0) || !(far_ > near_))
         return -1;
     for (i = 0; i < 16; i++) {
@@ -86,6 +101,9 @@ static int rzo_cam_init(rzo_cam *c, const double *vp, double near_, double far_,
         c->s = scale;
         if (!(scale > 0.0))
             return -1;
+    } else if (kind == RZO_PIECEWISE) {
+        c->o = 0.0;        /* the ranges are set by rzo_cam_ranges */
+        c->s = 1.0;
     } else {
         return -1;
     }
@@ -100,6 +118,64 @@ static int rzo_cam_init(rzo_cam *c, const double *vp, double near_, double far_,
 }
 
 /*
+ * Piecewise map: nr ranges starting at b[0] <= near < b[1] < ..., each with
+ * its own number of integer values per unit of depth.  Range k+1 starts one
+ * integer above the largest value range k can produce, so q never decreases
+ * with d.
+ */
+static int rzo_cam_ranges(rzo_cam *c, int32_t nr, const double *b, const double *sb)
+{
+    int k;
+    if (nr < 1 || nr > RZO_MAX_RANGES || !(b[0] <= c->near_))
+        return -1;
+    c->nr = nr;
+    c->base[0] = 0;
+    for (k = 0; k < nr; k++) {
+        if (!(sb[k] > 0.0) || (k > 0 && !(b[k] > b[k - 1])))
+            return -1;
+        c->b[k] = b[k];
+        c->sb[k] = sb[k];
+        c->inv[k] = 1.0 / sb[k];
+        if (k + 1 < nr)
+            c->base[k + 1] = c->base[k] + (uint64_t)floor((b[k + 1] - b[k]) * sb[k]) + 1;
+    }
+    c->base[nr] = (1ull << 40) - 1;
+    return 0;
+}
+
+/* Depth -> 40-bit integer depth with the camera's map. */
+static uint64_t rzo_quantise(const rzo_cam *c, double d)
+{
+    double t, tf;
+    if (c->kind == RZO_PIECEWISE) {
+        int k = 0;
+        uint64_t qk;
+        while (k + 1 < c->nr && d >= c->b[k + 1])
+            k++;
+        /* d < b[k+1] and IEEE rounding is monotone, so this never exceeds
+           floor((b[k+1] - b[k]) * sb[k]) = base[k+1] - base[k] - 1 */
+        t = (d - c->b[k]) * c->sb[k];
+        tf = floor(t);
+        qk = c->base[k] + (uint64_t)tf;
+        return qk > (1ull << 40) - 2 ? (1ull << 40) - 2 : qk;
+    }
+    t = (d - c->o) * c->s;
+    tf = floor(t);
+    if (tf > RZO_Q_MAX)
+        tf = RZO_Q_MAX;
+    return (uint64_t)tf;
+}
+
+/* Linear depth of the start of integer depth q under a piecewise map. */
+static double rzo_depth_of(const rzo_cam *c, uint64_t q)
+{
+    int k = 0;
+    while (k + 1 < c->nr && q >= c->base[k + 1])
+        k++;
+    return c->b[k] + (double)(q - c->base[k]) * c->inv[k];
+}
+
+/*
  * The fragment of one point (section 2.1): its pixel index and its 40-bit
  * integer depth.  Returns 0 when the point is discarded.
  */
@@ -109,7 +185,7 @@ static int rzo_fragment(const rzo_cam *c, float x, float y, float z,
     const float *m = c->m;
     const double *v = c->vp;
     float cx, cy, cw, nx, ny, fx, fy;
-    double d, t, tf;
+    double d;
     int32_t px, py;
 
     /* clip coordinates in single precision, left to right */
@@ -147,13 +223,8 @@ static int rzo_fragment(const rzo_cam *c, float x, float y, float z,
         return 0;
 
     /* integer part of the scaled depth, kept inside 40 bits */
-    t = (d - c->o) * c->s;
-    tf = floor(t);
-    if (tf > RZO_Q_MAX)
-        tf = RZO_Q_MAX;
-
     *pix = (int64_t)py * c->w + px;
-    *q = (uint64_t)tf;
+    *q = rzo_quantise(c, d);
     return 1;
 }
 
@@ -163,11 +234,14 @@ static int rzo_fragment(const rzo_cam *c, float x, float y, float z,
 
 /* Depth-map constants (o, s, z0) as the oracle derives them. */
 int rzo_depth_constants(const double *vp, double near_, double far_, int32_t w,
-                        int32_t h, int32_t kind, double scale, double *o,
-                        double *s, uint64_t *z0)
+                        int32_t h, int32_t kind, double scale, int32_t nr,
+                        const double *rb, const double *rs, double *o, double *s,
+                        uint64_t *z0)
 {
     rzo_cam c;
     if (rzo_cam_init(&c, vp, near_, far_, w, h, kind, scale))
+        return -1;
+    if (kind == RZO_PIECEWISE && rzo_cam_ranges(&c, nr, rb, rs))
         return -1;
     *o = c.o;
     *s = c.s;
@@ -178,12 +252,14 @@ int rzo_depth_constants(const double *vp, double near_, double far_, int32_t w,
 /* Per-point fragments: pix[i] = pixel index or -1, q[i] = integer depth. */
 int rzo_fragments(const float *x, const float *y, const float *z, int64_t n,
                   const double *vp, double near_, double far_, int32_t w,
-                  int32_t h, int32_t kind, double scale, int64_t *pix,
-                  uint64_t *q)
+                  int32_t h, int32_t kind, double scale, int32_t nr,
+                  const double *rb, const double *rs, int64_t *pix, uint64_t *q)
 {
     rzo_cam c;
     int64_t i;
     if (rzo_cam_init(&c, vp, near_, far_, w, h, kind, scale))
+        return -1;
+    if (kind == RZO_PIECEWISE && rzo_cam_ranges(&c, nr, rb, rs))
         return -1;
     for (i = 0; i < n; i++) {
         int64_t p;
@@ -214,11 +290,14 @@ void rzo_clear(uint64_t *fb, int64_t npix, uint32_t bg)
 int rzo_raster_min(const float *x, const float *y, const float *z,
                    const uint32_t *rgb, int64_t n, const double *vp,
                    double near_, double far_, int32_t w, int32_t h,
-                   int32_t kind, double scale, uint64_t *fb)
+                   int32_t kind, double scale, int32_t nr, const double *rb,
+                   const double *rs, uint64_t *fb)
 {
     rzo_cam c;
     int64_t i;
     if (rzo_cam_init(&c, vp, near_, far_, w, h, kind, scale))
+        return -1;
+    if (kind == RZO_PIECEWISE && rzo_cam_ranges(&c, nr, rb, rs))
         return -1;
     for (i = 0; i < n; i++) {
         int64_t p;
@@ -254,14 +333,17 @@ void rzo_resolve_min(uint64_t *fb, int64_t npix, uint32_t bg, uint32_t *img)
 int rzo_hq_accumulate(const float *x, const float *y, const float *z,
                       const uint32_t *rgb, int64_t n, const double *vp,
                       double near_, double far_, int32_t w, int32_t h,
-                      int32_t kind, double scale, uint32_t eps_num,
-                      uint32_t eps_den, const uint64_t *fb, uint64_t *sums)
+                      int32_t kind, double scale, int32_t nr, const double *rb,
+                      const double *rs, uint32_t eps_num, uint32_t eps_den,
+                      const uint64_t *fb, uint64_t *sums)
 {
     rzo_cam c;
     int64_t i;
     if (eps_den == 0)
         return -1;
     if (rzo_cam_init(&c, vp, near_, far_, w, h, kind, scale))
+        return -1;
+    if (kind == RZO_PIECEWISE && rzo_cam_ranges(&c, nr, rb, rs))
         return -1;
     for (i = 0; i < n; i++) {
         int64_t p;
@@ -272,10 +354,19 @@ int rzo_hq_accumulate(const float *x, const float *y, const float *z,
         qmin = fb[p] >> 24;
         if (q < qmin)
             return -2; /* fb does not hold this cloud's depth pass */
-        /* exact: 128-bit products cannot overflow */
-        if ((unsigned __int128)eps_den * (q - qmin) >
-            (unsigned __int128)eps_num * ((unsigned __int128)qmin + c.z0))
-            continue;
+        if (c.kind == RZO_PIECEWISE) {
+            /* q + z0 is not proportional to d here: compare the linear
+               depths the two integers stand for, in double precision */
+            const double dq = rzo_depth_of(&c, q);
+            const double dm = rzo_depth_of(&c, qmin);
+            const double lhs = (double)eps_den * (dq - dm);
+            const double rhs = (double)eps_num * dm;
+            if (!(lhs <= rhs))
+                continue;
+        } else if ((unsigned __int128)eps_den * (q - qmin) >
+                   (unsigned __int128)eps_num * ((unsigned __int128)qmin + c.z0)) {
+            continue;   /* exact: 128-bit products cannot overflow */
+        }
         col = rgb[i];
         sums[4 * p + 0] += col & 0xFFu;
         sums[4 * p + 1] += (col >> 8) & 0xFFu;

@@ -399,3 +399,84 @@ def test_resolve_clears_framebuffer(oracle):
     sums = oracle.hq_accumulate(c.x, c.y, c.z, c.rgb, v.vp, v.near, v.far, v.width, v.height, fb)
     oracle.hq_resolve(sums, fb, bg)
     assert (fb == oracle.clear_value(bg)).all() and (sums == 0).all()
+
+
+# --------------------------------------------------------------------------
+# piecewise depth map (section 2.1: sub-ranges with their own precision)
+# --------------------------------------------------------------------------
+
+def _paper_ranges():
+    pw = _gold("paper_constants.json")["piecewise_example"]
+    return tuple((a, sc) for (a, _), sc in zip(pw["ranges_m"], pw["values_per_m"]))
+
+
+def _piecewise_q_exact(d, ranges):
+    """Integer depth by the definition, in exact rationals."""
+    starts = [F(a) for a, _ in ranges]
+    scales = [F(sc) for _, sc in ranges]
+    base = [0]
+    for k in range(len(ranges) - 1):
+        base.append(base[k] + math.floor((starts[k + 1] - starts[k]) * scales[k]) + 1)
+    k = max(i for i, a in enumerate(starts) if F(d) >= a)
+    return base[k] + math.floor((F(d) - starts[k]) * scales[k]), base
+
+
+def test_piecewise_paper_example(oracle):
+    """nm up to 10 m, um up to 10 km, mm beyond: every range uses at most
+    10 billion values, 30 billion in all (section 2.1)."""
+    ranges = _paper_ranges()
+    g = _gold("paper_constants.json")["piecewise_example"]
+    vp = _axis_camera()
+    ds = np.array([0.5, 5.0, 9.5, np.nextafter(np.float32(10), np.float32(0)), 10.0, 10.5, 9999.5,
+                   10000.0, 12345.5, 1.0e6, 9.0e6], np.float32)
+    e = np.zeros_like(ds)
+    pix, q = oracle.fragments(e, e, -ds, vp, 0.25, 1.0e7, 2, 2, oracle.PIECEWISE, ranges)
+    assert (pix == 3).all()
+    for d, qq in zip(ds, q):
+        want, base = _piecewise_q_exact(float(d), ranges)
+        assert int(qq) == want, (float(d), int(qq), want)
+    # bases: 1e10 + 1 and 1e10 + 1 + 9.99e9 + 1; the last value is below 3e10
+    _, base = _piecewise_q_exact(1.0, ranges)
+    assert base == [0, 10_000_000_001, 19_990_000_002]
+    top = base[2] + math.floor((F(10_000_000) - F(10_000)) * F(1000))
+    assert top <= g["total_values"] and max(base[1], base[2] - base[1]) <= g["max_values_per_range"] + 1
+    # dense sweep: never decreasing, and distinct float32 depths stay
+    # distinct (nm near the camera, mm far away)
+    for lo, hi in ((0.3, 12.0), (9990.0, 10020.0), (9.0e5, 9.1e5)):
+        d = np.unique(np.linspace(lo, hi, 20001).astype(np.float32))
+        e = np.zeros_like(d)
+        _, qq = oracle.fragments(e, e, -d, vp, 0.25, 1.0e7, 2, 2, oracle.PIECEWISE, ranges)
+        qq = qq.astype(np.int64)
+        assert (np.diff(qq) > 0).all()
+
+
+def test_piecewise_window_uses_linear_depth(oracle):
+    """With sub-ranges the 1% window is taken in linear depth, relative to the
+    nearest depth, also across a range boundary: nearest 5.00 m, 5.04 m in,
+    5.0505 m out (1.01 x 5.00 = 5.05), 5.06 m out; nearest 9.95 m, 10.04 m in
+    (next range), 10.06 m out.  Worked out by hand."""
+    ranges = _paper_ranges()
+    vp = _axis_camera()
+    for zs in ([5.0, 5.04, 5.0505, 5.06], [9.95, 10.04, 10.0496, 10.06]):
+        z = -np.array(zs, np.float32)
+        e = np.zeros_like(z)
+        rgb = np.array([10, 20, 100, 200], np.uint32)
+        _, sums, _ = oracle.render_hq(e, e, z, rgb, vp, 0.25, 1.0e7, 2, 2, oracle.PIECEWISE,
+                                      ranges)
+        assert sums[3].tolist() == [30, 0, 0, 2]
+
+
+def test_piecewise_range_boundary(oracle):
+    """Range 1 starts one integer above the largest value of range 0, also
+    when the next start is not on range 0's grid."""
+    vp = _axis_camera()
+    ranges = ((0.0, 3.0), (1.0, 1000.0))        # base[1] = floor(1 * 3) + 1 = 4
+    d = np.array([0.5, 0.99999994, 1.0, 1.001], np.float32)
+    e = np.zeros_like(d)
+    _, q = oracle.fragments(e, e, -d, vp, 0.25, 10.0, 2, 2, oracle.PIECEWISE, ranges)
+    assert q.tolist() == [1, 2, 4, 5]
+    ranges = ((0.0, 2.5), (1.0, 1000.0))        # base[1] = floor(2.5) + 1 = 3
+    d = np.array([0.9999999, 1.0], np.float32)
+    e = np.zeros_like(d)
+    _, q = oracle.fragments(e, e, -d, vp, 0.25, 10.0, 2, 2, oracle.PIECEWISE, ranges)
+    assert q.tolist() == [2, 3]

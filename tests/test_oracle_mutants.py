@@ -23,7 +23,8 @@ MUTANTS = {
     "depth in single precision": ("d = d + v[15];", "d = d + v[15];\n    d = (double)cw;"),
     "far inclusive": ("d < c->far_", "d <= c->far_"),
     "near exclusive": ("d >= c->near_", "d > c->near_"),
-    "round instead of floor": ("tf = floor(t);", "tf = round(t);"),
+    "round instead of floor": ("    t = (d - c->o) * c->s;\n    tf = floor(t);",
+                               "    t = (d - c->o) * c->s;\n    tf = round(t);"),
     "no clamp below clear depth": ("#define RZO_Q_MAX ((double)((1ull << 40) - 2))",
                                    "#define RZO_Q_MAX ((double)((1ull << 40) - 1))"),
     "linear range off by one": ("#define RZO_Q_RANGE ((double)((1ull << 40) - 1))",
@@ -36,8 +37,15 @@ MUTANTS = {
     "eps window exclusive": ("(unsigned __int128)eps_den * (q - qmin) >\n",
                              "(unsigned __int128)eps_den * (q - qmin) >=\n"),
     "eps offset z0 dropped": ("((unsigned __int128)qmin + c.z0)", "((unsigned __int128)qmin)"),
-    "eps num and den swapped": ("if ((unsigned __int128)eps_den * (q - qmin) >\n            (unsigned __int128)eps_num",
-                                "if ((unsigned __int128)eps_num * (q - qmin) >\n            (unsigned __int128)eps_den"),
+    "eps num and den swapped": ("if ((unsigned __int128)eps_den * (q - qmin) >\n                   (unsigned __int128)eps_num",
+                                "if ((unsigned __int128)eps_num * (q - qmin) >\n                   (unsigned __int128)eps_den"),
+    "piecewise base off by one": ("+ (uint64_t)floor((b[k + 1] - b[k]) * sb[k]) + 1;",
+                                  "+ (uint64_t)floor((b[k + 1] - b[k]) * sb[k]);"),
+    "piecewise range boundary exclusive": ("while (k + 1 < c->nr && d >= c->b[k + 1])",
+                                           "while (k + 1 < c->nr && d > c->b[k + 1])"),
+    "piecewise range start not subtracted": ("t = (d - c->b[k]) * c->sb[k];", "t = d * c->sb[k];"),
+    "piecewise window from the wrong depth": ("const double rhs = (double)eps_num * dm;",
+                                              "const double rhs = (double)eps_num * dq;"),
     "truncating average": ("uint64_t r = (2 * sums[4 * p + 0] + cnt) / (2 * cnt);",
                            "uint64_t r = sums[4 * p + 0] / cnt;"),
     "green reads blue": ("sums[4 * p + 1] += (col >> 8) & 0xFFu;", "sums[4 * p + 1] += (col >> 16) & 0xFFu;"),
@@ -64,6 +72,9 @@ PINS = [
     (T.test_fragments_match_exact_projection, {"seed": 1, "kind": 0, "scale": 0.0}),
     (T.test_framebuffer_matches_brute_force, {"seed": 5}),
     (T.test_eps_window_relative_to_linear_depth, {}),
+    (T.test_piecewise_paper_example, {}),
+    (T.test_piecewise_window_uses_linear_depth, {}),
+    (T.test_piecewise_range_boundary, {}),
     (T.test_hq_depth_pass_equals_basic, {}),
     (T.test_hq_huge_eps_averages_whole_pixel, {}),
     (T.test_hq_integer_window_matches_linear_depth, {}),
