@@ -75,6 +75,18 @@ extern "C" {
 /* o = 0, s = scale: the paper's example is scale = 1000 for millimetre
    precision in a scene given in metres.  Requires far * scale <= 2^40 - 1. */
 #define RZ_DEPTH_SCALE 1
+/* Sub-ranges with their own precision (section 2.1, e.g. nm up to 10 m, um
+   up to 10 km, mm beyond).  Range k starts at range_start[k] (strictly
+   increasing, range_start[0] <= near) with range_scale[k] > 0 values per
+   unit of depth:
+     base[0] = 0,  base[k+1] = base[k] + floor((start[k+1] - start[k]) * scale[k]) + 1,
+     q = base[k] + floor((d - start[k]) * scale[k])  for start[k] <= d < start[k+1],
+   which never decreases with d.  Requires the last range to reach far
+   within 2^40 - 1 values (else RZ_EDEPTHRANGE).  The splatting window then
+   compares linear depths: den * (d(q) - d(qmin)) <= num * d(qmin) in double,
+   with d(q) = start[k] + (q - base[k]) * (1 / scale[k]). */
+#define RZ_DEPTH_PIECEWISE 2
+#define RZ_MAX_RANGES 8
 
 typedef struct rz_points {
     const float *x;        /* device, n floats */
@@ -93,15 +105,18 @@ typedef struct rz_view {
 } rz_view;
 
 typedef struct rz_depth_map {
-    int32_t kind;          /* RZ_DEPTH_LINEAR or RZ_DEPTH_SCALE           */
+    int32_t kind;          /* RZ_DEPTH_LINEAR, _SCALE or _PIECEWISE       */
     double scale;          /* used by RZ_DEPTH_SCALE only; > 0            */
+    int32_t nranges;       /* RZ_DEPTH_PIECEWISE: 1 .. RZ_MAX_RANGES      */
+    double range_start[RZ_MAX_RANGES];
+    double range_scale[RZ_MAX_RANGES];
 } rz_depth_map;
 
 typedef struct rz_hq_params {
     /* eps = eps_num / eps_den (section 2.2 uses 1/100).  A fragment of depth
        q joins pixel p iff eps_den * (q - qmin) <= eps_num * (qmin + z0),
        qmin = nearest depth of p, z0 = floor(o * s) (so that q + z0 is
-       proportional to d).  1 <= eps_den <= 2^20, eps_num <= 2^20, and
+       proportional to d); for RZ_DEPTH_PIECEWISE see there.  1 <= eps_den <= 2^20, eps_num <= 2^20, and
        eps_num * (2^40 + z0) < 2^63 (else RZ_EDEPTHRANGE). */
     uint32_t eps_num;
     uint32_t eps_den;

@@ -66,9 +66,52 @@ int make_proj(const rz_view *v, const rz_depth_map *dm, Proj *P)
         s = dm->scale;
         if (!(v->far_ * s <= kQRange))
             return RZ_EDEPTHRANGE;
+    } else if (dm->kind == RZ_DEPTH_PIECEWISE) {
+        const int32_t nr = dm->nranges;
+        if (nr < 1 || nr > RZ_MAX_RANGES || !isfinite(dm->range_start[0]) ||
+            !(dm->range_start[0] <= v->near_))
+            return RZ_EINVAL;
+        // bases from consecutive starts (independent of far); only the
+        // range that contains far bounds the depths that can occur
+        double base = 0.0;
+        for (int32_t k = 0; k < nr; ++k) {
+            const double b = dm->range_start[k], sc = dm->range_scale[k];
+            if (!isfinite(b) || !isfinite(sc) || !(sc > 0.0) ||
+                (k > 0 && !(b > dm->range_start[k - 1])))
+                return RZ_EINVAL;
+            P->rb[k] = b;
+            P->rs[k] = sc;
+            P->rinv[k] = 1.0 / sc;
+            P->rbase[k] = (uint64_t)base;
+            if (b < v->far_) {
+                const double end = k + 1 < nr && dm->range_start[k + 1] < v->far_
+                                       ? dm->range_start[k + 1]
+                                       : v->far_;
+                if (!(base + floor((end - b) * sc) <= kQRange - 1.0))
+                    return RZ_EDEPTHRANGE;
+            }
+            if (k + 1 < nr) {
+                base += floor((dm->range_start[k + 1] - b) * sc) + 1.0;
+                if (!(base < 9.0e18))
+                    return RZ_EDEPTHRANGE;
+            }
+        }
+        for (int32_t k = nr; k < 8; ++k) {
+            P->rb[k] = 0.0;
+            P->rs[k] = 1.0;
+            P->rinv[k] = 1.0;
+            P->rbase[k] = (1ull << 40) - 1;
+        }
+        P->rbase[nr] = (1ull << 40) - 1;
+        P->rbase[8] = (1ull << 40) - 1;
+        P->nr = nr;
+        o = 0.0;
+        s = 1.0;
     } else {
         return RZ_EINVAL;
     }
+    if (dm->kind != RZ_DEPTH_PIECEWISE)
+        P->nr = 0;
     if (!isfinite(s) || !(s > 0.0))
         return RZ_EDEPTHRANGE;
     const double z0 = floor(o * s);
@@ -105,7 +148,9 @@ int check_hq(const rz_hq_params *hq, const Proj &P, uint32_t *num, uint32_t *den
     if (d < 1 || d > (1u << 20) || n > (1u << 20))
         return RZ_EINVAL;
     // num * (2^40 + z0) < 2^63, and den * 2^40 < 2^63 holds by den <= 2^20
-    if (n > 0 && (double)P.z0 + 1099511627776.0 >= 9223372036854775808.0 / (double)n)
+    // (the piecewise window is tested in double precision instead)
+    if (P.nr == 0 && n > 0 &&
+        (double)P.z0 + 1099511627776.0 >= 9223372036854775808.0 / (double)n)
         return RZ_EDEPTHRANGE;
     *num = n;
     *den = d;

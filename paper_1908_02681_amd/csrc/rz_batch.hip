@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(512) k_mv_raster_min(Pts p, const MvView *__re
 }
 
 // Accumulate passes of the splatting views views[0 .. nv) over one chunk.
-template <int PPT, bool VEC, bool XCD, int BIN>
+template <int PPT, bool VEC, bool XCD, int BIN, bool PW>
 __global__ void __launch_bounds__(512) k_mv_hq_accum(Pts p, const MvView *__restrict__ views,
                                                      int32_t nv, int64_t nchunks)
 {
@@ -106,15 +106,15 @@ __global__ void __launch_bounds__(512) k_mv_hq_accum(Pts p, const MvView *__rest
     for (int32_t k = 0; k < nv; ++k) {
         const Proj P = views[k].P;
         if (BIN == kBinWave) {
-            accum_chunk_wave<PPT>(P, views[k].eps_num, views[k].eps_den, views[k].fb,
-                                  views[k].acc, x, y, z, c, in,
-                                  s_waves + (threadIdx.x >> 6) * kWaveTileWords);
+            accum_chunk_wave<PPT, PW>(P, views[k].eps_num, views[k].eps_den, views[k].fb,
+                                      views[k].acc, x, y, z, c, in,
+                                      s_waves + (threadIdx.x >> 6) * kWaveTileWords);
         } else {
             if (BIN == kBinBlock && k > 0)
                 __syncthreads();
-            accum_chunk<PPT, BIN == kBinBlock>(P, views[k].eps_num, views[k].eps_den,
-                                               views[k].fb, views[k].acc, x, y, z, c, in,
-                                               s_tile, s_box);
+            accum_chunk<PPT, BIN == kBinBlock, PW>(P, views[k].eps_num, views[k].eps_den,
+                                                   views[k].fb, views[k].acc, x, y, z, c, in,
+                                                   s_tile, s_box);
         }
     }
 }
@@ -178,15 +178,18 @@ __global__ void __launch_bounds__(256) k_mv_checksum(const MvResolve *__restrict
 }
 
 template <int PPT, bool VEC, bool XCD, int BIN>
-hipError_t mv_launch_ppt(bool hq, const Pts &p, const MvView *views, int32_t nv, const Tune &t,
-                         hipStream_t s)
+hipError_t mv_launch_ppt(bool hq, bool pw, const Pts &p, const MvView *views, int32_t nv,
+                         const Tune &t, hipStream_t s)
 {
     const int64_t nchunks = (p.n + (int64_t)t.block * PPT - 1) / ((int64_t)t.block * PPT);
     const int64_t grid = XCD ? (nchunks + kXcds - 1) / kXcds * kXcds : nchunks;
     const size_t lds =
         BIN == kBinWave ? (size_t)(t.block / 64) * kWaveTileWords * sizeof(uint64_t) : 0;
-    if (hq)
-        hipLaunchKernelGGL((k_mv_hq_accum<PPT, VEC, XCD, BIN>), dim3((uint32_t)grid),
+    if (hq && pw)
+        hipLaunchKernelGGL((k_mv_hq_accum<PPT, VEC, XCD, BIN, true>), dim3((uint32_t)grid),
+                           dim3(t.block), lds, s, p, views, nv, nchunks);
+    else if (hq)
+        hipLaunchKernelGGL((k_mv_hq_accum<PPT, VEC, XCD, BIN, false>), dim3((uint32_t)grid),
                            dim3(t.block), lds, s, p, views, nv, nchunks);
     else
         hipLaunchKernelGGL((k_mv_raster_min<PPT, VEC, XCD, BIN>), dim3((uint32_t)grid),
@@ -195,37 +198,37 @@ hipError_t mv_launch_ppt(bool hq, const Pts &p, const MvView *views, int32_t nv,
 }
 
 template <int PPT, bool VEC, bool XCD>
-hipError_t mv_launch_bin(bool hq, const Pts &p, const MvView *views, int32_t nv, const Tune &t,
-                         hipStream_t s)
+hipError_t mv_launch_bin(bool hq, bool pw, const Pts &p, const MvView *views, int32_t nv,
+                         const Tune &t, hipStream_t s)
 {
     switch (t.bin) {
-    case kBinBlock: return mv_launch_ppt<PPT, VEC, XCD, kBinBlock>(hq, p, views, nv, t, s);
-    case kBinWave: return mv_launch_ppt<PPT, VEC, XCD, kBinWave>(hq, p, views, nv, t, s);
-    default: return mv_launch_ppt<PPT, VEC, XCD, kBinNone>(hq, p, views, nv, t, s);
+    case kBinBlock: return mv_launch_ppt<PPT, VEC, XCD, kBinBlock>(hq, pw, p, views, nv, t, s);
+    case kBinWave: return mv_launch_ppt<PPT, VEC, XCD, kBinWave>(hq, pw, p, views, nv, t, s);
+    default: return mv_launch_ppt<PPT, VEC, XCD, kBinNone>(hq, pw, p, views, nv, t, s);
     }
 }
 
 template <int PPT>
-hipError_t mv_launch_sel(bool hq, const Pts &p, const MvView *views, int32_t nv, const Tune &t,
-                         bool vec, hipStream_t s)
+hipError_t mv_launch_sel(bool hq, bool pw, const Pts &p, const MvView *views, int32_t nv,
+                         const Tune &t, bool vec, hipStream_t s)
 {
     if (vec)
-        return t.xcd_remap ? mv_launch_bin<PPT, true, true>(hq, p, views, nv, t, s)
-                           : mv_launch_bin<PPT, true, false>(hq, p, views, nv, t, s);
-    return mv_launch_bin<PPT, false, false>(hq, p, views, nv, t, s);
+        return t.xcd_remap ? mv_launch_bin<PPT, true, true>(hq, pw, p, views, nv, t, s)
+                           : mv_launch_bin<PPT, true, false>(hq, pw, p, views, nv, t, s);
+    return mv_launch_bin<PPT, false, false>(hq, pw, p, views, nv, t, s);
 }
 
-hipError_t mv_launch(bool hq, const Pts &p, const MvView *views, int32_t nv, const Tune &t,
-                     hipStream_t s)
+hipError_t mv_launch(bool hq, bool pw, const Pts &p, const MvView *views, int32_t nv,
+                     const Tune &t, hipStream_t s)
 {
     if (p.n == 0 || nv == 0)
         return hipSuccess;
     const bool vec = (((uintptr_t)p.x | (uintptr_t)p.y | (uintptr_t)p.z | (uintptr_t)p.rgb) &
                       15u) == 0;
     switch (t.ppt) {
-    case 4: return mv_launch_sel<4>(hq, p, views, nv, t, vec, s);
-    case 8: return mv_launch_sel<8>(hq, p, views, nv, t, vec, s);
-    case 16: return mv_launch_sel<16>(hq, p, views, nv, t, vec, s);
+    case 4: return mv_launch_sel<4>(hq, pw, p, views, nv, t, vec, s);
+    case 8: return mv_launch_sel<8>(hq, pw, p, views, nv, t, vec, s);
+    case 16: return mv_launch_sel<16>(hq, pw, p, views, nv, t, vec, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -272,6 +275,7 @@ struct rz_batch {
     Pts pts;
     int32_t nviews = 0;
     int32_t nhq = 0;
+    bool hq_pw = false;                   // some splatting view uses a piecewise map
     int64_t resolve_blocks = 0;
     void *dmem = nullptr;                 // one allocation: tables + checksum word
     MvView *d_raster = nullptr;           // all views
@@ -292,9 +296,11 @@ hipError_t enqueue(rz_batch *b, hipStream_t s)
     const int32_t K = b->opts.views_per_group;
     hipError_t e = hipSuccess;
     for (int32_t g = 0; g < b->nviews && e == hipSuccess; g += K)
-        e = mv_launch(false, b->pts, b->d_raster + g, std::min(K, b->nviews - g), b->tune, s);
+        e = mv_launch(false, false, b->pts, b->d_raster + g, std::min(K, b->nviews - g), b->tune,
+                      s);
     for (int32_t g = 0; g < b->nhq && e == hipSuccess; g += K)
-        e = mv_launch(true, b->pts, b->d_accum + g, std::min(K, b->nhq - g), b->tune, s);
+        e = mv_launch(true, b->hq_pw, b->pts, b->d_accum + g, std::min(K, b->nhq - g), b->tune,
+                      s);
     if (e == hipSuccess && b->resolve_blocks > 0) {
         hipLaunchKernelGGL(k_mv_resolve, dim3((uint32_t)b->resolve_blocks), dim3(256), 0, s,
                            b->d_resolve, b->nviews, b->opts.status);
@@ -420,6 +426,8 @@ int rz_batch_plan(const rz_points *pts, const rz_batch_view *views, int32_t nvie
     b->pts = Pts{pts->x, pts->y, pts->z, pts->rgb, pts->n};
     b->nviews = nviews;
     b->nhq = (int32_t)accum.size();
+    for (const MvView &m : accum)
+        b->hq_pw = b->hq_pw || m.P.nr > 0;
     b->resolve_blocks = blocks;
     b->opts = o;
     b->tune = tune_of(o.launch);

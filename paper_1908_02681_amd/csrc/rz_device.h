@@ -52,6 +52,52 @@ __device__ __forceinline__ T ldnt(const T *p) { return __builtin_nontemporal_loa
 template <typename T>
 __device__ __forceinline__ void stnt(T v, T *p) { __builtin_nontemporal_store(v, p); }
 
+// 0 <= t < 2^40, integral: split into two exact 32-bit halves.
+__device__ __forceinline__ uint64_t to_u64(double t)
+{
+    const uint32_t hi = (uint32_t)(t * 0x1p-32);
+    const uint32_t lo = (uint32_t)(t - (double)hi * 0x1p32);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Piecewise depth map (section 2.1, sub-ranges with their own precision):
+// range k with start rb[k] <= d < rb[k+1]; q = rbase[k] + floor((d - rb[k]) *
+// rs[k]), which stays below rbase[k+1] because IEEE rounding is monotone.
+__device__ __forceinline__ uint64_t piecewise_q(const Proj &P, double d)
+{
+    int k = 0;
+    for (int i = 1; i < 8; ++i)
+        k = (i < P.nr && d >= P.rb[i]) ? i : k;
+    const double tf = floor((d - P.rb[k]) * P.rs[k]);
+    const uint64_t q = P.rbase[k] + to_u64(tf);
+    return q > (1ull << 40) - 2 ? (1ull << 40) - 2 : q;
+}
+
+// Linear depth of integer depth q under the piecewise map.
+__device__ __forceinline__ double piecewise_depth(const Proj &P, uint64_t q)
+{
+    int k = 0;
+    for (int i = 1; i < 8; ++i)
+        k = (i < P.nr && q >= P.rbase[i]) ? i : k;
+    return P.rb[k] + (double)(q - P.rbase[k]) * P.rinv[k];
+}
+
+// Section 2.2's window: does a fragment of depth q join the pixel whose
+// nearest depth is qmin?  Linear maps: exact integer test; piecewise maps:
+// the linear depths the integers stand for, in double precision.
+template <bool PW>
+__device__ __forceinline__ bool in_window(const Proj &P, uint32_t eps_num, uint32_t eps_den,
+                                          uint64_t q, uint64_t qmin)
+{
+    if (!PW || P.nr == 0)   // PW kernels also serve linear views of a batch
+        return (uint64_t)eps_den * (q - qmin) <= (uint64_t)eps_num * (qmin + P.z0);
+    const double dq = piecewise_depth(P, q);
+    const double dm = piecewise_depth(P, qmin);
+    const double lhs = (double)eps_den * (dq - dm);
+    const double rhs = (double)eps_num * dm;
+    return lhs <= rhs;
+}
+
 // The fragment of one point: pixel coordinates and 40-bit depth (section
 // 2.1).  Returns false when the point is discarded.
 __device__ __forceinline__ bool fragment(const Proj &P, float x, float y, float z,
@@ -87,13 +133,14 @@ __device__ __forceinline__ bool fragment(const Proj &P, float x, float y, float 
     d = d + P.v[3];
     if (!(d >= P.near_ && d < P.far_))
         return false;
-    double tf = floor((d - P.o) * P.s);
-    if (tf > kQMax)
-        tf = kQMax;
-    // 0 <= tf < 2^40: split into two exact 32-bit halves
-    const uint32_t hi = (uint32_t)(tf * 0x1p-32);
-    const uint32_t lo = (uint32_t)(tf - (double)hi * 0x1p32);
-    q = ((uint64_t)hi << 32) | lo;
+    if (P.nr == 0) {
+        double tf = floor((d - P.o) * P.s);
+        if (tf > kQMax)
+            tf = kQMax;
+        q = to_u64(tf);
+    } else {
+        q = piecewise_q(P, d);
+    }
     return true;
 }
 
@@ -335,6 +382,18 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Row and column of tile entry i in a tile bw wide: i / bw through a float
+// reciprocal, corrected to the exact quotient (i < 2^24, bw <= 2^15).
+__device__ __forceinline__ void tile_rc(uint32_t i, uint32_t bw, float inv_bw, uint32_t &r,
+                                        uint32_t &col)
+{
+    uint32_t q = (uint32_t)((float)i * inv_bw);
+    q = q * bw > i ? q - 1 : q;
+    q = (q + 1) * bw <= i ? q + 1 : q;
+    r = q;
+    col = i - q * bw;
+}
+
 // Screen rectangle of the live fragments of one wave (no workgroup barrier).
 template <int PPT>
 __device__ __forceinline__ Box wave_box(const uint32_t (&px)[PPT], const uint32_t (&py)[PPT],
@@ -413,11 +472,12 @@ __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__res
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         wave_sync();
+        const float inv_bw = 1.0f / (float)bw;
         for (uint32_t i = lane; i < area; i += 64) {
             const uint64_t v = w_tile[i];
             if (v != ~0ull) {
-                const uint32_t r = i / bw;
-                const uint32_t col = i - r * bw;
+                uint32_t r, col;
+                tile_rc(i, bw, inv_bw, r, col);
                 uint64_t *dst = fb + (uint64_t)(box.y0 + r) * (uint32_t)P.width + box.x0 + col;
                 const uint64_t cur = __hip_atomic_load(dst, __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_AGENT);
@@ -431,15 +491,23 @@ __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__res
         for (int j = 0; j < PPT; ++j)
             direct[j] = live[j];
     }
-    uint64_t cur[PPT];
+    // fragments outside the tile: usually none in the whole wave
+    bool any_direct = false;
 #pragma unroll
     for (int j = 0; j < PPT; ++j)
-        cur[j] = __hip_atomic_load(fb + (direct[j] ? pix[j] : 0u), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+        any_direct = any_direct || direct[j];
+    if (__any(any_direct)) {
+        uint64_t cur[PPT];
 #pragma unroll
-    for (int j = 0; j < PPT; ++j)
-        if (direct[j] && key[j] < cur[j])
-            __hip_atomic_fetch_min(fb + pix[j], key[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int j = 0; j < PPT; ++j)
+            cur[j] = __hip_atomic_load(fb + (direct[j] ? pix[j] : 0u), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int j = 0; j < PPT; ++j)
+            if (direct[j] && key[j] < cur[j])
+                __hip_atomic_fetch_min(fb + pix[j], key[j], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // Accumulation pass of high-quality splatting over one chunk (section 2.2).
@@ -450,8 +518,9 @@ __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__res
 // pixel are summed in registers, and with BIN the workgroup's sums are
 // gathered in an LDS tile (64-bit LDS adds) and flushed once per pixel.
 // Integer sums are order independent, so every variant gives the same bits.
+// PW: the piecewise depth map's window test (linear depths in double).
 // Barrier rules as for raster_chunk.
-template <int PPT, bool BIN>
+template <int PPT, bool BIN, bool PW>
 __device__ __forceinline__ void accum_chunk(const Proj &P, uint32_t eps_num, uint32_t eps_den,
                                             const uint64_t *__restrict__ fb,
                                             uint64_t *__restrict__ acc,
@@ -482,8 +551,7 @@ __device__ __forceinline__ void accum_chunk(const Proj &P, uint32_t eps_num, uin
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const uint64_t qmin = fbv[j] >> 24;
-        ok[j] = ok[j] &&
-                (uint64_t)eps_den * (q[j] - qmin) <= (uint64_t)eps_num * (qmin + P.z0);
+        ok[j] = ok[j] && in_window<PW>(P, eps_num, eps_den, q[j], qmin);
     }
     uint64_t w0[PPT], w1[PPT];
 #pragma unroll
@@ -558,7 +626,7 @@ __device__ __forceinline__ void accum_chunk(const Proj &P, uint32_t eps_num, uin
 
 // Accumulate pass over one chunk with a private LDS tile per wave (see
 // raster_chunk_wave).  Same result bits as accum_chunk.
-template <int PPT>
+template <int PPT, bool PW>
 __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num,
                                                  uint32_t eps_den,
                                                  const uint64_t *__restrict__ fb,
@@ -587,8 +655,7 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const uint64_t qmin = fbv[j] >> 24;
-        ok[j] = ok[j] &&
-                (uint64_t)eps_den * (q[j] - qmin) <= (uint64_t)eps_num * (qmin + P.z0);
+        ok[j] = ok[j] && in_window<PW>(P, eps_num, eps_den, q[j], qmin);
     }
     uint64_t w0[PPT], w1[PPT];
 #pragma unroll
@@ -631,12 +698,13 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
             }
         }
         wave_sync();
+        const float inv_bw = 1.0f / (float)bw;
         for (uint32_t i = lane; i < area; i += 64) {
             const uint64_t a1 = w_tile[2 * i + 1];
             if (a1 != 0ull) {
                 const uint64_t a0 = w_tile[2 * i];
-                const uint32_t r = i / bw;
-                const uint32_t col = i - r * bw;
+                uint32_t r, col;
+                tile_rc(i, bw, inv_bw, r, col);
                 uint64_t *dst =
                     acc + 2 * ((uint64_t)(box.y0 + r) * (uint32_t)P.width + box.x0 + col);
                 __hip_atomic_fetch_add(dst, a0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

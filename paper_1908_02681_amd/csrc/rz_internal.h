@@ -18,15 +18,22 @@ struct Proj {
     double o, s;          // q = floor((d - o) * s)
     uint64_t z0;          // floor(o * s)
     int32_t width, height;
+    // piecewise depth map: nr > 0 selects it
+    int32_t nr;
+    int32_t pad_;
+    double rb[8];         // range starts
+    double rs[8];         // values per unit
+    double rinv[8];       // 1 / rs
+    uint64_t rbase[9];    // first integer of each range; rbase[nr] = 2^40 - 1
 };
 
 // Launch shape of the point kernels.
 struct Tune {
-    int block = 256;       // threads per workgroup: 64, 128, 256 or 512
+    int block = 64;        // threads per workgroup: 64, 128, 256 or 512
     int ppt = 16;          // points per thread: 4, 8 or 16
     int early_out = 1;     // read the framebuffer before the atomic
-    int xcd_remap = 1;     // give each XCD a contiguous range of chunks
-    int bin = 1;           // LDS tile merge before the global atomics
+    int xcd_remap = 0;     // give each XCD a contiguous range of chunks
+    int bin = 2;           // 0 none, 1 workgroup LDS tile, 2 per-wave LDS tile
 };
 
 constexpr uint64_t kDepthOnes = 0xFFFFFFFFFF000000ull;

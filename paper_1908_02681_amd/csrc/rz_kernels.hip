@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(512) k_raster_min(Pts p, Proj P, uint64_t *__r
 }
 
 // Accumulation pass of section 2.2 for one view.
-template <int PPT, bool VEC, bool XCD, int BIN>
+template <int PPT, bool VEC, bool XCD, int BIN, bool PW>
 __global__ void __launch_bounds__(512) k_hq_accum(Pts p, Proj P, uint32_t eps_num,
                                                   uint32_t eps_den,
                                                   const uint64_t *__restrict__ fb,
@@ -58,11 +58,11 @@ __global__ void __launch_bounds__(512) k_hq_accum(Pts p, Proj P, uint32_t eps_nu
     bool in[PPT];
     load_points<PPT, VEC>(p, chunk * (int64_t)blockDim.x * PPT, x, y, z, c, in);
     if (BIN == kBinWave)
-        accum_chunk_wave<PPT>(P, eps_num, eps_den, fb, acc, x, y, z, c, in,
-                              s_waves + (threadIdx.x >> 6) * kWaveTileWords);
+        accum_chunk_wave<PPT, PW>(P, eps_num, eps_den, fb, acc, x, y, z, c, in,
+                                  s_waves + (threadIdx.x >> 6) * kWaveTileWords);
     else
-        accum_chunk<PPT, BIN == kBinBlock>(P, eps_num, eps_den, fb, acc, x, y, z, c, in, s_tile,
-                                           s_box);
+        accum_chunk<PPT, BIN == kBinBlock, PW>(P, eps_num, eps_den, fb, acc, x, y, z, c, in,
+                                               s_tile, s_box);
 }
 
 // Resolve of section 2.1: colour bits to the image, framebuffer cleared.
@@ -160,7 +160,7 @@ hipError_t raster_min_ppt(const Pts &p, const Proj &P, uint64_t *fb, const Tune 
     return hipGetLastError();
 }
 
-template <int PPT, bool VEC, int BIN>
+template <int PPT, bool VEC, int BIN, bool PW>
 hipError_t hq_accum_ppt(const Pts &p, const Proj &P, uint32_t num, uint32_t den,
                         const uint64_t *fb, uint64_t *acc, const Tune &t, hipStream_t s)
 {
@@ -168,10 +168,10 @@ hipError_t hq_accum_ppt(const Pts &p, const Proj &P, uint32_t num, uint32_t den,
     const size_t lds = wave_lds(BIN, t.block);
     if (t.xcd_remap) {
         const int64_t grid = (nchunks + kXcds - 1) / kXcds * kXcds;
-        hipLaunchKernelGGL((k_hq_accum<PPT, VEC, true, BIN>), dim3((uint32_t)grid),
+        hipLaunchKernelGGL((k_hq_accum<PPT, VEC, true, BIN, PW>), dim3((uint32_t)grid),
                            dim3(t.block), lds, s, p, P, num, den, fb, acc, nchunks);
     } else {
-        hipLaunchKernelGGL((k_hq_accum<PPT, VEC, false, BIN>), dim3((uint32_t)nchunks),
+        hipLaunchKernelGGL((k_hq_accum<PPT, VEC, false, BIN, PW>), dim3((uint32_t)nchunks),
                            dim3(t.block), lds, s, p, P, num, den, fb, acc, nchunks);
     }
     return hipGetLastError();
@@ -203,15 +203,23 @@ hipError_t raster_min_dispatch(const Pts &p, const Proj &P, uint64_t *fb, const 
                              : raster_min_vec<PPT, false>(p, P, fb, t, s);
 }
 
+template <int PPT, bool VEC, bool PW>
+hipError_t hq_accum_bin(const Pts &p, const Proj &P, uint32_t num, uint32_t den,
+                        const uint64_t *fb, uint64_t *acc, const Tune &t, hipStream_t s)
+{
+    switch (t.bin) {
+    case kBinBlock: return hq_accum_ppt<PPT, VEC, kBinBlock, PW>(p, P, num, den, fb, acc, t, s);
+    case kBinWave: return hq_accum_ppt<PPT, VEC, kBinWave, PW>(p, P, num, den, fb, acc, t, s);
+    default: return hq_accum_ppt<PPT, VEC, kBinNone, PW>(p, P, num, den, fb, acc, t, s);
+    }
+}
+
 template <int PPT, bool VEC>
 hipError_t hq_accum_vec(const Pts &p, const Proj &P, uint32_t num, uint32_t den,
                         const uint64_t *fb, uint64_t *acc, const Tune &t, hipStream_t s)
 {
-    switch (t.bin) {
-    case kBinBlock: return hq_accum_ppt<PPT, VEC, kBinBlock>(p, P, num, den, fb, acc, t, s);
-    case kBinWave: return hq_accum_ppt<PPT, VEC, kBinWave>(p, P, num, den, fb, acc, t, s);
-    default: return hq_accum_ppt<PPT, VEC, kBinNone>(p, P, num, den, fb, acc, t, s);
-    }
+    return P.nr ? hq_accum_bin<PPT, VEC, true>(p, P, num, den, fb, acc, t, s)
+                : hq_accum_bin<PPT, VEC, false>(p, P, num, den, fb, acc, t, s);
 }
 
 template <int PPT>

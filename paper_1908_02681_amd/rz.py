@@ -27,6 +27,7 @@ RZ_KEEP_KEYS = 1
 RZ_STATUS_HQ_OVERFLOW = 1
 DEPTH_LINEAR = 0
 DEPTH_SCALE = 1
+DEPTH_PIECEWISE = 2
 
 CLEAR_DEPTH = 0xFFFFFFFFFF000000
 
@@ -51,8 +52,12 @@ class rz_view(ctypes.Structure):
                 ("width", c_int32), ("height", c_int32)]
 
 
+RZ_MAX_RANGES = 8
+
+
 class rz_depth_map(ctypes.Structure):
-    _fields_ = [("kind", c_int32), ("scale", c_double)]
+    _fields_ = [("kind", c_int32), ("scale", c_double), ("nranges", c_int32),
+                ("range_start", c_double * RZ_MAX_RANGES), ("range_scale", c_double * RZ_MAX_RANGES)]
 
 
 class rz_hq_params(ctypes.Structure):
@@ -245,7 +250,19 @@ def view_struct(view) -> rz_view:
 
 
 def depth_struct(kind=DEPTH_LINEAR, scale=0.0) -> rz_depth_map:
-    return rz_depth_map(int(kind), float(scale))
+    """LINEAR / SCALE (scale a number) or PIECEWISE with
+    scale = ((start_0, values_per_unit_0), (start_1, values_per_unit_1), ...)."""
+    d = rz_depth_map()
+    d.kind = int(kind)
+    if int(kind) == DEPTH_PIECEWISE:
+        r = list(scale)
+        d.nranges = len(r)
+        for k, (b, sc) in enumerate(r[:RZ_MAX_RANGES]):
+            d.range_start[k] = float(b)
+            d.range_scale[k] = float(sc)
+    else:
+        d.scale = float(scale)
+    return d
 
 
 def _npix(view):
@@ -344,7 +361,7 @@ def hq_accumulate(points: Points, view, fb, acc, depth=None, eps=(1, 100), strea
     return acc
 
 
-def set_launch(block=256, ppt=16, early_out=1, xcd_remap=1, bin=1):
+def set_launch(block=64, ppt=16, early_out=1, xcd_remap=0, bin=2):
     """Launch shape of the point kernels (defaults = the library's)."""
     _check(load().rz_set_launch(ctypes.byref(rz_launch(block, ppt, early_out, xcd_remap, bin))),
            "rz_set_launch")
@@ -389,7 +406,7 @@ class Batch:
     """Many views of one resident cloud (rz_batch_* in include/rz.h).
 
     views: objects with vp, near, far, width, height; modes: RZ_MODE_* per
-    view.  Allocates (torch) and clears each view's fb / acc / img once; the
+    view; depth: one depth map for all views, or a list with one per view.  Allocates (torch) and clears each view's fb / acc / img once; the
     library owns only its view table and graph.  Every run renders all views
     and leaves fb/acc cleared again."""
 
@@ -407,8 +424,15 @@ class Batch:
         self.backgrounds = bgs
         self.fbs, self.accs, self.imgs = [], [], []
         arr = (rz_batch_view * n)()
-        ds = depth if isinstance(depth, rz_depth_map) else depth_struct(*(depth or (DEPTH_LINEAR, 0.0)))
+
+        def as_struct(d):
+            return d if isinstance(d, rz_depth_map) else depth_struct(*(d or (DEPTH_LINEAR, 0.0)))
+        per_view = isinstance(depth, list)
+        if per_view and len(depth) != n:
+            raise RzError(RZ_EINVAL, "one depth map per view")
+        ds_all = [as_struct(d) for d in depth] if per_view else [as_struct(depth)] * n
         for i, (v, m) in enumerate(zip(self.views, self.modes)):
+            ds = ds_all[i]
             fb, acc = new_framebuffer(v, bgs[i], hq=(m == RZ_MODE_HQ))
             img = torch.empty(_npix(v), dtype=torch.int32, device="cuda")
             self.fbs.append(fb)

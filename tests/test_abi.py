@@ -92,6 +92,14 @@ def test_argument_validation(rz):
     assert _call_min(rz, depth=(1, -1.0)) == E.RZ_EINVAL                           # scale <= 0
     # millimetres up to 1e9 m fit 40 bits; 1.1e9 m do not (section 2.1)
     assert _call_min(rz, view=_View(far=1.2e9), depth=(1, 1000.0)) == E.RZ_EDEPTHRANGE
+    # piecewise: starts must increase, the first must not lie beyond near,
+    # and the last range must reach far inside 40 bits
+    pw = ((0.0, 1e9), (10.0, 1e6), (1e4, 1e3))
+    assert _call_min(rz, view=_View(near=0.5), depth=(2, ((1.0, 1e3),))) == E.RZ_EINVAL
+    assert _call_min(rz, view=_View(far=5.0), depth=(2, ((0.0, 1e3), (0.0, 1e3)))) == E.RZ_EINVAL
+    assert _call_min(rz, view=_View(far=5.0), depth=(2, ((0.0, -1.0),))) == E.RZ_EINVAL
+    assert _call_min(rz, view=_View(far=5.0), depth=(2, ())) == E.RZ_EINVAL
+    assert _call_min(rz, view=_View(far=2e9), depth=(2, pw)) == E.RZ_EDEPTHRANGE
     assert _call_min(rz, fb=0) == E.RZ_EINVAL
     assert _call_min(rz, img=0) == E.RZ_EINVAL                                     # img needed
     assert _call_min(rz, flags=2) == E.RZ_EINVAL

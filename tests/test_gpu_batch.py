@@ -152,3 +152,27 @@ def test_batch_status_flags_overflow(rz):
     assert int(status.item()) & rz.RZ_STATUS_HQ_OVERFLOW
     assert b.images()[1][3] == 0x00FF00
     b.close()
+
+
+def test_batch_mixed_depth_maps(rz, oracle, scene):
+    """Linear and piecewise views in one batch (one splatting kernel serves
+    both kinds): each view equals its oracle image."""
+    import torch
+    cloud, views, modes, bgs = scene
+    pw = (2, ((0.0, 1.0e9), (10.0, 1.0e6), (1.0e4, 1.0e3)))
+    lin = (0, 0.0)
+    depths = [pw if i % 2 else lin for i in range(len(views))]
+    ms = [1, 1, 0, 1, 1, 0, 1, 1, 0, 1, 1][:len(views)]
+    pts = rz.Points.from_cloud(cloud)
+    b = rz.Batch(pts, views, ms, depth=depths, backgrounds=bgs)
+    b.run()
+    torch.cuda.synchronize()
+    for got, v, m, bg, dm in zip(b.images(), views, ms, bgs, depths):
+        if m == 0:
+            _, want = oracle.render_atomicmin(cloud.x, cloud.y, cloud.z, cloud.rgb, v.vp, v.near,
+                                              v.far, v.width, v.height, dm[0], dm[1], bg)
+        else:
+            _, _, want = oracle.render_hq(cloud.x, cloud.y, cloud.z, cloud.rgb, v.vp, v.near,
+                                          v.far, v.width, v.height, dm[0], dm[1], bg=bg)
+        assert np.array_equal(got, want)
+    b.close()

@@ -112,6 +112,35 @@ def test_config1_spheres(rz, oracle):
     check_scene(rz, oracle, cloud, view, label="1M spheres 1024x768")
 
 
+PAPER_RANGES = ((0.0, 1.0e9), (10.0, 1.0e6), (1.0e4, 1.0e3))   # nm, um, mm (section 2.1)
+
+
+@pytest.mark.parametrize("which", ["spheres", "terrain"])
+def test_piecewise_depth_map(rz, oracle, which):
+    if which == "spheres":
+        cloud, view = gen.config1(n=400_000)
+    else:
+        cloud = gen.terrain(2_000_000, 6)
+        view = gen.terrain_view(640, 360)
+    check_scene(rz, oracle, cloud, view, depth=(2, PAPER_RANGES), label=f"piecewise {which}")
+
+
+def test_piecewise_window_across_ranges(rz, oracle):
+    """Fragments straddling the 10 m range boundary: the GPU's window test in
+    linear depth equals the oracle's (hand-worked values in the oracle pins)."""
+    rng = np.random.default_rng(4)
+    n = 20000
+    z = -rng.uniform(9.9, 10.1, n).astype(np.float32)
+    x = (rng.integers(0, 4, n) * 0.5 - 0.75).astype(np.float32)
+    y = (rng.integers(0, 4, n) * 0.5 - 0.75).astype(np.float32)
+    vp = np.zeros((4, 4))
+    vp[0, 0] = vp[1, 1] = 10.0
+    vp[3, 2] = -1.0
+    cloud = gen.Cloud(x * 1.0, y * 1.0, z, rng.integers(0, 1 << 24, n, dtype=np.uint32))
+    view = gen.View(vp, 0.25, 1.0e7, 8, 8)
+    check_scene(rz, oracle, cloud, view, depth=(2, PAPER_RANGES), label="window across ranges")
+
+
 def test_background_and_scale_map(rz, oracle):
     cloud, view = gen.config1(n=300_000)
     check_scene(rz, oracle, cloud, view, depth=(1, 1000.0), bg=0x3A2B1C, label="mm map, bg")
