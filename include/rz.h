@@ -166,6 +166,29 @@ int rasterize_hq_splat(const rz_points *pts, const rz_view *view,
                        void *stream);
 
 /*
+ * Screen-sorted rendering, for clouds in no particular order (the paper
+ * notes that shuffled points make the atomicMin method slower, section 3).
+ * Same results as rasterize_atomicmin (hq == NULL) or rasterize_hq_splat
+ * (hq != NULL), bit for bit, computed differently: the fragments are first
+ * counted and scattered into buckets per 32x32 screen tile (a counting
+ * sort), then each tile is reduced in LDS and merged into fb (and acc) with
+ * one coalesced atomic per pixel; the splat sums are taken straight from
+ * the buckets, without a second projection.
+ *   workspace    device memory of at least
+ *                rz_sorted_workspace_bytes(pts->n, width, height) bytes,
+ *                owned by the caller, 256-byte aligned; its contents on entry
+ *                do not matter.
+ *   Limits: ceil(width / 32) * ceil(height / 32) <= 8192 tiles (e.g. up to
+ *   3840x2160), else RZ_EINVAL.  Other arguments as for the one-view calls.
+ */
+int64_t rz_sorted_workspace_bytes(int64_t n, int32_t width, int32_t height);
+int rasterize_sorted(const rz_points *pts, const rz_view *view,
+                     const rz_depth_map *depth, const rz_hq_params *hq,
+                     uint32_t background, uint64_t *fb, uint64_t *acc,
+                     uint32_t *img, uint32_t *status, void *workspace,
+                     int64_t workspace_bytes, uint32_t flags, void *stream);
+
+/*
  * Building blocks (section 2.1 resolve, section 2.2 third pass).
  * rz_clear: fb[p] = 0xffffffffff000000 | (background & 0xffffff) for
  *   p < npix, and acc[0 .. 2*npix) = 0 when acc is not NULL.

@@ -111,6 +111,10 @@ SIGNATURES = {
     "rasterize_hq_splat": ([P(rz_points), P(rz_view), P(rz_depth_map), P(rz_hq_params), c_uint32,
                             c_void_p, c_void_p, c_void_p, c_void_p, c_uint32, c_void_p],
                            ctypes.c_int),
+    "rz_sorted_workspace_bytes": ([c_int64, c_int32, c_int32], c_int64),
+    "rasterize_sorted": ([P(rz_points), P(rz_view), P(rz_depth_map), P(rz_hq_params), c_uint32,
+                          c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_uint32,
+                          c_void_p], ctypes.c_int),
     "rz_clear": ([c_void_p, c_void_p, c_int64, c_uint32, c_void_p], ctypes.c_int),
     "rz_hq_accumulate": ([P(rz_points), P(rz_view), P(rz_depth_map), P(rz_hq_params), c_void_p,
                           c_void_p, c_void_p], ctypes.c_int),
@@ -359,6 +363,51 @@ def hq_accumulate(points: Points, view, fb, acc, depth=None, eps=(1, 100), strea
                                    ctypes.byref(hq), _ptr(fb), _ptr(acc), _stream(stream)),
            "rz_hq_accumulate")
     return acc
+
+
+def sorted_workspace_bytes(n: int, width: int, height: int) -> int:
+    """Workspace the screen-sorted path needs for n points at width x height."""
+    b = load().rz_sorted_workspace_bytes(int(n), int(width), int(height))
+    if b < 0:
+        raise RzError(RZ_EINVAL, "rz_sorted_workspace_bytes: invalid size")
+    return b
+
+
+def new_workspace(n: int, width: int, height: int):
+    """Device workspace (256-byte aligned) for rasterize_sorted."""
+    torch = _torch()
+    nbytes = max(sorted_workspace_bytes(n, width, height), 256)
+    return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+
+def rasterize_sorted(points: Points, view, depth=None, hq=False, eps=(1, 100), background=0,
+                     fb=None, acc=None, img=None, status=None, workspace=None, keep_keys=False,
+                     stream=None):
+    """Screen-sorted rendering: the images of rasterize_atomicmin (hq=False)
+    or rasterize_hq_splat (hq=True), bit for bit, through a counting sort of
+    the fragments by screen tile.  Returns (fb, acc, img, status); acc and
+    status are None without hq."""
+    torch = _torch()
+    _require_gpu(points.x, fb, acc, img, status, workspace)
+    if fb is None or (hq and acc is None):
+        fb, acc = new_framebuffer(view, background, hq=hq, stream=stream)
+    if img is None and not keep_keys:
+        img = torch.empty(_npix(view), dtype=torch.int32, device="cuda")
+    if hq and status is None:
+        status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    if workspace is None:
+        workspace = new_workspace(points.n, view.width, view.height)
+    ps, vs = points.struct(), view_struct(view)
+    ds = depth if isinstance(depth, rz_depth_map) else depth_struct(*(depth or (DEPTH_LINEAR, 0.0)))
+    hp = ctypes.byref(rz_hq_params(int(eps[0]), int(eps[1]))) if hq else None
+    rc = load().rasterize_sorted(ctypes.byref(ps), ctypes.byref(vs), ctypes.byref(ds), hp,
+                                 int(background) & 0xFFFFFFFF, _ptr(fb),
+                                 _ptr(acc) if hq else None, None if keep_keys else _ptr(img),
+                                 _ptr(status) if hq else None, _ptr(workspace),
+                                 workspace.numel() * workspace.element_size(),
+                                 RZ_KEEP_KEYS if keep_keys else 0, _stream(stream))
+    _check(rc, "rasterize_sorted")
+    return fb, (acc if hq else None), (None if keep_keys else img), (status if hq else None)
 
 
 def set_launch(block=64, ppt=16, early_out=1, xcd_remap=0, bin=2):

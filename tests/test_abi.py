@@ -36,7 +36,7 @@ def declared_functions():
 def test_header_declares_the_entry_points():
     names = declared_functions()
     for n in ("rasterize_atomicmin", "rasterize_hq_splat", "rz_clear", "rz_resolve_min",
-              "rz_resolve_hq", "rz_error_string"):
+              "rz_resolve_hq", "rz_error_string", "rasterize_sorted", "rz_sorted_workspace_bytes"):
         assert n in names
 
 
@@ -122,6 +122,35 @@ def test_argument_validation(rz):
     assert lib.rz_resolve_min(ctypes.c_void_p(1), 4, 0, None, None) == E.RZ_EINVAL
     assert lib.rz_resolve_hq(ctypes.c_void_p(1), None, 4, 0, ctypes.c_void_p(1), None,
                              None) == E.RZ_EINVAL
+
+
+def test_sorted_path_validation(rz):
+    """Workspace sizes and the checks made before any launch."""
+    lib = rz.load()
+    assert lib.rz_sorted_workspace_bytes(-1, 64, 48) == -1
+    assert lib.rz_sorted_workspace_bytes(10, 0, 48) == -1
+    small = lib.rz_sorted_workspace_bytes(0, 64, 48)
+    big = lib.rz_sorted_workspace_bytes(1_000_000, 64, 48)
+    assert small >= 0 and small % 256 == 0 and big % 256 == 0
+    assert big >= small + 10 * 1_000_000      # 8-byte key and 2-byte pixel per fragment
+    ps, ds = rz.rz_points(1, 1, 1, 1, 10), rz.depth_struct()
+    need = lib.rz_sorted_workspace_bytes(10, 64, 48)
+
+    def call(view=None, ws=256 * 4096, ws_bytes=None, hq=None, fb=1, acc=1, img=1):
+        vs = rz.view_struct(view or _View())
+        return lib.rasterize_sorted(ctypes.byref(ps), ctypes.byref(vs), ctypes.byref(ds),
+                                    hq and ctypes.byref(hq), 0, fb and ctypes.c_void_p(fb),
+                                    acc and ctypes.c_void_p(acc), img and ctypes.c_void_p(img),
+                                    None, ws and ctypes.c_void_p(ws),
+                                    need if ws_bytes is None else ws_bytes, 0, None)
+    E = rz.RZ_EINVAL
+    assert call(view=_View(w=3872, h=2176)) == E            # 121 x 68 tiles > 8192
+    assert call(ws=0) == E                                   # no workspace
+    assert call(ws=256 * 4096 + 8) == E                      # not 256-byte aligned
+    assert call(ws_bytes=need - 1) == E                      # too small
+    assert call(hq=rz.rz_hq_params(1, 100), acc=0) == E      # splatting needs acc
+    assert call(hq=rz.rz_hq_params(1, 0)) == E
+    assert call(fb=0) == E and call(img=0) == E
 
 
 def test_launch_shape_validation(rz):
