@@ -7,9 +7,9 @@
 //      k_sort_scan     exclusive scan of the totals (bucket starts)
 //   C  k_sort_scatter  same fragments again: key and in-tile pixel into the
 //                      tile's bucket at an LDS cursor
-//   D  k_sort_raster   per tile (slice): LDS min, one coalesced global
-//                      atomic per touched pixel
-//   E  k_sort_accum    per tile (slice): eps window against the finished
+//   D  k_sort_raster   per chunk of a tile's bucket: LDS min, one coalesced
+//                      global atomic per touched pixel
+//   E  k_sort_accum    per chunk of a tile's bucket: eps window against the finished
 //                      depth pass, LDS sums, one flush per pixel
 // Every step is a minimum or an integer sum, so the result is the oracle's
 // bit for bit regardless of the order in which fragments land.
@@ -37,15 +37,17 @@ constexpr int kMaxTiles = 8192;               // LDS histogram: 32 KiB
 constexpr int kGroups = 1024;                 // workgroups of passes A and C
 constexpr int kSortBlock = 256;
 constexpr int kSortPpt = 8;
-constexpr int64_t kSliceFrags = 32768;        // fragments per tile slice (D, E)
-constexpr int kMaxSlices = 64;
+constexpr uint32_t kChunk = 8192;             // fragments per workgroup in passes D, E
+constexpr int kPrefixTiles = 32;              // pass B: tiles per workgroup
+constexpr int kPrefixSegs = 32;               // pass B: workgroup segments per tile
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 struct Layout {
-    int32_t ntx = 0, nty = 0, ntiles = 0, groups = 0, slices = 1;
+    int32_t ntx = 0, nty = 0, ntiles = 0, groups = 0;
     int64_t per_wg = 0;
-    size_t counts = 0, total = 0, start = 0, keys = 0, lps = 0, bytes = 0;
+    int64_t chunks_max = 0;   // bound on the chunks of passes D and E
+    size_t counts = 0, total = 0, start = 0, cstart = 0, keys = 0, lps = 0, bytes = 0;
 };
 
 Layout layout(int64_t n, int32_t w, int32_t h)
@@ -60,12 +62,13 @@ Layout layout(int64_t n, int32_t w, int32_t h)
         L.per_wg = (want + chunk - 1) / chunk * chunk;
         L.groups = (int32_t)((n + L.per_wg - 1) / L.per_wg);
     }
-    int64_t sl = (n + (int64_t)L.ntiles * kSliceFrags - 1) / ((int64_t)L.ntiles * kSliceFrags);
-    L.slices = (int32_t)(sl < 1 ? 1 : (sl > kMaxSlices ? kMaxSlices : sl));
+    // sum over tiles of ceil(count / kChunk) <= n / kChunk + ntiles
+    L.chunks_max = (n + kChunk - 1) / kChunk + L.ntiles;
     L.counts = 0;
     L.total = align256(L.counts + (size_t)L.groups * L.ntiles * 4);
     L.start = align256(L.total + (size_t)L.ntiles * 4);
-    L.keys = align256(L.start + ((size_t)L.ntiles + 1) * 4);
+    L.cstart = align256(L.start + ((size_t)L.ntiles + 1) * 4);
+    L.keys = align256(L.cstart + ((size_t)L.ntiles + 1) * 4);
     L.lps = align256(L.keys + (size_t)n * 8);
     L.bytes = align256(L.lps + (size_t)n * 2);
     return L;
@@ -105,53 +108,91 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_count(Pts p, Proj P, uint32
 
 // Pass B, first half: per tile, each workgroup's offset inside the tile's
 // bucket (exclusive prefix over workgroups, in place) and the tile total.
-__global__ void __launch_bounds__(256) k_sort_prefix(uint32_t *counts, int32_t groups,
-                                                     int32_t ntiles, uint32_t *total)
+// A workgroup takes kPrefixTiles tiles; each of its kPrefixSegs segments
+// sums a run of up to kPrefixSegs workgroups, the segment sums are scanned
+// in LDS, and the segments write their offsets.  groups <= 1024.
+__global__ void __launch_bounds__(kPrefixTiles * kPrefixSegs)
+    k_sort_prefix(uint32_t *counts, int32_t groups, int32_t ntiles, uint32_t *total)
 {
-    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntiles)
-        return;
-    uint32_t s = 0;
-    for (int32_t g = 0; g < groups; ++g) {
-        const int64_t i = (int64_t)g * ntiles + t;
-        const uint32_t c = counts[i];
-        counts[i] = s;
-        s += c;
+    __shared__ uint32_t s_seg[kPrefixSegs][kPrefixTiles];
+    const int tt = threadIdx.x % kPrefixTiles, seg = threadIdx.x / kPrefixTiles;
+    const int32_t t = blockIdx.x * kPrefixTiles + tt;
+    const bool on = t < ntiles;
+    const int32_t g0 = seg * kPrefixSegs;
+    uint32_t c[kPrefixSegs];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPrefixSegs; ++k) {
+        const int32_t g = g0 + k;
+        c[k] = on && g < groups ? counts[(int64_t)g * ntiles + t] : 0u;
+        sum += c[k];
     }
-    total[t] = s;
+    s_seg[seg][tt] = sum;
+    __syncthreads();
+    if (seg == 0) {   // exclusive scan over the segments of tile tt
+        uint32_t run = 0;
+        for (int k = 0; k < kPrefixSegs; ++k) {
+            const uint32_t v = s_seg[k][tt];
+            s_seg[k][tt] = run;
+            run += v;
+        }
+        if (on)
+            total[t] = run;
+    }
+    __syncthreads();
+    uint32_t run = s_seg[seg][tt];
+#pragma unroll
+    for (int k = 0; k < kPrefixSegs; ++k) {
+        const int32_t g = g0 + k;
+        if (on && g < groups)
+            counts[(int64_t)g * ntiles + t] = run;
+        run += c[k];
+    }
 }
 
-// Pass B, second half: bucket starts = exclusive scan of the tile totals
-// (one workgroup of 1024 threads, 8 tiles each); start[ntiles] = all.
+// Pass B, second half: bucket starts = exclusive scan of the tile totals,
+// and chunk starts = exclusive scan of ceil(total / kChunk) (the work items
+// of passes D and E); start[ntiles] and cstart[ntiles] are the sums.  One
+// workgroup of 1024 threads, 8 tiles each.
 __global__ void __launch_bounds__(1024) k_sort_scan(const uint32_t *total, uint32_t *start,
-                                                    int32_t ntiles)
+                                                    uint32_t *cstart, int32_t ntiles)
 {
-    __shared__ uint32_t s_sum[1024];
+    __shared__ uint32_t s_sum[1024], s_ch[1024];
     const int32_t t0 = threadIdx.x * 8;
     uint32_t v[8];
-    uint32_t local = 0;
+    uint32_t local = 0, lch = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         v[k] = t0 + k < ntiles ? total[t0 + k] : 0u;
         local += v[k];
+        lch += (v[k] + kChunk - 1) / kChunk;
     }
     s_sum[threadIdx.x] = local;
+    s_ch[threadIdx.x] = lch;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {   // inclusive scan (Hillis-Steele)
-        const uint32_t add = threadIdx.x >= (uint32_t)off ? s_sum[threadIdx.x - off] : 0u;
+    for (int off = 1; off < 1024; off <<= 1) {   // inclusive scans (Hillis-Steele)
+        const bool has = threadIdx.x >= (uint32_t)off;
+        const uint32_t add = has ? s_sum[threadIdx.x - off] : 0u;
+        const uint32_t addc = has ? s_ch[threadIdx.x - off] : 0u;
         __syncthreads();
         s_sum[threadIdx.x] += add;
+        s_ch[threadIdx.x] += addc;
         __syncthreads();
     }
-    uint32_t run = s_sum[threadIdx.x] - local;
+    uint32_t run = s_sum[threadIdx.x] - local, runc = s_ch[threadIdx.x] - lch;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        if (t0 + k < ntiles)
+        if (t0 + k < ntiles) {
             start[t0 + k] = run;
+            cstart[t0 + k] = runc;
+        }
         run += v[k];
+        runc += (v[k] + kChunk - 1) / kChunk;
     }
-    if (threadIdx.x == 1023)
+    if (threadIdx.x == 1023) {
         start[ntiles] = s_sum[1023];
+        cstart[ntiles] = s_ch[1023];
+    }
 }
 
 // Pass C: the same fragments as pass A (same range, same arithmetic), each
@@ -194,37 +235,67 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_scatter(Pts p, Proj P,
     }
 }
 
-// The slice [lo, hi) of tile t's bucket handled by this workgroup.
-__device__ __forceinline__ void slice_of(const uint32_t *start, int32_t slices, int32_t &t,
-                                         uint32_t &lo, uint32_t &hi)
+// The chunk of this workgroup: tile t (the last tile whose first chunk is
+// at or before blockIdx.x) and the range [lo, hi) of its bucket, at most
+// kChunk fragments.  Workgroups beyond the last chunk get lo >= hi.
+__device__ __forceinline__ void chunk_of(const uint32_t *start, const uint32_t *cstart,
+                                         int32_t ntiles, int32_t &t, uint32_t &lo, uint32_t &hi)
 {
-    t = blockIdx.x / slices;
-    const uint32_t s = blockIdx.x % slices;
-    const uint32_t b0 = start[t], b1 = start[t + 1];
-    const uint32_t per = (b1 - b0 + slices - 1) / slices;
-    lo = b0 + s * per;
-    hi = lo + per < b1 ? lo + per : b1;
+    const uint32_t b = blockIdx.x;
+    t = 0;
+    hi = lo = 0;
+    if (b >= cstart[ntiles])
+        return;
+    int32_t a = 0, z = ntiles;   // cstart[a] <= b < cstart[z]
+    while (z - a > 1) {
+        const int32_t m = (a + z) >> 1;
+        if (cstart[m] <= b)
+            a = m;
+        else
+            z = m;
+    }
+    t = a;
+    const uint32_t end = start[t + 1];
+    lo = start[t] + (b - cstart[t]) * kChunk;
+    hi = end - lo > kChunk ? lo + kChunk : end;
 }
 
-// Pass D: depth pass of one tile slice (section 2.1's minimum).
+constexpr int kUnroll = 4;   // bucket entries in flight per thread (D, E)
+
+// Pass D: depth pass of one chunk of a tile's bucket (section 2.1's minimum).
 __global__ void __launch_bounds__(256) k_sort_raster(const uint64_t *__restrict__ keys,
                                                      const uint16_t *__restrict__ lps,
                                                      const uint32_t *__restrict__ start,
+                                                     const uint32_t *__restrict__ cstart,
                                                      uint64_t *__restrict__ fb, int32_t ntx,
-                                                     int32_t width, int32_t slices)
+                                                     int32_t ntiles, int32_t width)
 {
     __shared__ uint64_t tile[kTilePix];
     int32_t t;
     uint32_t lo, hi;
-    slice_of(start, slices, t, lo, hi);
+    chunk_of(start, cstart, ntiles, t, lo, hi);
     if (lo >= hi)
         return;
     for (int i = threadIdx.x; i < kTilePix; i += blockDim.x)
         tile[i] = ~0ull;
     __syncthreads();
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
-        __hip_atomic_fetch_min(&tile[lps[i]], ldnt(keys + i), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kUnroll * blockDim.x) {
+        uint64_t k[kUnroll];
+        uint32_t l[kUnroll];
+        bool ok[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * blockDim.x;
+            ok[u] = i < hi;
+            k[u] = ok[u] ? ldnt(keys + i) : ~0ull;
+            l[u] = ok[u] ? lps[i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (ok[u])
+                __hip_atomic_fetch_min(&tile[l[u]], k[u], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
     __syncthreads();
     const uint32_t x0 = (uint32_t)(t % ntx) << kTileShift, y0 = (uint32_t)(t / ntx) << kTileShift;
     for (int l = threadIdx.x; l < kTilePix; l += blockDim.x) {
@@ -240,23 +311,23 @@ __global__ void __launch_bounds__(256) k_sort_raster(const uint64_t *__restrict_
     }
 }
 
-// Pass E: splat accumulation of one tile slice (section 2.2), from the
-// bucket's keys; fb holds the finished depth pass.
+// Pass E: splat accumulation of one chunk of a tile's bucket (section 2.2),
+// from the bucket's keys; fb holds the finished depth pass.
 template <bool PW>
 __global__ void __launch_bounds__(256) k_sort_accum(const uint64_t *__restrict__ keys,
                                                     const uint16_t *__restrict__ lps,
-                                                    const uint32_t *__restrict__ start, Proj P,
+                                                    const uint32_t *__restrict__ start,
+                                                    const uint32_t *__restrict__ cstart, Proj P,
                                                     uint32_t eps_num, uint32_t eps_den,
                                                     const uint64_t *__restrict__ fb,
                                                     uint64_t *__restrict__ acc, int32_t ntx,
-                                                    int32_t width, int32_t height,
-                                                    int32_t slices)
+                                                    int32_t ntiles, int32_t width, int32_t height)
 {
     __shared__ uint64_t qmin[kTilePix];
     __shared__ uint64_t sums[2 * kTilePix];
     int32_t t;
     uint32_t lo, hi;
-    slice_of(start, slices, t, lo, hi);
+    chunk_of(start, cstart, ntiles, t, lo, hi);
     if (lo >= hi)
         return;
     const uint32_t x0 = (uint32_t)(t % ntx) << kTileShift, y0 = (uint32_t)(t / ntx) << kTileShift;
@@ -268,23 +339,37 @@ __global__ void __launch_bounds__(256) k_sort_accum(const uint64_t *__restrict__
         sums[2 * l + 1] = 0ull;
     }
     __syncthreads();
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const uint64_t key = ldnt(keys + i);
-        const uint32_t l = lps[i];
-        if (in_window<PW>(P, eps_num, eps_den, key >> 24, qmin[l])) {
-            const uint32_t c = (uint32_t)(key & kRgbMask);
-            const uint64_t w0 = (uint64_t)(c & 0xFFu) | ((uint64_t)((c >> 8) & 0xFFu) << 32);
-            const uint64_t w1 = (uint64_t)((c >> 16) & 0xFFu) | (1ull << 32);
-            __hip_atomic_fetch_add(&sums[2 * l], w0, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_add(&sums[2 * l + 1], w1, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kUnroll * blockDim.x) {
+        uint64_t k[kUnroll];
+        uint32_t l[kUnroll];
+        bool ok[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * blockDim.x;
+            ok[u] = i < hi;
+            k[u] = ok[u] ? ldnt(keys + i) : 0ull;
+            l[u] = ok[u] ? lps[i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            ok[u] = ok[u] && in_window<PW>(P, eps_num, eps_den, k[u] >> 24, qmin[l[u]]);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (ok[u]) {
+                const uint32_t c = (uint32_t)(k[u] & kRgbMask);
+                const uint64_t w0 = (uint64_t)(c & 0xFFu) | ((uint64_t)((c >> 8) & 0xFFu) << 32);
+                const uint64_t w1 = (uint64_t)((c >> 16) & 0xFFu) | (1ull << 32);
+                __hip_atomic_fetch_add(&sums[2 * l[u]], w0, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(&sums[2 * l[u] + 1], w1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
         }
     }
     __syncthreads();
     for (int l = threadIdx.x; l < kTilePix; l += blockDim.x) {
         const uint64_t a1 = sums[2 * l + 1];
-        if (a1 != 0ull) {
+        if (a1 != 0ull) {   // count > 0 (at most kChunk), so the pixel is on screen
             uint64_t *dst = acc + 2 * ((uint64_t)(y0 + (l >> kTileShift)) * (uint32_t)width +
                                        x0 + (l & 31));
             __hip_atomic_fetch_add(dst, sums[2 * l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -299,6 +384,7 @@ hipError_t sort_passes(const Pts &p, const Proj &P, const Layout &L, char *ws, b
     uint32_t *counts = (uint32_t *)(ws + L.counts);
     uint32_t *total = (uint32_t *)(ws + L.total);
     uint32_t *start = (uint32_t *)(ws + L.start);
+    uint32_t *cstart = (uint32_t *)(ws + L.cstart);
     uint64_t *keys = (uint64_t *)(ws + L.keys);
     uint16_t *lps = (uint16_t *)(ws + L.lps);
     const size_t lds = (size_t)L.ntiles * sizeof(uint32_t);
@@ -311,9 +397,9 @@ hipError_t sort_passes(const Pts &p, const Proj &P, const Layout &L, char *ws, b
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_sort_prefix, dim3((L.ntiles + 255) / 256), dim3(256), 0, s, counts,
-                       L.groups, L.ntiles, total);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, total, start, L.ntiles);
+    hipLaunchKernelGGL(k_sort_prefix, dim3((L.ntiles + kPrefixTiles - 1) / kPrefixTiles),
+                       dim3(kPrefixTiles * kPrefixSegs), 0, s, counts, L.groups, L.ntiles, total);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, total, start, cstart, L.ntiles);
     if (vec)
         hipLaunchKernelGGL((k_sort_scatter<kSortPpt, true>), dim3(L.groups), dim3(kSortBlock),
                            lds, s, p, P, counts, start, keys, lps, L.ntx, L.ntiles, L.per_wg);
@@ -372,19 +458,22 @@ int rasterize_sorted(const rz_points *pts, const rz_view *view, const rz_depth_m
         const uint64_t *keys = (const uint64_t *)(ws + L.keys);
         const uint16_t *lps = (const uint16_t *)(ws + L.lps);
         const uint32_t *start = (const uint32_t *)(ws + L.start);
-        const dim3 grid((uint32_t)((int64_t)L.ntiles * L.slices));
+        const uint32_t *cstart = (const uint32_t *)(ws + L.cstart);
+        const dim3 grid((uint32_t)L.chunks_max);   // workgroups past the last chunk exit
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_sort_raster, grid, dim3(256), 0, s, keys, lps, start, fb, L.ntx,
-                               P.width, L.slices);
+            hipLaunchKernelGGL(k_sort_raster, grid, dim3(256), 0, s, keys, lps, start, cstart, fb,
+                               L.ntx, L.ntiles, P.width);
             e = hipGetLastError();
         }
         if (e == hipSuccess && hq) {
             if (P.nr)
                 hipLaunchKernelGGL((k_sort_accum<true>), grid, dim3(256), 0, s, keys, lps, start,
-                                   P, num, den, fb, acc, L.ntx, P.width, P.height, L.slices);
+                                   cstart, P, num, den, fb, acc, L.ntx, L.ntiles, P.width,
+                                   P.height);
             else
                 hipLaunchKernelGGL((k_sort_accum<false>), grid, dim3(256), 0, s, keys, lps, start,
-                                   P, num, den, fb, acc, L.ntx, P.width, P.height, L.slices);
+                                   cstart, P, num, den, fb, acc, L.ntx, L.ntiles, P.width,
+                                   P.height);
             e = hipGetLastError();
         }
     }
