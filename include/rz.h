@@ -170,16 +170,20 @@ int rasterize_hq_splat(const rz_points *pts, const rz_view *view,
  * notes that shuffled points make the atomicMin method slower, section 3).
  * Same results as rasterize_atomicmin (hq == NULL) or rasterize_hq_splat
  * (hq != NULL), bit for bit, computed differently: the fragments are first
- * counted and scattered into buckets per 32x32 screen tile (a counting
- * sort), then each tile is reduced in LDS and merged into fb (and acc) with
- * one coalesced atomic per pixel; the splat sums are taken straight from
- * the buckets, without a second projection.
+ * sorted into buckets per 32x32 screen tile (counted, then scattered in two
+ * levels: 256x256-pixel buckets, then tiles), then each tile is reduced in
+ * LDS and merged into fb (and acc) with one coalesced atomic per pixel; the
+ * splat sums are taken straight from the buckets, without a second
+ * projection.
  *   workspace    device memory of at least
- *                rz_sorted_workspace_bytes(pts->n, width, height) bytes,
- *                owned by the caller, 256-byte aligned; its contents on entry
- *                do not matter.
- *   Limits: ceil(width / 32) * ceil(height / 32) <= 8192 tiles (e.g. up to
- *   3840x2160), else RZ_EINVAL.  Other arguments as for the one-view calls.
+ *                rz_sorted_workspace_bytes(pts->n, width, height) bytes
+ *                (about 20 bytes per point), owned by the caller, 256-byte
+ *                aligned; its contents on entry do not matter.  May be NULL
+ *                when pts->n == 0.
+ *   Limits: ceil(width / 256) * ceil(height / 256) <= 256 (e.g. 4096x4096
+ *   or 7680x2160), else RZ_EINVAL; rz_sorted_workspace_bytes returns -1 for
+ *   such a screen or a negative size.  Other arguments and errors as for
+ *   the one-view calls.
  */
 int64_t rz_sorted_workspace_bytes(int64_t n, int32_t width, int32_t height);
 int rasterize_sorted(const rz_points *pts, const rz_view *view,

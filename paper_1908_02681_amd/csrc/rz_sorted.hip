@@ -1,18 +1,26 @@
 // Screen-sorted rendering (declared in include/rz.h): the same depth pass
 // (section 2.1) and splat accumulation (section 2.2) for clouds in no
 // particular order, where one global atomic per fragment would hit random
-// framebuffer lines.  A counting sort by 32x32 screen tile first:
-//   A  k_sort_count    per workgroup range: LDS histogram of fragment tiles
-//   B  k_sort_prefix   per tile: prefix over workgroups, tile totals
-//      k_sort_scan     exclusive scan of the totals (bucket starts)
-//   C  k_sort_scatter  same fragments again: key and in-tile pixel into the
-//                      tile's bucket at an LDS cursor
-//   D  k_sort_raster   per chunk of a tile's bucket: LDS min, one coalesced
-//                      global atomic per touched pixel
-//   E  k_sort_accum    per chunk of a tile's bucket: eps window against the finished
-//                      depth pass, LDS sums, one flush per pixel
-// Every step is a minimum or an integer sum, so the result is the oracle's
-// bit for bit regardless of the order in which fragments land.
+// framebuffer lines.  The fragments are first sorted by 32x32 screen tile in
+// two scatter levels, so that every write of the sort is part of a long run:
+//   A   k_sort_count   histogram of fragment tiles (LDS per workgroup, then
+//                      one global add per tile)
+//   B   k_sort_scan    tile bucket starts, coarse bucket starts and the
+//                      work lists of passes C2, D and E
+//   C1  k_sort_coarse  fragments again, each workgroup step ranks its 8192
+//                      points by coarse bucket (256x256 pixels) in LDS and
+//                      reserves one run per bucket: key + pixel in bucket
+//   C2  k_sort_fine    per chunk of a coarse bucket: the same into the 64
+//                      tile buckets it covers: key + pixel in tile
+//   D   k_sort_raster  per chunk of a tile bucket: LDS minimum, then one
+//                      coalesced global atomic per touched pixel
+//   E   k_sort_accum   per chunk of a tile bucket: eps window against the
+//                      finished depth pass, LDS sums, one flush per pixel
+// Tiles are numbered coarse bucket first ("slots"): slot = coarse * 64 +
+// 8 * (tile row in bucket) + (tile column in bucket), so a coarse bucket is
+// the contiguous union of its 64 tile buckets.  Every reduction is a
+// minimum or an integer sum, so the result is the oracle's bit for bit
+// whatever order the fragments land in.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -33,21 +41,25 @@ using namespace dev;
 
 constexpr int kTileShift = 5;                 // 32 x 32 pixel tiles
 constexpr int kTilePix = 1 << (2 * kTileShift);
-constexpr int kMaxTiles = 8192;               // LDS histogram: 32 KiB
-constexpr int kGroups = 1024;                 // workgroups of passes A and C
-constexpr int kSortBlock = 256;
-constexpr int kSortPpt = 8;
-constexpr uint32_t kChunk = 8192;             // fragments per workgroup in passes D, E
-constexpr int kPrefixTiles = 32;              // pass B: tiles per workgroup
-constexpr int kPrefixSegs = 32;               // pass B: workgroup segments per tile
+constexpr int kCoarseShift = 3;               // 8 x 8 tiles per coarse bucket
+constexpr int kSlotsPerCoarse = 1 << (2 * kCoarseShift);
+constexpr int kMaxCoarse = 256;
+constexpr int kMaxSlots = kMaxCoarse * kSlotsPerCoarse;   // pass A histogram: 64 KiB
+constexpr int kGroups = 512;                  // workgroups of passes A and C1
+constexpr int kSortBlock = 1024;
+constexpr int kSortPpt = 8;                   // 8192 points per workgroup step
+constexpr int kStep = kSortBlock * kSortPpt;
+constexpr uint32_t kChunk = 8192;             // bucket entries per work item (C2, D, E)
+constexpr int kUnroll = 4;                    // bucket entries in flight per thread (D, E)
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 struct Layout {
-    int32_t ntx = 0, nty = 0, ntiles = 0, groups = 0;
+    int32_t ntx = 0, nty = 0, ccols = 0, crows = 0, ncoarse = 0, nslots = 0, groups = 0;
     int64_t per_wg = 0;
-    int64_t chunks_max = 0;   // bound on the chunks of passes D and E
-    size_t counts = 0, total = 0, start = 0, cstart = 0, keys = 0, lps = 0, bytes = 0;
+    int64_t cchunks_max = 0, fchunks_max = 0;   // bounds on the work lists
+    size_t total = 0, fstart = 0, fchunk = 0, fcursor = 0, ccursor = 0, cchunk = 0;
+    size_t xkeys = 0, xlpc = 0, ykeys = 0, ylps = 0, bytes = 0;
 };
 
 Layout layout(int64_t n, int32_t w, int32_t h)
@@ -55,115 +67,142 @@ Layout layout(int64_t n, int32_t w, int32_t h)
     Layout L;
     L.ntx = (w + (1 << kTileShift) - 1) >> kTileShift;
     L.nty = (h + (1 << kTileShift) - 1) >> kTileShift;
-    L.ntiles = L.ntx * L.nty;
-    const int64_t chunk = (int64_t)kSortBlock * kSortPpt;
+    L.ccols = (L.ntx + (1 << kCoarseShift) - 1) >> kCoarseShift;
+    L.crows = (L.nty + (1 << kCoarseShift) - 1) >> kCoarseShift;
+    L.ncoarse = L.ccols * L.crows;
+    L.nslots = L.ncoarse * kSlotsPerCoarse;
     if (n > 0) {
         const int64_t want = (n + kGroups - 1) / kGroups;
-        L.per_wg = (want + chunk - 1) / chunk * chunk;
+        L.per_wg = (want + kStep - 1) / kStep * kStep;
         L.groups = (int32_t)((n + L.per_wg - 1) / L.per_wg);
     }
-    // sum over tiles of ceil(count / kChunk) <= n / kChunk + ntiles
-    L.chunks_max = (n + kChunk - 1) / kChunk + L.ntiles;
-    L.counts = 0;
-    L.total = align256(L.counts + (size_t)L.groups * L.ntiles * 4);
-    L.start = align256(L.total + (size_t)L.ntiles * 4);
-    L.cstart = align256(L.start + ((size_t)L.ntiles + 1) * 4);
-    L.keys = align256(L.cstart + ((size_t)L.ntiles + 1) * 4);
-    L.lps = align256(L.keys + (size_t)n * 8);
-    L.bytes = align256(L.lps + (size_t)n * 2);
+    // sum over buckets of ceil(count / kChunk) <= n / kChunk + buckets
+    L.cchunks_max = (n + kChunk - 1) / kChunk + L.ncoarse;
+    L.fchunks_max = (n + kChunk - 1) / kChunk + L.nslots;
+    size_t o = 0;
+    auto take = [&o](size_t bytes) {
+        const size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    L.total = take((size_t)L.nslots * 4);
+    L.fstart = take(((size_t)L.nslots + 1) * 4);
+    L.fchunk = take(((size_t)L.nslots + 1) * 4);
+    L.fcursor = take((size_t)L.nslots * 4);
+    L.ccursor = take((size_t)L.ncoarse * 4);
+    L.cchunk = take(((size_t)L.ncoarse + 1) * 4);
+    L.xkeys = take((size_t)n * 8);
+    L.xlpc = take((size_t)n * 2);
+    L.ykeys = take((size_t)n * 8);
+    L.ylps = take((size_t)n * 2);
+    L.bytes = o;
     return L;
 }
 
-// Pass A: number of fragments per screen tile in this workgroup's range.
-template <int PPT, bool VEC>
-__global__ void __launch_bounds__(kSortBlock) k_sort_count(Pts p, Proj P, uint32_t *counts,
-                                                           int32_t ntx, int32_t ntiles,
+// Slot of the tile holding pixel (px, py).
+__device__ __forceinline__ uint32_t slot_of(uint32_t px, uint32_t py, int32_t ccols)
+{
+    const uint32_t tx = px >> kTileShift, ty = py >> kTileShift;
+    const uint32_t c = (ty >> kCoarseShift) * (uint32_t)ccols + (tx >> kCoarseShift);
+    return (c << (2 * kCoarseShift)) | ((ty & 7u) << kCoarseShift) | (tx & 7u);
+}
+
+// First pixel of the tile of a slot.
+__device__ __forceinline__ void slot_origin(uint32_t slot, int32_t ccols, uint32_t &x0,
+                                            uint32_t &y0)
+{
+    const uint32_t c = slot >> (2 * kCoarseShift), f = slot & (kSlotsPerCoarse - 1);
+    const uint32_t tx = (c % (uint32_t)ccols) * 8u + (f & 7u);
+    const uint32_t ty = (c / (uint32_t)ccols) * 8u + (f >> kCoarseShift);
+    x0 = tx << kTileShift;
+    y0 = ty << kTileShift;
+}
+
+// Adds this lane's entry to the LDS counter hist[bin] and returns the
+// counter before it (the entry's rank among the workgroup's entries of that
+// bin).  A wave whose live lanes share one bin makes a single atomic.  Every
+// lane of the wave must call it.
+__device__ __forceinline__ uint32_t lds_rank(uint32_t *hist, uint32_t bin, bool live)
+{
+    const uint64_t m = __ballot(live);
+    if (m == 0)
+        return 0u;
+    const uint32_t below =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    const int leader = __builtin_ctzll(m);
+    const uint32_t b0 = __shfl(bin, leader);
+    if (__all(!live || bin == b0)) {
+        uint32_t base = 0;
+        if (live && below == 0)
+            base = atomicAdd(&hist[b0], (uint32_t)__popcll(m));
+        return __shfl(base, leader) + below;
+    }
+    return live ? atomicAdd(&hist[bin], 1u) : 0u;
+}
+
+__global__ void k_sort_zero(uint32_t *p, int32_t n)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0u;
+}
+
+// Pass A: fragments per tile.  Each workgroup takes a contiguous range of
+// points, counts in LDS and adds its non-zero counts to total[].
+template <bool VEC>
+__global__ void __launch_bounds__(kSortBlock) k_sort_count(Pts p, Proj P, uint32_t *total,
+                                                           int32_t ccols, int32_t nslots,
                                                            int64_t per_wg)
 {
     extern __shared__ uint32_t hist[];
-    for (int32_t i = threadIdx.x; i < ntiles; i += blockDim.x)
-        hist[i] = 0;
+    for (int32_t i = threadIdx.x; i < nslots; i += blockDim.x)
+        hist[i] = 0u;
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * per_wg;
     Pts q = p;
     q.n = lo + per_wg < p.n ? lo + per_wg : p.n;
-    for (int64_t base = lo; base < q.n; base += (int64_t)blockDim.x * PPT) {
-        float x[PPT], y[PPT], z[PPT];
-        uint32_t c[PPT];
-        bool in[PPT];
-        load_points<PPT, VEC>(q, base, x, y, z, c, in);
+    for (int64_t base = lo; base < q.n; base += kStep) {
+        float x[kSortPpt], y[kSortPpt], z[kSortPpt];
+        uint32_t c[kSortPpt];
+        bool in[kSortPpt];
+        load_points<kSortPpt, VEC>(q, base, x, y, z, c, in);
 #pragma unroll
-        for (int j = 0; j < PPT; ++j) {
+        for (int j = 0; j < kSortPpt; ++j) {
             uint32_t px = 0, py = 0;
             uint64_t qq = 0;
             const bool live = in[j] && fragment(P, x[j], y[j], z[j], px, py, qq);
-            if (live)
-                atomicAdd(&hist[(py >> kTileShift) * (uint32_t)ntx + (px >> kTileShift)], 1u);
+            lds_rank(hist, live ? slot_of(px, py, ccols) : 0u, live);
         }
     }
     __syncthreads();
-    for (int32_t i = threadIdx.x; i < ntiles; i += blockDim.x)
-        counts[(int64_t)blockIdx.x * ntiles + i] = hist[i];
-}
-
-// Pass B, first half: per tile, each workgroup's offset inside the tile's
-// bucket (exclusive prefix over workgroups, in place) and the tile total.
-// A workgroup takes kPrefixTiles tiles; each of its kPrefixSegs segments
-// sums a run of up to kPrefixSegs workgroups, the segment sums are scanned
-// in LDS, and the segments write their offsets.  groups <= 1024.
-__global__ void __launch_bounds__(kPrefixTiles * kPrefixSegs)
-    k_sort_prefix(uint32_t *counts, int32_t groups, int32_t ntiles, uint32_t *total)
-{
-    __shared__ uint32_t s_seg[kPrefixSegs][kPrefixTiles];
-    const int tt = threadIdx.x % kPrefixTiles, seg = threadIdx.x / kPrefixTiles;
-    const int32_t t = blockIdx.x * kPrefixTiles + tt;
-    const bool on = t < ntiles;
-    const int32_t g0 = seg * kPrefixSegs;
-    uint32_t c[kPrefixSegs];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < kPrefixSegs; ++k) {
-        const int32_t g = g0 + k;
-        c[k] = on && g < groups ? counts[(int64_t)g * ntiles + t] : 0u;
-        sum += c[k];
-    }
-    s_seg[seg][tt] = sum;
-    __syncthreads();
-    if (seg == 0) {   // exclusive scan over the segments of tile tt
-        uint32_t run = 0;
-        for (int k = 0; k < kPrefixSegs; ++k) {
-            const uint32_t v = s_seg[k][tt];
-            s_seg[k][tt] = run;
-            run += v;
-        }
-        if (on)
-            total[t] = run;
-    }
-    __syncthreads();
-    uint32_t run = s_seg[seg][tt];
-#pragma unroll
-    for (int k = 0; k < kPrefixSegs; ++k) {
-        const int32_t g = g0 + k;
-        if (on && g < groups)
-            counts[(int64_t)g * ntiles + t] = run;
-        run += c[k];
+    for (int32_t i = threadIdx.x; i < nslots; i += blockDim.x) {
+        const uint32_t v = hist[i];
+        if (v)
+            atomicAdd(&total[i], v);
     }
 }
 
-// Pass B, second half: bucket starts = exclusive scan of the tile totals,
-// and chunk starts = exclusive scan of ceil(total / kChunk) (the work items
-// of passes D and E); start[ntiles] and cstart[ntiles] are the sums.  One
-// workgroup of 1024 threads, 8 tiles each.
-__global__ void __launch_bounds__(1024) k_sort_scan(const uint32_t *total, uint32_t *start,
-                                                    uint32_t *cstart, int32_t ntiles)
+// Pass B: one workgroup of 1024 threads, 16 slots each (nslots <= 16384).
+//   fstart  exclusive scan of the tile totals (tile bucket starts), and
+//           fstart[nslots] = all fragments; fcursor = fstart;
+//   fchunk  exclusive scan of ceil(total / kChunk): work items of D and E;
+//   ccursor first entry of each coarse bucket (= fstart of its first slot);
+//   cchunk  exclusive scan of ceil(coarse total / kChunk): work items of C2.
+__global__ void __launch_bounds__(1024) k_sort_scan(const uint32_t *total, uint32_t *fstart,
+                                                    uint32_t *fchunk, uint32_t *fcursor,
+                                                    uint32_t *ccursor, uint32_t *cchunk,
+                                                    int32_t nslots, int32_t ncoarse)
 {
+    constexpr int K = kMaxSlots / 1024;
+    static_assert(kSlotsPerCoarse % K == 0, "a coarse bucket spans whole threads");
+    constexpr int kThreadsPerCoarse = kSlotsPerCoarse / K;
     __shared__ uint32_t s_sum[1024], s_ch[1024];
-    const int32_t t0 = threadIdx.x * 8;
-    uint32_t v[8];
+    const int32_t t0 = threadIdx.x * K;
+    uint32_t v[K];
     uint32_t local = 0, lch = 0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        v[k] = t0 + k < ntiles ? total[t0 + k] : 0u;
+    for (int k = 0; k < K; ++k) {
+        v[k] = t0 + k < nslots ? total[t0 + k] : 0u;
         local += v[k];
         lch += (v[k] + kChunk - 1) / kChunk;
     }
@@ -181,99 +220,194 @@ __global__ void __launch_bounds__(1024) k_sort_scan(const uint32_t *total, uint3
     }
     uint32_t run = s_sum[threadIdx.x] - local, runc = s_ch[threadIdx.x] - lch;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        if (t0 + k < ntiles) {
-            start[t0 + k] = run;
-            cstart[t0 + k] = runc;
+    for (int k = 0; k < K; ++k) {
+        if (t0 + k < nslots) {
+            fstart[t0 + k] = run;
+            fcursor[t0 + k] = run;
+            fchunk[t0 + k] = runc;
         }
         run += v[k];
         runc += (v[k] + kChunk - 1) / kChunk;
     }
     if (threadIdx.x == 1023) {
-        start[ntiles] = s_sum[1023];
-        cstart[ntiles] = s_ch[1023];
+        fstart[nslots] = s_sum[1023];
+        fchunk[nslots] = s_ch[1023];
     }
+    // coarse buckets: s_sum holds the inclusive sums per thread
+    uint32_t cn = 0;
+    if ((int32_t)threadIdx.x < ncoarse) {
+        const int32_t last = kThreadsPerCoarse * threadIdx.x + kThreadsPerCoarse - 1;
+        const uint32_t end = s_sum[last];
+        const uint32_t beg = threadIdx.x ? s_sum[last - kThreadsPerCoarse] : 0u;
+        ccursor[threadIdx.x] = beg;
+        cn = (end - beg + kChunk - 1) / kChunk;
+    }
+    __syncthreads();
+    s_ch[threadIdx.x] = cn;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t addc = threadIdx.x >= (uint32_t)off ? s_ch[threadIdx.x - off] : 0u;
+        __syncthreads();
+        s_ch[threadIdx.x] += addc;
+        __syncthreads();
+    }
+    if ((int32_t)threadIdx.x < ncoarse)
+        cchunk[threadIdx.x] = s_ch[threadIdx.x] - cn;
+    if (threadIdx.x == 1023)
+        cchunk[ncoarse] = s_ch[1023];
 }
 
-// Pass C: the same fragments as pass A (same range, same arithmetic), each
-// written to its tile's bucket: the key, and the pixel inside the tile.
-template <int PPT, bool VEC>
-__global__ void __launch_bounds__(kSortBlock) k_sort_scatter(Pts p, Proj P,
-                                                             const uint32_t *counts,
-                                                             const uint32_t *start,
-                                                             uint64_t *keys, uint16_t *lps,
-                                                             int32_t ntx, int32_t ntiles,
-                                                             int64_t per_wg)
+// Pass C1: the fragments of pass A again (same ranges, same arithmetic).
+// Each step of 8192 points is ranked per coarse bucket in LDS; one global
+// atomic per bucket reserves the step's run, written contiguously.
+template <bool VEC>
+__global__ void __launch_bounds__(kSortBlock) k_sort_coarse(Pts p, Proj P, uint32_t *ccursor,
+                                                            uint64_t *xkeys, uint16_t *xlpc,
+                                                            int32_t ccols, int32_t ncoarse,
+                                                            int64_t per_wg)
 {
-    extern __shared__ uint32_t cursor[];
-    for (int32_t i = threadIdx.x; i < ntiles; i += blockDim.x)
-        cursor[i] = start[i] + counts[(int64_t)blockIdx.x * ntiles + i];
-    const uint32_t end = start[ntiles];
-    __syncthreads();
+    __shared__ uint32_t s_cnt[kMaxCoarse], s_base[kMaxCoarse];
+    const uint64_t end = (uint64_t)p.n;   // bucket arrays hold n entries
     const int64_t lo = (int64_t)blockIdx.x * per_wg;
     Pts q = p;
     q.n = lo + per_wg < p.n ? lo + per_wg : p.n;
-    for (int64_t base = lo; base < q.n; base += (int64_t)blockDim.x * PPT) {
-        float x[PPT], y[PPT], z[PPT];
-        uint32_t c[PPT];
-        bool in[PPT];
-        load_points<PPT, VEC>(q, base, x, y, z, c, in);
+    for (int64_t base = lo; base < q.n; base += kStep) {
+        if ((int32_t)threadIdx.x < ncoarse)
+            s_cnt[threadIdx.x] = 0u;
+        __syncthreads();
+        float x[kSortPpt], y[kSortPpt], z[kSortPpt];
+        uint32_t c[kSortPpt];
+        bool in[kSortPpt];
+        load_points<kSortPpt, VEC>(q, base, x, y, z, c, in);
+        uint64_t key[kSortPpt];
+        uint32_t cb[kSortPpt], lpc[kSortPpt], rank[kSortPpt];
+        bool live[kSortPpt];
 #pragma unroll
-        for (int j = 0; j < PPT; ++j) {
+        for (int j = 0; j < kSortPpt; ++j) {
             uint32_t px = 0, py = 0;
             uint64_t qq = 0;
-            const bool live = in[j] && fragment(P, x[j], y[j], z[j], px, py, qq);
-            if (live) {
-                const uint32_t tile = (py >> kTileShift) * (uint32_t)ntx + (px >> kTileShift);
-                const uint32_t pos = atomicAdd(&cursor[tile], 1u);
-                if (pos >= end)   // unreachable: passes A and C see the same fragments
-                    continue;
-                keys[pos] = (qq << 24) | ((uint64_t)c[j] & kRgbMask);
-                lps[pos] = (uint16_t)(((py & 31u) << kTileShift) | (px & 31u));
+            live[j] = in[j] && fragment(P, x[j], y[j], z[j], px, py, qq);
+            key[j] = (qq << 24) | ((uint64_t)c[j] & kRgbMask);
+            cb[j] = live[j] ? slot_of(px, py, ccols) >> (2 * kCoarseShift) : 0u;
+            lpc[j] = ((py & 255u) << 8) | (px & 255u);
+            rank[j] = lds_rank(s_cnt, cb[j], live[j]);
+        }
+        __syncthreads();
+        if ((int32_t)threadIdx.x < ncoarse) {
+            const uint32_t k = s_cnt[threadIdx.x];
+            s_base[threadIdx.x] = k ? atomicAdd(&ccursor[threadIdx.x], k) : 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kSortPpt; ++j) {
+            const uint64_t pos = (uint64_t)s_base[cb[j]] + rank[j];
+            if (live[j] && pos < end) {   // pos < end always: A and C1 agree
+                xkeys[pos] = key[j];
+                xlpc[pos] = (uint16_t)lpc[j];
             }
         }
+        __syncthreads();   // s_cnt and s_base are reused by the next step
     }
 }
 
-// The chunk of this workgroup: tile t (the last tile whose first chunk is
-// at or before blockIdx.x) and the range [lo, hi) of its bucket, at most
-// kChunk fragments.  Workgroups beyond the last chunk get lo >= hi.
-__device__ __forceinline__ void chunk_of(const uint32_t *start, const uint32_t *cstart,
-                                         int32_t ntiles, int32_t &t, uint32_t &lo, uint32_t &hi)
+// Last index a with list[a] <= b (list[0] = 0 <= b < list[count]).
+__device__ __forceinline__ int32_t find_item(const uint32_t *list, int32_t count, uint32_t b)
 {
-    const uint32_t b = blockIdx.x;
-    t = 0;
-    hi = lo = 0;
-    if (b >= cstart[ntiles])
-        return;
-    int32_t a = 0, z = ntiles;   // cstart[a] <= b < cstart[z]
+    int32_t a = 0, z = count;
     while (z - a > 1) {
         const int32_t m = (a + z) >> 1;
-        if (cstart[m] <= b)
+        if (list[m] <= b)
             a = m;
         else
             z = m;
     }
-    t = a;
-    const uint32_t end = start[t + 1];
-    lo = start[t] + (b - cstart[t]) * kChunk;
+    return a;
+}
+
+// Pass C2: one chunk of a coarse bucket into the bucket's 64 tile buckets,
+// ranked in LDS as in C1.
+__global__ void __launch_bounds__(kSortBlock) k_sort_fine(const uint64_t *__restrict__ xkeys,
+                                                          const uint16_t *__restrict__ xlpc,
+                                                          const uint32_t *__restrict__ fstart,
+                                                          const uint32_t *__restrict__ cchunk,
+                                                          uint32_t *fcursor,
+                                                          uint64_t *__restrict__ ykeys,
+                                                          uint16_t *__restrict__ ylps,
+                                                          int32_t ncoarse, int64_t n)
+{
+    __shared__ uint32_t s_cnt[kSlotsPerCoarse], s_base[kSlotsPerCoarse];
+    const uint32_t b = blockIdx.x;
+    if (b >= cchunk[ncoarse])
+        return;
+    const int32_t cb = find_item(cchunk, ncoarse, b);
+    const uint32_t bucket_end = fstart[(cb + 1) * kSlotsPerCoarse];
+    const uint32_t lo = fstart[cb * kSlotsPerCoarse] + (b - cchunk[cb]) * kChunk;
+    const uint32_t hi = bucket_end - lo > kChunk ? lo + kChunk : bucket_end;
+    if (threadIdx.x < kSlotsPerCoarse)
+        s_cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    constexpr int K = kChunk / kSortBlock;
+    uint64_t key[K];
+    uint32_t f[K], lp[K], rank[K];
+    bool ok[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const uint64_t i = (uint64_t)lo + (uint64_t)u * kSortBlock + threadIdx.x;
+        ok[u] = i < hi;
+        key[u] = ok[u] ? ldnt(xkeys + i) : 0ull;
+        const uint32_t v = ok[u] ? (uint32_t)xlpc[i] : 0u;
+        f[u] = ((v >> 13) << kCoarseShift) | ((v & 255u) >> kTileShift);
+        lp[u] = (((v >> 8) & 31u) << kTileShift) | (v & 31u);
+    }
+#pragma unroll
+    for (int u = 0; u < K; ++u)
+        rank[u] = lds_rank(s_cnt, f[u], ok[u]);
+    __syncthreads();
+    if (threadIdx.x < kSlotsPerCoarse) {
+        const uint32_t k = s_cnt[threadIdx.x];
+        s_base[threadIdx.x] =
+            k ? atomicAdd(&fcursor[cb * kSlotsPerCoarse + threadIdx.x], k) : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const uint64_t pos = (uint64_t)s_base[f[u]] + rank[u];
+        if (ok[u] && pos < (uint64_t)n) {   // pos < n always: the totals of A
+            ykeys[pos] = key[u];
+            ylps[pos] = (uint16_t)lp[u];
+        }
+    }
+}
+
+// The work item of this workgroup in passes D and E: slot t and the range
+// [lo, hi) of its tile bucket, at most kChunk entries.  Workgroups past the
+// last item get lo >= hi.
+__device__ __forceinline__ void chunk_of(const uint32_t *fstart, const uint32_t *fchunk,
+                                         int32_t nslots, int32_t &t, uint32_t &lo, uint32_t &hi)
+{
+    const uint32_t b = blockIdx.x;
+    t = 0;
+    hi = lo = 0;
+    if (b >= fchunk[nslots])
+        return;
+    t = find_item(fchunk, nslots, b);
+    const uint32_t end = fstart[t + 1];
+    lo = fstart[t] + (b - fchunk[t]) * kChunk;
     hi = end - lo > kChunk ? lo + kChunk : end;
 }
 
-constexpr int kUnroll = 4;   // bucket entries in flight per thread (D, E)
-
-// Pass D: depth pass of one chunk of a tile's bucket (section 2.1's minimum).
+// Pass D: depth pass of one chunk of a tile bucket (section 2.1's minimum).
 __global__ void __launch_bounds__(256) k_sort_raster(const uint64_t *__restrict__ keys,
                                                      const uint16_t *__restrict__ lps,
-                                                     const uint32_t *__restrict__ start,
-                                                     const uint32_t *__restrict__ cstart,
-                                                     uint64_t *__restrict__ fb, int32_t ntx,
-                                                     int32_t ntiles, int32_t width)
+                                                     const uint32_t *__restrict__ fstart,
+                                                     const uint32_t *__restrict__ fchunk,
+                                                     uint64_t *__restrict__ fb, int32_t ccols,
+                                                     int32_t nslots, int32_t width)
 {
     __shared__ uint64_t tile[kTilePix];
     int32_t t;
     uint32_t lo, hi;
-    chunk_of(start, cstart, ntiles, t, lo, hi);
+    chunk_of(fstart, fchunk, nslots, t, lo, hi);
     if (lo >= hi)
         return;
     for (int i = threadIdx.x; i < kTilePix; i += blockDim.x)
@@ -297,7 +431,8 @@ __global__ void __launch_bounds__(256) k_sort_raster(const uint64_t *__restrict_
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __syncthreads();
-    const uint32_t x0 = (uint32_t)(t % ntx) << kTileShift, y0 = (uint32_t)(t / ntx) << kTileShift;
+    uint32_t x0, y0;
+    slot_origin((uint32_t)t, ccols, x0, y0);
     for (int l = threadIdx.x; l < kTilePix; l += blockDim.x) {
         const uint64_t v = tile[l];
         if (v != ~0ull) {   // a fragment landed here, so the pixel is on screen
@@ -311,26 +446,27 @@ __global__ void __launch_bounds__(256) k_sort_raster(const uint64_t *__restrict_
     }
 }
 
-// Pass E: splat accumulation of one chunk of a tile's bucket (section 2.2),
+// Pass E: splat accumulation of one chunk of a tile bucket (section 2.2),
 // from the bucket's keys; fb holds the finished depth pass.
 template <bool PW>
 __global__ void __launch_bounds__(256) k_sort_accum(const uint64_t *__restrict__ keys,
                                                     const uint16_t *__restrict__ lps,
-                                                    const uint32_t *__restrict__ start,
-                                                    const uint32_t *__restrict__ cstart, Proj P,
+                                                    const uint32_t *__restrict__ fstart,
+                                                    const uint32_t *__restrict__ fchunk, Proj P,
                                                     uint32_t eps_num, uint32_t eps_den,
                                                     const uint64_t *__restrict__ fb,
-                                                    uint64_t *__restrict__ acc, int32_t ntx,
-                                                    int32_t ntiles, int32_t width, int32_t height)
+                                                    uint64_t *__restrict__ acc, int32_t ccols,
+                                                    int32_t nslots, int32_t width, int32_t height)
 {
     __shared__ uint64_t qmin[kTilePix];
     __shared__ uint64_t sums[2 * kTilePix];
     int32_t t;
     uint32_t lo, hi;
-    chunk_of(start, cstart, ntiles, t, lo, hi);
+    chunk_of(fstart, fchunk, nslots, t, lo, hi);
     if (lo >= hi)
         return;
-    const uint32_t x0 = (uint32_t)(t % ntx) << kTileShift, y0 = (uint32_t)(t / ntx) << kTileShift;
+    uint32_t x0, y0;
+    slot_origin((uint32_t)t, ccols, x0, y0);
     for (int l = threadIdx.x; l < kTilePix; l += blockDim.x) {
         const uint32_t x = x0 + (l & 31), y = y0 + (l >> kTileShift);
         const bool on = x < (uint32_t)width && y < (uint32_t)height;
@@ -378,34 +514,39 @@ __global__ void __launch_bounds__(256) k_sort_accum(const uint64_t *__restrict__
     }
 }
 
+// Passes A to C2: leaves the tile buckets (ykeys, ylps) and their starts.
 hipError_t sort_passes(const Pts &p, const Proj &P, const Layout &L, char *ws, bool vec,
                        hipStream_t s)
 {
-    uint32_t *counts = (uint32_t *)(ws + L.counts);
     uint32_t *total = (uint32_t *)(ws + L.total);
-    uint32_t *start = (uint32_t *)(ws + L.start);
-    uint32_t *cstart = (uint32_t *)(ws + L.cstart);
-    uint64_t *keys = (uint64_t *)(ws + L.keys);
-    uint16_t *lps = (uint16_t *)(ws + L.lps);
-    const size_t lds = (size_t)L.ntiles * sizeof(uint32_t);
+    uint32_t *fstart = (uint32_t *)(ws + L.fstart);
+    uint32_t *fchunk = (uint32_t *)(ws + L.fchunk);
+    uint32_t *fcursor = (uint32_t *)(ws + L.fcursor);
+    uint32_t *ccursor = (uint32_t *)(ws + L.ccursor);
+    uint32_t *cchunk = (uint32_t *)(ws + L.cchunk);
+    uint64_t *xkeys = (uint64_t *)(ws + L.xkeys);
+    uint16_t *xlpc = (uint16_t *)(ws + L.xlpc);
+    uint64_t *ykeys = (uint64_t *)(ws + L.ykeys);
+    uint16_t *ylps = (uint16_t *)(ws + L.ylps);
+    hipLaunchKernelGGL(k_sort_zero, dim3((L.nslots + 255) / 256), dim3(256), 0, s, total,
+                       L.nslots);
+    const size_t lds = (size_t)L.nslots * sizeof(uint32_t);
     if (vec)
-        hipLaunchKernelGGL((k_sort_count<kSortPpt, true>), dim3(L.groups), dim3(kSortBlock), lds,
-                           s, p, P, counts, L.ntx, L.ntiles, L.per_wg);
+        hipLaunchKernelGGL((k_sort_count<true>), dim3(L.groups), dim3(kSortBlock), lds, s, p, P,
+                           total, L.ccols, L.nslots, L.per_wg);
     else
-        hipLaunchKernelGGL((k_sort_count<kSortPpt, false>), dim3(L.groups), dim3(kSortBlock), lds,
-                           s, p, P, counts, L.ntx, L.ntiles, L.per_wg);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_sort_prefix, dim3((L.ntiles + kPrefixTiles - 1) / kPrefixTiles),
-                       dim3(kPrefixTiles * kPrefixSegs), 0, s, counts, L.groups, L.ntiles, total);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, total, start, cstart, L.ntiles);
+        hipLaunchKernelGGL((k_sort_count<false>), dim3(L.groups), dim3(kSortBlock), lds, s, p, P,
+                           total, L.ccols, L.nslots, L.per_wg);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, total, fstart, fchunk, fcursor,
+                       ccursor, cchunk, L.nslots, L.ncoarse);
     if (vec)
-        hipLaunchKernelGGL((k_sort_scatter<kSortPpt, true>), dim3(L.groups), dim3(kSortBlock),
-                           lds, s, p, P, counts, start, keys, lps, L.ntx, L.ntiles, L.per_wg);
+        hipLaunchKernelGGL((k_sort_coarse<true>), dim3(L.groups), dim3(kSortBlock), 0, s, p, P,
+                           ccursor, xkeys, xlpc, L.ccols, L.ncoarse, L.per_wg);
     else
-        hipLaunchKernelGGL((k_sort_scatter<kSortPpt, false>), dim3(L.groups), dim3(kSortBlock),
-                           lds, s, p, P, counts, start, keys, lps, L.ntx, L.ntiles, L.per_wg);
+        hipLaunchKernelGGL((k_sort_coarse<false>), dim3(L.groups), dim3(kSortBlock), 0, s, p, P,
+                           ccursor, xkeys, xlpc, L.ccols, L.ncoarse, L.per_wg);
+    hipLaunchKernelGGL(k_sort_fine, dim3((uint32_t)L.cchunks_max), dim3(kSortBlock), 0, s, xkeys,
+                       xlpc, fstart, cchunk, fcursor, ykeys, ylps, L.ncoarse, p.n);
     return hipGetLastError();
 }
 
@@ -421,6 +562,8 @@ int64_t rz_sorted_workspace_bytes(int64_t n, int32_t width, int32_t height)
     if (n < 0 || width < 1 || height < 1)
         return -1;
     const Layout L = layout(n, width, height);
+    if (L.ncoarse > kMaxCoarse)
+        return -1;
     return (int64_t)L.bytes;
 }
 
@@ -441,7 +584,7 @@ int rasterize_sorted(const rz_points *pts, const rz_view *view, const rz_depth_m
     if (!fb || (hq && !acc) || (flags & ~RZ_KEEP_KEYS) || (!(flags & RZ_KEEP_KEYS) && !img))
         return RZ_EINVAL;
     const Layout L = layout(pts->n, P.width, P.height);
-    if (L.ntiles > kMaxTiles)
+    if (L.ncoarse > kMaxCoarse)
         return RZ_EINVAL;
     if (pts->n > 0 && (!workspace || ((uintptr_t)workspace & 255u) ||
                        workspace_bytes < (int64_t)L.bytes))
@@ -455,25 +598,25 @@ int rasterize_sorted(const rz_points *pts, const rz_view *view, const rz_depth_m
                           15u) == 0;
         char *ws = (char *)workspace;
         e = sort_passes(p, P, L, ws, vec, s);
-        const uint64_t *keys = (const uint64_t *)(ws + L.keys);
-        const uint16_t *lps = (const uint16_t *)(ws + L.lps);
-        const uint32_t *start = (const uint32_t *)(ws + L.start);
-        const uint32_t *cstart = (const uint32_t *)(ws + L.cstart);
-        const dim3 grid((uint32_t)L.chunks_max);   // workgroups past the last chunk exit
+        const uint64_t *keys = (const uint64_t *)(ws + L.ykeys);
+        const uint16_t *lps = (const uint16_t *)(ws + L.ylps);
+        const uint32_t *fstart = (const uint32_t *)(ws + L.fstart);
+        const uint32_t *fchunk = (const uint32_t *)(ws + L.fchunk);
+        const dim3 grid((uint32_t)L.fchunks_max);   // workgroups past the last item exit
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_sort_raster, grid, dim3(256), 0, s, keys, lps, start, cstart, fb,
-                               L.ntx, L.ntiles, P.width);
+            hipLaunchKernelGGL(k_sort_raster, grid, dim3(256), 0, s, keys, lps, fstart, fchunk,
+                               fb, L.ccols, L.nslots, P.width);
             e = hipGetLastError();
         }
         if (e == hipSuccess && hq) {
             if (P.nr)
-                hipLaunchKernelGGL((k_sort_accum<true>), grid, dim3(256), 0, s, keys, lps, start,
-                                   cstart, P, num, den, fb, acc, L.ntx, L.ntiles, P.width,
+                hipLaunchKernelGGL((k_sort_accum<true>), grid, dim3(256), 0, s, keys, lps, fstart,
+                                   fchunk, P, num, den, fb, acc, L.ccols, L.nslots, P.width,
                                    P.height);
             else
-                hipLaunchKernelGGL((k_sort_accum<false>), grid, dim3(256), 0, s, keys, lps, start,
-                                   cstart, P, num, den, fb, acc, L.ntx, L.ntiles, P.width,
-                                   P.height);
+                hipLaunchKernelGGL((k_sort_accum<false>), grid, dim3(256), 0, s, keys, lps,
+                                   fstart, fchunk, P, num, den, fb, acc, L.ccols, L.nslots,
+                                   P.width, P.height);
             e = hipGetLastError();
         }
     }

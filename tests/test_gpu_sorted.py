@@ -84,20 +84,23 @@ def test_ordered_terrain(rz, oracle):
     check(rz, oracle, cloud, view, label="terrain ordered")
 
 
-def test_largest_screen(rz, oracle):
-    """3840x2160 is 120 x 68 = 8160 tiles, under the 8192 limit."""
+@pytest.mark.parametrize("size", [(3840, 2160), (4096, 4096)])
+def test_largest_screens(rz, oracle, size):
+    """4096x4096 is 16 x 16 coarse buckets, the limit (a 64 KiB tile
+    histogram in pass A)."""
     cloud = gen.shuffle(gen.terrain(1_000_000, 42, extent=100.0, amplitude=10.0,
                                     wavelength=40.0), 2)
-    view = gen.orbit_views(1, 8, [(3840, 2160)], extent=100.0, rmin=60.0, rmax=120.0, near=0.5,
+    view = gen.orbit_views(1, 8, [size], extent=100.0, rmin=60.0, rmax=120.0, near=0.5,
                            far=400.0)[0]
-    check(rz, oracle, cloud, view, label="3840x2160")
+    check(rz, oracle, cloud, view, label=f"{size[0]}x{size[1]}")
 
 
 def test_tile_limit(rz):
     import torch
     pts = rz.Points.from_cloud(gen.config1(n=1000)[0])
-    view = gen.make_view((0.5, 0.5, 2.5), (0.5, 0.5, 0.5), (0, 1, 0), 60.0, 3872, 2176, 0.01,
-                         10.0)   # 121 x 68 = 8228 tiles
+    view = gen.make_view((0.5, 0.5, 2.5), (0.5, 0.5, 0.5), (0, 1, 0), 60.0, 4352, 4096, 0.01,
+                         10.0)   # 17 x 16 coarse buckets > 256
+    assert rz.load().rz_sorted_workspace_bytes(1000, 4352, 4096) == -1
     with pytest.raises(rz.RzError):
         rz.rasterize_sorted(pts, view, workspace=torch.empty(1 << 20, dtype=torch.uint8,
                                                              device="cuda"))
