@@ -44,6 +44,19 @@ def workload(name):
     elif name == "spheres1m":
         cloud, view = gen.config1()
         desc = "8 spheres 1M points, shuffled, 1024x768"
+    elif name.startswith("stress300m"):
+        # stress300m[-shuffled]-1440p|360p: 250M terrain points (5x density)
+        # plus 20 dense spheres of 2.5M points
+        parts = name.split("-")
+        order = "shuffled" if "shuffled" in parts else "morton"
+        res = parts[-1]
+        if res not in ("1440p", "360p"):
+            raise SystemExit(f"unknown workload {name}")
+        log(f"[bench] generating the 300M-point stress cloud ({order})")
+        cloud, views = gen.config3(order=order)
+        view = views[0] if res == "1440p" else views[1]
+        desc = (f"stress 300M points (250M terrain + 20 spheres of 2.5M), {order}, "
+                f"{view.width}x{view.height}")
     else:
         raise SystemExit(f"unknown workload {name}")
     return cloud, view, desc
@@ -320,6 +333,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="terrain50m")
+    ap.add_argument("--path", choices=("direct", "sorted"), default="direct",
+                    help="direct: one atomic per fragment; sorted: screen-tile sort first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="verify one frame against the oracle")
     ap.add_argument("--batch-points", type=int, default=100_000_000)
@@ -360,7 +375,30 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] n={n} {W}x{H} launch={rz.get_launch()}")
 
+    ws = rz.new_workspace(n, W, H) if a.path == "sorted" else None
+
+    def step_sorted(ev):
+        # the same two frames through the screen-sorted path (one call each)
+        if ev:
+            ev[0].record()
+        rz.rasterize_sorted(pts, view, fb=fb, workspace=ws, keep_keys=True)
+        if ev:
+            ev[1].record()
+        rz.resolve_min(fb, npix, 0, img)
+        if ev:
+            ev[2].record()
+        rz.rasterize_sorted(pts, view, hq=True, eps=eps, fb=fb, acc=acc, workspace=ws,
+                            keep_keys=True)
+        if ev:
+            ev[3].record()
+            ev[4].record()
+        rz.resolve_hq(fb, acc, npix, 0, himg, status)
+        if ev:
+            ev[5].record()
+
     def step(ev):
+        if a.path == "sorted":
+            return step_sorted(ev)
         # atomicMin frame: depth pass, then resolve + clear
         if ev:
             ev[0].record()
@@ -410,14 +448,25 @@ def main():
     if int(status.item()) != 0:
         raise SystemExit("splat count overflow reported")
 
-    raster_ms = (avg[0] + avg[2]) / 2
-    accum_ms = avg[3]
-    kern = {
-        "k_raster_min": {"ms": raster_ms, "bytes": 16 * n, "launches_per_step": 2},
-        "k_hq_accum": {"ms": accum_ms, "bytes": 16 * n, "launches_per_step": 1},
-        "k_resolve_min": {"ms": avg[1], "bytes": 20 * npix, "launches_per_step": 1},
-        "k_resolve_hq": {"ms": avg[4], "bytes": 44 * npix, "launches_per_step": 1},
-    }
+    if a.path == "sorted":
+        # whole calls; bytes = the sort's own HBM traffic per point: count
+        # pass 16, coarse scatter 16 + 10, fine scatter 10 + 10, tile min 10
+        # (+ splat pass 10)
+        kern = {
+            "rasterize_sorted(atomicMin)": {"ms": avg[0], "bytes": 72 * n,
+                                            "launches_per_step": 1},
+            "rasterize_sorted(HQ)": {"ms": avg[2], "bytes": 82 * n, "launches_per_step": 1},
+            "k_resolve_min": {"ms": avg[1], "bytes": 20 * npix, "launches_per_step": 1},
+            "k_resolve_hq": {"ms": avg[4], "bytes": 44 * npix, "launches_per_step": 1},
+        }
+    else:
+        kern = {
+            "k_raster_min": {"ms": (avg[0] + avg[2]) / 2, "bytes": 16 * n,
+                             "launches_per_step": 2},
+            "k_hq_accum": {"ms": avg[3], "bytes": 16 * n, "launches_per_step": 1},
+            "k_resolve_min": {"ms": avg[1], "bytes": 20 * npix, "launches_per_step": 1},
+            "k_resolve_hq": {"ms": avg[4], "bytes": 44 * npix, "launches_per_step": 1},
+        }
     for k in kern.values():
         k["GBps"] = k["bytes"] / (k["ms"] * 1e-3) / 1e9
     dom = max(kern, key=lambda k: kern[k]["ms"] * kern[k]["launches_per_step"])
@@ -427,7 +476,7 @@ def main():
     if os.path.exists(tfile):
         with open(tfile) as f:
             tr = json.load(f)
-        rec = tr.get(a.workload, {}).get(dom)
+        rec = tr.get(a.workload if a.path == "direct" else f"{a.workload}:{a.path}", {}).get(dom)
         if rec and rec.get("source_hash") == kernel_source_hash():
             traffic = rec["bytes_per_launch"]
     out = {
@@ -444,7 +493,7 @@ def main():
         "dtype": "f32+f64->u64",
         "data": "synthetic",
         "config": {"workload": desc, "points": n, "width": W, "height": H,
-                   "eps": f"{eps[0]}/{eps[1]}", "depth_map": "linear 40-bit"},
+                   "eps": f"{eps[0]}/{eps[1]}", "depth_map": "linear 40-bit", "path": a.path},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(dk["GBps"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(dk["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic},

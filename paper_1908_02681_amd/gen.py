@@ -181,26 +181,36 @@ def _height_grid(g: int, h: float, seed: int, extent, amplitude, wavelength,
     return z
 
 
+def _compact_table() -> np.ndarray:
+    """Even bits of every 16-bit value, packed into 8 bits."""
+    v = np.arange(1 << 16, dtype=np.uint32)
+    out = np.zeros(1 << 16, np.uint32)
+    for b in range(8):
+        out |= ((v >> np.uint32(2 * b)) & np.uint32(1)) << np.uint32(b)
+    return out
+
+
+_COMPACT = _compact_table()
+
+
 def _compact1by1(v: np.ndarray) -> np.ndarray:
-    v = v & np.uint64(0x5555555555555555)
-    v = (v | (v >> np.uint64(1))) & np.uint64(0x3333333333333333)
-    v = (v | (v >> np.uint64(2))) & np.uint64(0x0F0F0F0F0F0F0F0F)
-    v = (v | (v >> np.uint64(4))) & np.uint64(0x00FF00FF00FF00FF)
-    v = (v | (v >> np.uint64(8))) & np.uint64(0x0000FFFF0000FFFF)
-    v = (v | (v >> np.uint64(16))) & np.uint64(0x00000000FFFFFFFF)
-    return v
+    """Even bits of v (uint32, at most 32 bits), packed: the x part of a Z code."""
+    t = _COMPACT
+    return t[v & np.uint32(0xFFFF)] | (t[v >> np.uint32(16)] << np.uint32(8))
 
 
 def _morton_cells(g: int, n: int):
     """The first n cells of a g x g grid in Z (Morton) order, as (i, j)."""
     k = max(1, int(math.ceil(math.log2(g))))
+    if k > 16:
+        raise ValueError("grid side above 65536")
     total = 1 << (2 * k)
     out_i, out_j, have = [], [], 0
     step = 1 << 24
     for start in range(0, total, step):
-        code = np.arange(start, min(total, start + step), dtype=np.uint64)
+        code = np.arange(start, min(total, start + step), dtype=np.uint32)
         i = _compact1by1(code)
-        j = _compact1by1(code >> np.uint64(1))
+        j = _compact1by1(code >> np.uint32(1))
         keep = (i < g) & (j < g)
         i, j = i[keep].astype(np.int64), j[keep].astype(np.int64)
         out_i.append(i)
