@@ -24,6 +24,8 @@ CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
 LINEAR = 0
 SCALE = 1
 PIECEWISE = 2
+GL24 = 3        # depth pass only: 24-bit window depth of the perspective matrix
+F32REV = 4      # depth pass only: reversed single-precision depth
 
 _lock = threading.Lock()
 _lib = None
@@ -47,10 +49,10 @@ def configure(lib):
     lib.rzo_fragments.argtypes = [P, P, P, i64] + cam + [P, P]
     lib.rzo_clear.argtypes = [P, i64, u32]
     lib.rzo_clear.restype = None
-    lib.rzo_raster_min.argtypes = [P, P, P, P, i64] + cam + [P]
+    lib.rzo_raster_min.argtypes = [P, P, P, P, i64] + cam + [i32, P]
     lib.rzo_resolve_min.argtypes = [P, i64, u32, P]
     lib.rzo_resolve_min.restype = None
-    lib.rzo_hq_accumulate.argtypes = [P, P, P, P, i64] + cam + [u32, u32, P, P]
+    lib.rzo_hq_accumulate.argtypes = [P, P, P, P, i64] + cam + [i32, u32, u32, P, P]
     lib.rzo_hq_resolve.argtypes = [P, P, i64, u32, P]
     lib.rzo_hq_resolve.restype = None
     return lib
@@ -124,7 +126,7 @@ def clear_value(bg: int = 0) -> int:
 
 
 def raster_min(x, y, z, rgb, vp, near, far, width, height, kind=LINEAR, scale=0.0,
-               bg=0, fb=None):
+               bg=0, fb=None, point_size=1):
     """Depth pass: the per-pixel minimum key (unresolved framebuffer)."""
     lib = _load()
     x, y, z, rgb = _f32(x), _f32(y), _f32(z), _u32(rgb)
@@ -133,7 +135,8 @@ def raster_min(x, y, z, rgb, vp, near, far, width, height, kind=LINEAR, scale=0.
         fb = np.empty(npix, np.uint64)
         lib.rzo_clear(_ptr(fb), npix, int(bg) & 0xFFFFFFFF)
     vp, cam = _cam_args(vp, near, far, width, height, kind, scale)
-    if lib.rzo_raster_min(_ptr(x), _ptr(y), _ptr(z), _ptr(rgb), x.shape[0], *cam, _ptr(fb)):
+    if lib.rzo_raster_min(_ptr(x), _ptr(y), _ptr(z), _ptr(rgb), x.shape[0], *cam,
+                          int(point_size), _ptr(fb)):
         raise ValueError("invalid camera or depth map")
     return fb
 
@@ -146,16 +149,17 @@ def resolve_min(fb, bg=0):
 
 
 def render_atomicmin(x, y, z, rgb, vp, near, far, width, height, kind=LINEAR,
-                     scale=0.0, bg=0):
+                     scale=0.0, bg=0, point_size=1):
     """Both steps of section 2.1. Returns (keys, image)."""
-    fb = raster_min(x, y, z, rgb, vp, near, far, width, height, kind, scale, bg)
+    fb = raster_min(x, y, z, rgb, vp, near, far, width, height, kind, scale, bg,
+                    point_size=point_size)
     keys = fb.copy()
     img = resolve_min(fb, bg)
     return keys, img
 
 
 def hq_accumulate(x, y, z, rgb, vp, near, far, width, height, fb, kind=LINEAR,
-                  scale=0.0, eps=(1, 100), sums=None):
+                  scale=0.0, eps=(1, 100), sums=None, point_size=1):
     """Second splatting pass: exact (R, G, B, count) per pixel."""
     lib = _load()
     x, y, z, rgb = _f32(x), _f32(y), _f32(z), _u32(rgb)
@@ -164,7 +168,7 @@ def hq_accumulate(x, y, z, rgb, vp, near, far, width, height, fb, kind=LINEAR,
         sums = np.zeros((npix, 4), np.uint64)
     vp, cam = _cam_args(vp, near, far, width, height, kind, scale)
     rc = lib.rzo_hq_accumulate(_ptr(x), _ptr(y), _ptr(z), _ptr(rgb), x.shape[0], *cam,
-                               int(eps[0]), int(eps[1]), _ptr(fb), _ptr(sums))
+                               int(point_size), int(eps[0]), int(eps[1]), _ptr(fb), _ptr(sums))
     if rc:
         raise ValueError(f"hq accumulate failed ({rc})")
     return sums
@@ -177,11 +181,13 @@ def hq_resolve(sums, fb, bg=0):
 
 
 def render_hq(x, y, z, rgb, vp, near, far, width, height, kind=LINEAR, scale=0.0,
-              eps=(1, 100), bg=0):
+              eps=(1, 100), bg=0, point_size=1):
     """All three passes of section 2.2. Returns (keys, sums[npix, 4], image)."""
-    fb = raster_min(x, y, z, rgb, vp, near, far, width, height, kind, scale, bg)
+    fb = raster_min(x, y, z, rgb, vp, near, far, width, height, kind, scale, bg,
+                    point_size=point_size)
     keys = fb.copy()
-    sums = hq_accumulate(x, y, z, rgb, vp, near, far, width, height, fb, kind, scale, eps)
+    sums = hq_accumulate(x, y, z, rgb, vp, near, far, width, height, fb, kind, scale, eps,
+                         point_size=point_size)
     out = sums.copy()
     img = hq_resolve(sums, fb, bg)
     return keys, out, img

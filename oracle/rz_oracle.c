@@ -49,6 +49,26 @@
  *    its eps window compares the linear depths of q and qmin in double:
  *    den * (d(q) - d(qmin)) <= num * d(qmin), d(q) = b[k] + (q - base[k]) / sb[k]
  *    (the reciprocal of sb[k] computed once).
+ *
+ * Two more depth encodings stand for what a graphics pipeline keeps in its
+ * depth buffer, the precision the paper's 40-bit integers are set against
+ * (sections 1 and 2.1); they are for the depth pass only:
+ *  - "gl24": window depth of the perspective matrix in single precision,
+ *    z_ndc = clip.z / clip.w (row 2 of the float matrix, same operation
+ *    order as the other rows), z_win = (z_ndc + 1) / 2, kept as a 24-bit
+ *    unsigned normalised integer round(z_win * (2^24 - 1)) (rounding to
+ *    nearest, ties up), fragments with z_ndc outside [-1, 1] discarded;
+ *  - "f32rev": reversed depth in single precision, z_rev = (float)near /
+ *    clip.w (1 at the near plane, falling towards 0 far away), kept as its
+ *    32-bit pattern complemented, 2^32 - 1 - bits(z_rev), so that nearer is
+ *    smaller like every other key.
+ * Both leave the near/far cull on d as for every map.
+ *
+ * Point size (section 3 on cost per fragment): a point of size k covers the
+ * k x k pixels px - r .. px - r + k - 1, py - r .. py - r + k - 1 with
+ * r = (k - 1) / 2 around its pixel (px, py), clipped to the screen; the point
+ * itself is still culled by its centre.  Every covered pixel gets the same
+ * key, and in the splat pass every covered pixel tests its own window.
  */
 #include <math.h>
 #include <stddef.h>
@@ -59,13 +79,14 @@
 #define RZO_Q_MAX ((double)((1ull << 40) - 2)) /* largest fragment depth   */
 #define RZO_Q_RANGE ((double)((1ull << 40) - 1))
 
-enum { RZO_LINEAR = 0, RZO_SCALE = 1, RZO_PIECEWISE = 2 };
+enum { RZO_LINEAR = 0, RZO_SCALE = 1, RZO_PIECEWISE = 2, RZO_GL24 = 3, RZO_F32REV = 4 };
 #define RZO_MAX_RANGES 8
 
 typedef struct {
     float m[16];       /* view-projection rounded to float, row-major */
     double vp[16];     /* the same in double                          */
     double near_, far_;
+    float nearf;       /* near rounded to float (f32rev)              */
     double o, s;       /* q = floor((d - o) * s)                      */
     uint64_t z0;       /* floor(o * s): q + z0 is proportional to d   */
     float fw, fh;      /* framebuffer size as float                   */
@@ -93,6 +114,7 @@ static int rzo_cam_init(rzo_cam *c, const double *vp, double near_, double far_,
     }
     c->near_ = near_;
     c->far_ = far_;
+    c->nearf = (float)near_;
     if (kind == RZO_LINEAR) {
         c->o = near_;
         c->s = RZO_Q_RANGE / (far_ - near_);
@@ -103,6 +125,9 @@ static int rzo_cam_init(rzo_cam *c, const double *vp, double near_, double far_,
             return -1;
     } else if (kind == RZO_PIECEWISE) {
         c->o = 0.0;        /* the ranges are set by rzo_cam_ranges */
+        c->s = 1.0;
+    } else if (kind == RZO_GL24 || kind == RZO_F32REV) {
+        c->o = 0.0;        /* no linear map: see rzo_fragment */
         c->s = 1.0;
     } else {
         return -1;
@@ -222,10 +247,41 @@ static int rzo_fragment(const rzo_cam *c, float x, float y, float z,
     if (!(d >= c->near_ && d < c->far_))
         return 0;
 
-    /* integer part of the scaled depth, kept inside 40 bits */
     *pix = (int64_t)py * c->w + px;
+    if (c->kind == RZO_GL24) {
+        /* window depth of the perspective matrix, 24-bit normalised */
+        float cz, nz, zw, t;
+        cz = m[8] * x;
+        cz = cz + m[9] * y;
+        cz = cz + m[10] * z;
+        cz = cz + m[11];
+        nz = cz / cw;
+        if (!(nz >= -1.0f && nz <= 1.0f))
+            return 0;
+        zw = (nz + 1.0f) * 0.5f;
+        t = zw * 16777215.0f;
+        *q = (uint64_t)floor((double)t + 0.5);
+        return 1;
+    }
+    if (c->kind == RZO_F32REV) {
+        /* reversed single-precision depth, complemented bit pattern */
+        union { float f; uint32_t u; } zr;
+        zr.f = c->nearf / cw;
+        *q = (uint64_t)(0xFFFFFFFFu - zr.u);
+        return 1;
+    }
+    /* integer part of the scaled depth, kept inside 40 bits */
     *q = rzo_quantise(c, d);
     return 1;
+}
+
+/* Pixel range [lo, hi) covered along one axis by a point of size k whose
+   centre pixel is c, clipped to [0, size). */
+static void rzo_span(int64_t c, int32_t k, int32_t size, int64_t *lo, int64_t *hi)
+{
+    const int64_t r = (k - 1) / 2;
+    *lo = c - r < 0 ? 0 : c - r;
+    *hi = c - r + k > size ? size : c - r + k;
 }
 
 /* ---------------------------------------------------------------------- */
@@ -291,22 +347,26 @@ int rzo_raster_min(const float *x, const float *y, const float *z,
                    const uint32_t *rgb, int64_t n, const double *vp,
                    double near_, double far_, int32_t w, int32_t h,
                    int32_t kind, double scale, int32_t nr, const double *rb,
-                   const double *rs, uint64_t *fb)
+                   const double *rs, int32_t psize, uint64_t *fb)
 {
     rzo_cam c;
     int64_t i;
-    if (rzo_cam_init(&c, vp, near_, far_, w, h, kind, scale))
+    if (psize < 1 || rzo_cam_init(&c, vp, near_, far_, w, h, kind, scale))
         return -1;
     if (kind == RZO_PIECEWISE && rzo_cam_ranges(&c, nr, rb, rs))
         return -1;
     for (i = 0; i < n; i++) {
-        int64_t p;
+        int64_t p, x0, x1, y0, y1, xx, yy;
         uint64_t q, key;
         if (!rzo_fragment(&c, x[i], y[i], z[i], &p, &q))
             continue;
         key = (q << 24) | ((uint64_t)rgb[i] & RZO_RGB_MASK);
-        if (key < fb[p])
-            fb[p] = key;
+        rzo_span(p % w, psize, w, &x0, &x1);
+        rzo_span(p / w, psize, h, &y0, &y1);
+        for (yy = y0; yy < y1; yy++)
+            for (xx = x0; xx < x1; xx++)
+                if (key < fb[yy * w + xx])
+                    fb[yy * w + xx] = key;
     }
     return 0;
 }
@@ -334,44 +394,51 @@ int rzo_hq_accumulate(const float *x, const float *y, const float *z,
                       const uint32_t *rgb, int64_t n, const double *vp,
                       double near_, double far_, int32_t w, int32_t h,
                       int32_t kind, double scale, int32_t nr, const double *rb,
-                      const double *rs, uint32_t eps_num, uint32_t eps_den,
-                      const uint64_t *fb, uint64_t *sums)
+                      const double *rs, int32_t psize, uint32_t eps_num,
+                      uint32_t eps_den, const uint64_t *fb, uint64_t *sums)
 {
     rzo_cam c;
     int64_t i;
-    if (eps_den == 0)
+    if (eps_den == 0 || psize < 1 || kind == RZO_GL24 || kind == RZO_F32REV)
         return -1;
     if (rzo_cam_init(&c, vp, near_, far_, w, h, kind, scale))
         return -1;
     if (kind == RZO_PIECEWISE && rzo_cam_ranges(&c, nr, rb, rs))
         return -1;
     for (i = 0; i < n; i++) {
-        int64_t p;
-        uint64_t q, qmin;
+        int64_t p, x0, x1, y0, y1, xx, yy;
+        uint64_t q;
         uint32_t col;
         if (!rzo_fragment(&c, x[i], y[i], z[i], &p, &q))
             continue;
-        qmin = fb[p] >> 24;
-        if (q < qmin)
-            return -2; /* fb does not hold this cloud's depth pass */
-        if (c.kind == RZO_PIECEWISE) {
-            /* q + z0 is not proportional to d here: compare the linear
-               depths the two integers stand for, in double precision */
-            const double dq = rzo_depth_of(&c, q);
-            const double dm = rzo_depth_of(&c, qmin);
-            const double lhs = (double)eps_den * (dq - dm);
-            const double rhs = (double)eps_num * dm;
-            if (!(lhs <= rhs))
-                continue;
-        } else if ((unsigned __int128)eps_den * (q - qmin) >
-                   (unsigned __int128)eps_num * ((unsigned __int128)qmin + c.z0)) {
-            continue;   /* exact: 128-bit products cannot overflow */
-        }
         col = rgb[i];
-        sums[4 * p + 0] += col & 0xFFu;
-        sums[4 * p + 1] += (col >> 8) & 0xFFu;
-        sums[4 * p + 2] += (col >> 16) & 0xFFu;
-        sums[4 * p + 3] += 1;
+        rzo_span(p % w, psize, w, &x0, &x1);
+        rzo_span(p / w, psize, h, &y0, &y1);
+        for (yy = y0; yy < y1; yy++) {
+            for (xx = x0; xx < x1; xx++) {
+                const int64_t pp = yy * w + xx;
+                const uint64_t qmin = fb[pp] >> 24;
+                if (q < qmin)
+                    return -2; /* fb does not hold this cloud's depth pass */
+                if (c.kind == RZO_PIECEWISE) {
+                    /* q + z0 is not proportional to d here: compare the
+                       linear depths the two integers stand for, in double */
+                    const double dq = rzo_depth_of(&c, q);
+                    const double dm = rzo_depth_of(&c, qmin);
+                    const double lhs = (double)eps_den * (dq - dm);
+                    const double rhs = (double)eps_num * dm;
+                    if (!(lhs <= rhs))
+                        continue;
+                } else if ((unsigned __int128)eps_den * (q - qmin) >
+                           (unsigned __int128)eps_num * ((unsigned __int128)qmin + c.z0)) {
+                    continue;   /* exact: 128-bit products cannot overflow */
+                }
+                sums[4 * pp + 0] += col & 0xFFu;
+                sums[4 * pp + 1] += (col >> 8) & 0xFFu;
+                sums[4 * pp + 2] += (col >> 16) & 0xFFu;
+                sums[4 * pp + 3] += 1;
+            }
+        }
     }
     return 0;
 }

@@ -480,3 +480,200 @@ def test_piecewise_range_boundary(oracle):
     e = np.zeros_like(d)
     _, q = oracle.fragments(e, e, -d, vp, 0.25, 10.0, 2, 2, oracle.PIECEWISE, ranges)
     assert q.tolist() == [2, 3]
+
+
+# --------------------------------------------------------------------------
+# depth encodings of a graphics depth buffer (depth pass only; sections 1
+# and 2.1 set the 40-bit integers against them)
+# --------------------------------------------------------------------------
+
+GL24, F32REV = 3, 4
+
+
+def _ortho_z_camera():
+    """clip = (x, y, z, 1): w = 1 and z_ndc = z."""
+    vp = np.zeros((4, 4))
+    vp[0, 0] = vp[1, 1] = vp[2, 2] = vp[3, 3] = 1.0
+    return vp
+
+
+def test_gl24_window_depth_codes(oracle):
+    """Dyadic depths with w = 1: round(((z + 1) / 2) * (2^24 - 1)), ties up,
+    worked by hand; |z_ndc| > 1 is clipped."""
+    z = np.array([-1.0, 0.0, 0.5, 1.0, -0.5, 1.0 + 2.0 ** -20, -1.0 - 2.0 ** -20], np.float32)
+    x = np.zeros_like(z)
+    pix, q = oracle.fragments(x, x, z, _ortho_z_camera(), 0.5, 2.0, 4, 4, GL24)
+    # (z+1)/2 * 16777215 = 0, 8388607.5, 12582911.25, 16777215, 4194303.75
+    assert [int(v) for v in q[:5]] == [0, 8388608, 12582911, 16777215, 4194304]
+    assert (pix[:5] == 2 * 4 + 2).all()          # the centre of a 4x4 screen
+    assert (pix[5:] == -1).all()
+
+
+def test_f32rev_codes(oracle):
+    """near / w as a float, bit pattern complemented: w = 0.5, 1, 2, 4 with
+    near = 0.5 give 1.0, 0.5, 0.25, 0.125, whose IEEE patterns are known."""
+    w = np.array([0.5, 1.0, 2.0, 4.0, 1000.0, 1000.001], np.float32)
+    x = np.zeros_like(w)
+    pix, q = oracle.fragments(x, x, -w, _axis_camera(), 0.5, 5000.0, 8, 8, F32REV)
+    patterns = [0x3F800000, 0x3F000000, 0x3E800000, 0x3E000000]
+    assert [int(v) for v in q[:4]] == [0xFFFFFFFF - b for b in patterns]
+    assert (np.diff(q.astype(np.int64)) > 0).all()     # farther is larger
+    assert q[5] > q[4]                                  # 1 mm apart at 1 km still ordered
+
+
+def test_gl24_codes_follow_the_perspective_depth(oracle):
+    """On the optical axis of a GL perspective matrix the window depth is
+    f (d - n) / ((f - n) d) (closed form); the codes stay within the float
+    pipeline's few quanta of it and never decrease with d."""
+    n, f = 0.5, 4000.0
+    vp = gen.perspective(60.0, 1.0, n, f)
+    d = np.array([0.6, 1.0, 3.0, 10.0, 50.0, 200.0, 1000.0, 3000.0], np.float32)
+    x = np.zeros_like(d)
+    pix, q = oracle.fragments(x, x, -d, vp, n, f, 8, 8, GL24)
+    assert (pix >= 0).all()
+    for di, qi in zip(d, q):
+        dd = F(float(di))
+        zw = F(f) * (dd - F(n)) / ((F(f) - F(n)) * dd)
+        assert abs(int(qi) - zw * (2 ** 24 - 1)) <= 4
+    assert (np.diff(q.astype(np.int64)) >= 0).all()
+
+
+def _two_surfaces_1mm(n=20000, W=64, H=64):
+    rng = np.random.default_rng(3)
+    v = gen.make_view((0, 0, 1000.0), (0, 0, 0), (0, 1, 0), 1.0, W, H, 0.5, 4000.0)
+    x = rng.uniform(-8, 8, n).astype(np.float32)
+    y = rng.uniform(-8, 8, n).astype(np.float32)
+    front = np.arange(n) % 2 == 0
+    z = np.where(front, np.float32(0.0), np.float32(-0.001)).astype(np.float32)
+    # the nearer surface has the larger colour word: ties show the far one
+    rgb = np.where(front, 0x00FF00, 0x0000FF).astype(np.uint32)
+    return v, x, y, z, rgb, front
+
+
+def test_depth_buffer_precision_at_one_kilometre(oracle):
+    """Two interleaved surfaces 1 mm apart at 1 km (near 0.5, far 4000).  The
+    40-bit linear map and the reversed float depth show the nearer surface in
+    every pixel it covers.  A 24-bit window depth cannot separate them: one
+    of its steps is about f n / ((f - n) d^2) = 5e-7 per metre in window
+    depth there, i.e. 2^-24 / 5e-7 = 0.12 m, so the colour tie rule decides
+    and the farther surface shows through."""
+    v, x, y, z, rgb, front = _two_surfaces_1mm()
+    W, H = v.width, v.height
+    px = set(oracle.fragments(x[front], y[front], z[front], v.vp, v.near, v.far, W, H)[0].tolist())
+    px.discard(-1)
+    px = np.array(sorted(px))
+    assert px.size > 3000
+    shown = {}
+    for kind in (LINEAR, F32REV, GL24):
+        _, img = oracle.render_atomicmin(x, y, z, rgb, v.vp, v.near, v.far, W, H, kind)
+        shown[kind] = (img[px] == 0x00FF00).mean()
+    assert shown[LINEAR] == 1.0 and shown[F32REV] == 1.0
+    assert shown[GL24] < 0.2
+
+
+def test_float_depth_kinds_are_depth_pass_only(oracle):
+    v, x, y, z, rgb, _ = _two_surfaces_1mm(200, 8, 8)
+    for kind in (GL24, F32REV):
+        with pytest.raises(ValueError):
+            oracle.render_hq(x, y, z, rgb, v.vp, v.near, v.far, 8, 8, kind)
+
+
+# --------------------------------------------------------------------------
+# point size: a point covers k x k pixels (section 3, cost per fragment)
+# --------------------------------------------------------------------------
+
+def _box(a, k, op, ident):
+    """out[y, x] = op over centres (cx, cy) with cx in [x + r - k + 1, x + r]
+    (r = (k - 1) // 2), likewise cy, of a[cy, cx]: the pixels a point of
+    size k centred at (cx, cy) covers, read from the covered pixel's side."""
+    H, W = a.shape
+    r = (k - 1) // 2
+    out = np.full_like(a, ident)
+    for oy in range(k):
+        for ox in range(k):
+            sy, sx = r - oy, r - ox        # centre = pixel + (sx, sy)
+            src = np.full_like(a, ident)
+            ys, yd = (slice(sy, H), slice(0, H - sy)) if sy >= 0 else (slice(0, H + sy), slice(-sy, H))
+            xs, xd = (slice(sx, W), slice(0, W - sx)) if sx >= 0 else (slice(0, W + sx), slice(-sx, W))
+            src[yd, xd] = a[ys, xs]
+            out = op(out, src)
+    return out
+
+
+def test_point_size_one_is_the_basic_pass(oracle):
+    W, H = 40, 24
+    v, x, y, z, rgb = _random_scene(9, 1500, W, H)
+    a = oracle.raster_min(x, y, z, rgb, v.vp, v.near, v.far, W, H)
+    b = oracle.raster_min(x, y, z, rgb, v.vp, v.near, v.far, W, H, point_size=1)
+    assert (a == b).all()
+
+
+def test_point_size_corner_hand_case(oracle):
+    """One point in the corner pixel (0, 0) of an 8x8 screen: size 3 covers
+    x, y in -1..1 clipped to 0..1 (4 pixels), size 4 covers -1..2 clipped to
+    0..2 (9 pixels), size 2 covers 0..1 (4 pixels)."""
+    vp = np.zeros((4, 4))
+    vp[0, 0] = vp[1, 1] = 1.0
+    vp[3, 3] = 1.0        # w = 1: window x = (x + 1) * 4
+    x = np.array([-0.99], np.float32)
+    y = np.array([-0.99], np.float32)
+    z = np.zeros(1, np.float32)
+    rgb = np.array([0x123456], np.uint32)
+    clear = oracle.clear_value(0)
+    for k, cover in ((2, [(0, 0), (1, 0), (0, 1), (1, 1)]), (3, [(0, 0), (1, 0), (0, 1), (1, 1)]),
+                     (4, [(xx, yy) for yy in range(3) for xx in range(3)])):
+        fb = oracle.raster_min(x, y, z, rgb, vp, 0.5, 2.0, 8, 8, point_size=k)
+        hit = sorted((int(p) % 8, int(p) // 8) for p in np.flatnonzero(fb != clear))
+        assert hit == sorted(cover), k
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5])
+def test_point_size_is_a_min_filter(oracle, k):
+    """Every point of size k writes its key into the k x k pixels around its
+    own pixel, so the framebuffer is a k x k minimum filter of the size-1
+    framebuffer (min is associative)."""
+    W, H = 40, 24
+    v, x, y, z, rgb = _random_scene(10 + k, 1500, W, H)
+    clear = np.uint64(oracle.clear_value(0))
+    fb1 = oracle.raster_min(x, y, z, rgb, v.vp, v.near, v.far, W, H).reshape(H, W)
+    fbk = oracle.raster_min(x, y, z, rgb, v.vp, v.near, v.far, W, H, point_size=k).reshape(H, W)
+    assert (fbk == _box(fb1, k, np.minimum, clear)).all()
+    assert (fbk != clear).sum() > (fb1 != clear).sum()
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_point_size_splat_sums_are_box_sums(oracle, k):
+    """With a window that accepts everything, every covered pixel adds the
+    point's colour once: the sums are k x k box sums of the size-1 sums."""
+    W, H = 40, 24
+    v, x, y, z, rgb = _random_scene(20 + k, 1500, W, H)
+    _, s1, _ = oracle.render_hq(x, y, z, rgb, v.vp, v.near, v.far, W, H, eps=(2 ** 20, 1))
+    _, sk, _ = oracle.render_hq(x, y, z, rgb, v.vp, v.near, v.far, W, H, eps=(2 ** 20, 1),
+                                point_size=k)
+    for ch in range(4):
+        a = s1[:, ch].reshape(H, W)
+        assert (sk[:, ch].reshape(H, W) == _box(a, k, np.add, np.uint64(0))).all()
+
+
+def test_point_size_splat_window_per_covered_pixel(oracle):
+    """Each covered pixel tests the point against its own nearest depth:
+    brute force over (point, covered pixel) pairs on a small scene."""
+    c, v = _small_terrain()
+    W, H, k = v.width, v.height, 3
+    x, y, z, rgb = c.x, c.y, c.z, c.rgb
+    o, s, z0 = oracle.depth_constants(v.vp, v.near, v.far, W, H)
+    keys, sums, _ = oracle.render_hq(x, y, z, rgb, v.vp, v.near, v.far, W, H, point_size=k)
+    pix, q = oracle.fragments(x, y, z, v.vp, v.near, v.far, W, H)
+    want = np.zeros((W * H, 4), np.uint64)
+    r = (k - 1) // 2
+    for i in np.flatnonzero(pix >= 0):
+        cx, cy = int(pix[i]) % W, int(pix[i]) // W
+        for yy in range(max(cy - r, 0), min(cy - r + k, H)):
+            for xx in range(max(cx - r, 0), min(cx - r + k, W)):
+                p = yy * W + xx
+                qmin = int(keys[p]) >> 24
+                if 100 * (int(q[i]) - qmin) <= qmin + z0:
+                    c = int(rgb[i])
+                    want[p] += np.array([c & 255, (c >> 8) & 255, (c >> 16) & 255, 1], np.uint64)
+    assert (sums == want).all()
+    assert (sums[:, 3] > 1).sum() > 50

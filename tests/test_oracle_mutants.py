@@ -31,14 +31,14 @@ MUTANTS = {
                                 "#define RZO_Q_RANGE ((double)((1ull << 40)))"),
     "pixel index transposed": ("*pix = (int64_t)py * c->w + px;", "*pix = (int64_t)px * c->h + py;"),
     "colour shift 23": ("key = (q << 24)", "key = (q << 23)"),
-    "max instead of min": ("if (key < fb[p])", "if (key > fb[p])"),
+    "max instead of min": ("if (key < fb[yy * w + xx])", "if (key > fb[yy * w + xx])"),
     "colour mask 16 bits": ("key = (q << 24) | ((uint64_t)rgb[i] & RZO_RGB_MASK);",
                             "key = (q << 24) | ((uint64_t)rgb[i] & 0xFFFFu);"),
     "eps window exclusive": ("(unsigned __int128)eps_den * (q - qmin) >\n",
                              "(unsigned __int128)eps_den * (q - qmin) >=\n"),
     "eps offset z0 dropped": ("((unsigned __int128)qmin + c.z0)", "((unsigned __int128)qmin)"),
-    "eps num and den swapped": ("if ((unsigned __int128)eps_den * (q - qmin) >\n                   (unsigned __int128)eps_num",
-                                "if ((unsigned __int128)eps_num * (q - qmin) >\n                   (unsigned __int128)eps_den"),
+    "eps num and den swapped": ("if ((unsigned __int128)eps_den * (q - qmin) >\n                           (unsigned __int128)eps_num",
+                                "if ((unsigned __int128)eps_num * (q - qmin) >\n                           (unsigned __int128)eps_den"),
     "piecewise base off by one": ("+ (uint64_t)floor((b[k + 1] - b[k]) * sb[k]) + 1;",
                                   "+ (uint64_t)floor((b[k + 1] - b[k]) * sb[k]);"),
     "piecewise range boundary exclusive": ("while (k + 1 < c->nr && d >= c->b[k + 1])",
@@ -48,13 +48,30 @@ MUTANTS = {
                                               "const double rhs = (double)eps_num * dq;"),
     "truncating average": ("uint64_t r = (2 * sums[4 * p + 0] + cnt) / (2 * cnt);",
                            "uint64_t r = sums[4 * p + 0] / cnt;"),
-    "green reads blue": ("sums[4 * p + 1] += (col >> 8) & 0xFFu;", "sums[4 * p + 1] += (col >> 16) & 0xFFu;"),
-    "count steps by two": ("sums[4 * p + 3] += 1;", "sums[4 * p + 3] += 2;"),
+    "green reads blue": ("sums[4 * pp + 1] += (col >> 8) & 0xFFu;",
+                         "sums[4 * pp + 1] += (col >> 16) & 0xFFu;"),
+    "count steps by two": ("sums[4 * pp + 3] += 1;", "sums[4 * pp + 3] += 2;"),
     "resolve clear drops background": (
         "img[p] = (uint32_t)(fb[p] & RZO_RGB_MASK);\n        fb[p] = RZO_DEPTH_ONES | ((uint64_t)bg & RZO_RGB_MASK);",
         "img[p] = (uint32_t)(fb[p] & RZO_RGB_MASK);\n        fb[p] = RZO_DEPTH_ONES;"),
     "splat background lost": ("img[p] = bg & 0xFFFFFFu;", "img[p] = 0;"),
     "splat sums not cleared": ("        sums[4 * p + 3] = 0;\n", ""),
+    "gl24 z from the w row": ("cz = cz + m[10] * z;", "cz = cz + m[14] * z;"),
+    "gl24 window offset dropped": ("zw = (nz + 1.0f) * 0.5f;", "zw = nz * 0.5f;"),
+    "gl24 truncates": ("*q = (uint64_t)floor((double)t + 0.5);", "*q = (uint64_t)floor((double)t);"),
+    "gl24 not clipped": ("        if (!(nz >= -1.0f && nz <= 1.0f))\n            return 0;\n", ""),
+    "gl24 23 bits": ("t = zw * 16777215.0f;", "t = zw * 8388607.0f;"),
+    "f32rev not complemented": ("*q = (uint64_t)(0xFFFFFFFFu - zr.u);", "*q = (uint64_t)zr.u;"),
+    "f32rev from far": ("zr.f = c->nearf / cw;", "zr.f = (float)c->far_ / cw;"),
+    "point square one short": ("*hi = c - r + k > size ? size : c - r + k;",
+                               "*hi = c - r + k - 1 > size ? size : c - r + k - 1;"),
+    "point square not centred": ("const int64_t r = (k - 1) / 2;", "const int64_t r = 0;"),
+    "point square radius rounded up": ("const int64_t r = (k - 1) / 2;", "const int64_t r = k / 2;"),
+    "splat footprint only the centre": (
+        "rzo_span(p % w, psize, w, &x0, &x1);\n        rzo_span(p / w, psize, h, &y0, &y1);\n        for (yy = y0; yy < y1; yy++) {",
+        "rzo_span(p % w, 1, w, &x0, &x1);\n        rzo_span(p / w, 1, h, &y0, &y1);\n        for (yy = y0; yy < y1; yy++) {"),
+    "splat window of the centre pixel": ("const uint64_t qmin = fb[pp] >> 24;",
+                                         "const uint64_t qmin = fb[p] >> 24;"),
 }
 
 PINS = [
@@ -78,6 +95,14 @@ PINS = [
     (T.test_hq_depth_pass_equals_basic, {}),
     (T.test_hq_huge_eps_averages_whole_pixel, {}),
     (T.test_hq_integer_window_matches_linear_depth, {}),
+    (T.test_gl24_window_depth_codes, {}),
+    (T.test_f32rev_codes, {}),
+    (T.test_gl24_codes_follow_the_perspective_depth, {}),
+    (T.test_depth_buffer_precision_at_one_kilometre, {}),
+    (T.test_point_size_corner_hand_case, {}),
+    *[(T.test_point_size_is_a_min_filter, {"k": k}) for k in (2, 3, 4, 5)],
+    *[(T.test_point_size_splat_sums_are_box_sums, {"k": k}) for k in (2, 3)],
+    (T.test_point_size_splat_window_per_covered_pixel, {}),
 ]
 
 
