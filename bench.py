@@ -335,6 +335,10 @@ def main():
     ap.add_argument("--workload", default="terrain50m")
     ap.add_argument("--path", choices=("direct", "sorted"), default="direct",
                     help="direct: one atomic per fragment; sorted: screen-tile sort first")
+    ap.add_argument("--point-size", type=int, default=1,
+                    help="points of k x k pixels (direct path)")
+    ap.add_argument("--depth", choices=("linear", "gl24", "f32rev"), default="linear",
+                    help="depth encoding; gl24 and f32rev have no splat frame")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--check", action="store_true", help="verify one frame against the oracle")
     ap.add_argument("--batch-points", type=int, default=100_000_000)
@@ -376,6 +380,34 @@ def main():
     log(f"[bench] n={n} {W}x{H} launch={rz.get_launch()}")
 
     ws = rz.new_workspace(n, W, H) if a.path == "sorted" else None
+    kinds = {"linear": rz.DEPTH_LINEAR, "gl24": rz.DEPTH_GL24, "f32rev": rz.DEPTH_F32REV}
+    depth = (kinds[a.depth], 0.0)
+    general = a.point_size > 1 or a.depth != "linear"
+    with_hq = a.depth == "linear"
+    if general and a.path != "direct":
+        raise SystemExit("--point-size and --depth apply to the direct path")
+
+    def step_general(ev):
+        # the same two frames through rasterize_points (k x k points, any
+        # depth encoding; the float encodings have no splat frame)
+        if ev:
+            ev[0].record()
+        rz.rasterize_points(pts, view, depth, point_size=a.point_size, fb=fb, keep_keys=True)
+        if ev:
+            ev[1].record()
+        rz.resolve_min(fb, npix, 0, img)
+        if ev:
+            ev[2].record()
+        if with_hq:
+            rz.rasterize_points(pts, view, depth, True, eps, a.point_size, fb=fb, acc=acc,
+                                keep_keys=True)
+        if ev:
+            ev[3].record()
+            ev[4].record()
+        if with_hq:
+            rz.resolve_hq(fb, acc, npix, 0, himg, status)
+        if ev:
+            ev[5].record()
 
     def step_sorted(ev):
         # the same two frames through the screen-sorted path (one call each)
@@ -399,6 +431,8 @@ def main():
     def step(ev):
         if a.path == "sorted":
             return step_sorted(ev)
+        if general:
+            return step_general(ev)
         # atomicMin frame: depth pass, then resolve + clear
         if ev:
             ev[0].record()
@@ -425,10 +459,14 @@ def main():
     if a.check:
         from oracle import oracle
         keys, oimg = oracle.render_atomicmin(cloud.x, cloud.y, cloud.z, cloud.rgb, view.vp,
-                                             view.near, view.far, W, H)
-        _, _, ohimg = oracle.render_hq(cloud.x, cloud.y, cloud.z, cloud.rgb, view.vp, view.near,
-                                       view.far, W, H, eps=eps)
-        ok = np.array_equal(rz.to_u32(img), oimg) and np.array_equal(rz.to_u32(himg), ohimg)
+                                             view.near, view.far, W, H, depth[0],
+                                             point_size=a.point_size)
+        ok = np.array_equal(rz.to_u32(img), oimg)
+        if with_hq:
+            _, _, ohimg = oracle.render_hq(cloud.x, cloud.y, cloud.z, cloud.rgb, view.vp,
+                                           view.near, view.far, W, H, eps=eps,
+                                           point_size=a.point_size)
+            ok = ok and np.array_equal(rz.to_u32(himg), ohimg)
         log(f"[bench] oracle check: {'bit-exact' if ok else 'MISMATCH'}")
         if not ok:
             raise SystemExit(1)
@@ -448,7 +486,15 @@ def main():
     if int(status.item()) != 0:
         raise SystemExit("splat count overflow reported")
 
-    if a.path == "sorted":
+    if general:
+        kern = {
+            "rasterize_points(atomicMin)": {"ms": avg[0], "bytes": 16 * n, "launches_per_step": 1},
+            "k_resolve_min": {"ms": avg[1], "bytes": 20 * npix, "launches_per_step": 1},
+        }
+        if with_hq:
+            kern["rasterize_points(HQ)"] = {"ms": avg[2], "bytes": 32 * n, "launches_per_step": 1}
+            kern["k_resolve_hq"] = {"ms": avg[4], "bytes": 44 * npix, "launches_per_step": 1}
+    elif a.path == "sorted":
         # whole calls; bytes = the sort's own HBM traffic per point: count
         # pass 16, coarse scatter 16 + 10, fine scatter 10 + 10, tile min 10
         # (+ splat pass 10)
@@ -477,11 +523,11 @@ def main():
         with open(tfile) as f:
             tr = json.load(f)
         rec = tr.get(a.workload if a.path == "direct" else f"{a.workload}:{a.path}", {}).get(dom)
-        if rec and rec.get("source_hash") == kernel_source_hash():
+        if rec and rec.get("source_hash") == kernel_source_hash(a.path):
             traffic = rec["bytes_per_launch"]
     out = {
         "metric": METRIC,
-        "value": round(2 * n / (ms_per_step * 1e-3) / 1e9, 4),
+        "value": round((2 if with_hq else 1) * n / (ms_per_step * 1e-3) / 1e9, 4),
         "unit": "Gpoints/s",
         "n_gpus": 1,
         "steps": a.steps,
@@ -493,13 +539,17 @@ def main():
         "dtype": "f32+f64->u64",
         "data": "synthetic",
         "config": {"workload": desc, "points": n, "width": W, "height": H,
-                   "eps": f"{eps[0]}/{eps[1]}", "depth_map": "linear 40-bit", "path": a.path},
+                   "eps": f"{eps[0]}/{eps[1]}",
+                   "depth_map": {"linear": "linear 40-bit", "gl24": "24-bit window depth",
+                                 "f32rev": "reversed float32 depth"}[a.depth],
+                   "point_size": a.point_size, "path": a.path},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(dk["GBps"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(dk["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic},
         "detail": {
             "atomicmin_gpts": round(n / ((avg[0] + avg[1]) * 1e-3) / 1e9, 3),
-            "hq_gpts": round(n / ((avg[2] + avg[3] + avg[4]) * 1e-3) / 1e9, 3),
+            "hq_gpts": (round(n / ((avg[2] + avg[3] + avg[4]) * 1e-3) / 1e9, 3)
+                        if with_hq else None),
             "kernels_ms": {k: round(v["ms"], 4) for k, v in kern.items()},
             "kernels_GBps": {k: round(v["GBps"], 1) for k, v in kern.items()},
             "evented_ms_per_step": round(float(avg.sum()), 4),
@@ -520,11 +570,19 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def kernel_source_hash():
+KERNEL_SOURCES = {
+    "direct": ("rz_kernels.hip", "rz_device.h", "rz_internal.h", "rz_api.cpp"),
+    "sorted": ("rz_sorted.hip", "rz_device.h", "rz_internal.h", "rz_api.cpp"),
+}
+
+
+def kernel_source_hash(path="direct"):
+    """Hash of the sources the measured kernels are built from: recorded HBM
+    traffic is reported only while it still matches."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1908_02681_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in KERNEL_SOURCES[path]:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

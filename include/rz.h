@@ -87,6 +87,19 @@ extern "C" {
    with d(q) = start[k] + (q - base[k]) * (1 / scale[k]). */
 #define RZ_DEPTH_PIECEWISE 2
 #define RZ_MAX_RANGES 8
+/* Encodings of a graphics depth buffer, for comparing precision with the
+   40-bit integers (sections 1 and 2.1); depth pass only (rasterize_atomicmin
+   and rasterize_points without hq; any other call returns RZ_EINVAL):
+   RZ_DEPTH_GL24: z_ndc = clip.z / clip.w in single precision (row 2 of the
+   float matrix, same operation order as the other rows), z_win =
+   (z_ndc + 1) * 0.5, depth = round(z_win * (2^24 - 1)) (ties up) as a 24-bit
+   integer; fragments with z_ndc outside [-1, 1] are discarded.
+   RZ_DEPTH_F32REV: z_rev = (float)near / clip.w in single precision (1 at
+   the near plane, towards 0 far away), depth = 2^32 - 1 - (bit pattern of
+   z_rev), so that nearer stays smaller.
+   Both keep the [near, far) cull on the double-precision depth. */
+#define RZ_DEPTH_GL24 3
+#define RZ_DEPTH_F32REV 4
 
 typedef struct rz_points {
     const float *x;        /* device, n floats */
@@ -126,7 +139,8 @@ typedef struct rz_hq_params {
  * Rasterization via atomicMin (section 2.1), then resolve.
  *   pts      points (device planes).
  *   view     camera and framebuffer size (host struct, read during the call).
- *   depth    depth map (host struct).
+ *   depth    depth map (host struct); any kind, RZ_DEPTH_GL24 and
+ *            RZ_DEPTH_F32REV included.
  *   background  24-bit colour of empty pixels (upper 8 bits ignored).
  *   fb       device, width*height uint64.  Precondition: in the cleared state
  *            0xffffffffff000000 | background (rz_clear, or a previous resolve).
@@ -193,6 +207,28 @@ int rasterize_sorted(const rz_points *pts, const rz_view *view,
                      int64_t workspace_bytes, uint32_t flags, void *stream);
 
 /*
+ * Points larger than one pixel (the paper relates cost to the number of
+ * fragments, section 3), and the depth encodings RZ_DEPTH_GL24 / _F32REV.
+ * A point of size k (1 <= k <= 16) is culled by its centre as usual and then
+ * covers the pixels px - r .. px - r + k - 1 and py - r .. py - r + k - 1,
+ * r = (k - 1) / 2, around its pixel (px, py), clipped to the screen; every
+ * covered pixel takes the point's key in the depth pass, and with hq every
+ * covered pixel tests the point against its own nearest depth.
+ *   hq       NULL: depth pass + resolve as rasterize_atomicmin; else the three
+ *            passes of rasterize_hq_splat (depth maps 0-2 only).
+ *   Other arguments as for rasterize_atomicmin / rasterize_hq_splat (acc and
+ *   status are used only with hq).  point_size 1 with an integer depth map
+ *   runs the same kernels as those calls.
+ * Errors: RZ_EINVAL (also point_size out of range, hq with a float depth
+ * encoding), RZ_EDEPTHRANGE, RZ_EHIP.
+ */
+int rasterize_points(const rz_points *pts, const rz_view *view,
+                     const rz_depth_map *depth, const rz_hq_params *hq,
+                     int32_t point_size, uint32_t background, uint64_t *fb,
+                     uint64_t *acc, uint32_t *img, uint32_t *status,
+                     uint32_t flags, void *stream);
+
+/*
  * Building blocks (section 2.1 resolve, section 2.2 third pass).
  * rz_clear: fb[p] = 0xffffffffff000000 | (background & 0xffffff) for
  *   p < npix, and acc[0 .. 2*npix) = 0 when acc is not NULL.
@@ -240,7 +276,11 @@ typedef struct rz_launch {
     int32_t xcd_remap;
     int32_t bin;
 } rz_launch;
-int rz_set_launch(const rz_launch *launch);   /* RZ_EINVAL if out of range */
+/* Sets the launch shape of both point passes of the one-view calls and the
+   server (RZ_EINVAL if out of range); NULL restores the library defaults
+   (depth pass 64 threads x 16 points, splat pass 128 x 8, early-out, no XCD
+   remap, per-wave tiles).  rz_get_launch reports the depth pass's shape. */
+int rz_set_launch(const rz_launch *launch);
 int rz_get_launch(rz_launch *launch);
 
 /* ---- batched multi-view rendering ------------------------------------ */

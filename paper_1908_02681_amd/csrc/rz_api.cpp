@@ -20,13 +20,16 @@ int hip_fail(hipError_t e)
     return RZ_EHIP;
 }
 
-static Tune g_tune;   // launch shape of the plain calls
+static Tune g_tune;              // launch shape of the depth pass
+static Tune g_tune_hq = kHqTune;  // and of the splat accumulate pass
 
 const Tune &current_tune() { return g_tune; }
+const Tune &current_tune_hq() { return g_tune_hq; }
 
 constexpr double kQRange = 1099511627775.0;   // 2^40 - 1
 constexpr int64_t kMaxPoints = 4294966784ll;  // 2^32 - 2^9
 constexpr int32_t kMaxSide = 32768;
+constexpr int32_t kMaxPointSize = 16;
 
 static bool finite_all(const double *v, int n)
 {
@@ -107,9 +110,13 @@ int make_proj(const rz_view *v, const rz_depth_map *dm, Proj *P)
         P->nr = nr;
         o = 0.0;
         s = 1.0;
+    } else if (dm->kind == RZ_DEPTH_GL24 || dm->kind == RZ_DEPTH_F32REV) {
+        o = 0.0;   // no integer map: the kernels encode the float depth
+        s = 1.0;
     } else {
         return RZ_EINVAL;
     }
+    P->zkind = dm->kind == RZ_DEPTH_GL24 || dm->kind == RZ_DEPTH_F32REV ? dm->kind : 0;
     if (dm->kind != RZ_DEPTH_PIECEWISE)
         P->nr = 0;
     if (!isfinite(s) || !(s > 0.0))
@@ -121,6 +128,9 @@ int make_proj(const rz_view *v, const rz_depth_map *dm, Proj *P)
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 4; ++c)
             P->m[4 * r + c] = (float)v->vp[4 * rows[r] + c];
+    for (int c = 0; c < 4; ++c)
+        P->mz[c] = (float)v->vp[8 + c];
+    P->nearf = (float)v->near_;
     P->fw = (float)v->width;
     P->fh = (float)v->height;
     P->hw = 0.5f * P->fw;
@@ -145,7 +155,7 @@ int check_hq(const rz_hq_params *hq, const Proj &P, uint32_t *num, uint32_t *den
         n = hq->eps_num;
         d = hq->eps_den;
     }
-    if (d < 1 || d > (1u << 20) || n > (1u << 20))
+    if (d < 1 || d > (1u << 20) || n > (1u << 20) || P.zkind != 0)
         return RZ_EINVAL;
     // num * (2^40 + z0) < 2^63, and den * 2^40 < 2^63 holds by den <= 2^20
     // (the piecewise window is tested in double precision instead)
@@ -177,7 +187,8 @@ int rasterize_atomicmin(const rz_points *pts, const rz_view *view, const rz_dept
         return RZ_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const Pts p{pts->x, pts->y, pts->z, pts->rgb, pts->n};
-    hipError_t e = launch_raster_min(p, P, fb, g_tune, s);
+    hipError_t e = P.zkind ? launch_raster_points(p, P, 1, fb, s)
+                           : launch_raster_min(p, P, fb, g_tune, s);
     if (e != hipSuccess)
         return hip_fail(e);
     if (!(flags & RZ_KEEP_KEYS)) {
@@ -207,7 +218,7 @@ int rasterize_hq_splat(const rz_points *pts, const rz_view *view, const rz_depth
     const Pts p{pts->x, pts->y, pts->z, pts->rgb, pts->n};
     hipError_t e = launch_raster_min(p, P, fb, g_tune, s);
     if (e == hipSuccess)
-        e = launch_hq_accum(p, P, num, den, fb, acc, g_tune, s);
+        e = launch_hq_accum(p, P, num, den, fb, acc, g_tune_hq, s);
     if (e == hipSuccess && !(flags & RZ_KEEP_KEYS))
         e = launch_resolve_hq(fb, acc, (int64_t)P.width * P.height, background, img, status, s);
     return e == hipSuccess ? RZ_OK : hip_fail(e);
@@ -228,7 +239,39 @@ int rz_hq_accumulate(const rz_points *pts, const rz_view *view, const rz_depth_m
     if (!fb || !acc)
         return RZ_EINVAL;
     const Pts p{pts->x, pts->y, pts->z, pts->rgb, pts->n};
-    hipError_t e = launch_hq_accum(p, P, num, den, fb, acc, g_tune, (hipStream_t)stream);
+    hipError_t e = launch_hq_accum(p, P, num, den, fb, acc, g_tune_hq, (hipStream_t)stream);
+    return e == hipSuccess ? RZ_OK : hip_fail(e);
+}
+
+int rasterize_points(const rz_points *pts, const rz_view *view, const rz_depth_map *depth,
+                     const rz_hq_params *hq, int32_t point_size, uint32_t background,
+                     uint64_t *fb, uint64_t *acc, uint32_t *img, uint32_t *status,
+                     uint32_t flags, void *stream)
+{
+    int rc = check_points(pts);
+    if (rc)
+        return rc;
+    Proj P;
+    if ((rc = make_proj(view, depth, &P)))
+        return rc;
+    uint32_t num = 1, den = 100;
+    if (hq && (rc = check_hq(hq, P, &num, &den)))
+        return rc;
+    if (point_size < 1 || point_size > kMaxPointSize || !fb || (hq && !acc) ||
+        (flags & ~RZ_KEEP_KEYS) || (!(flags & RZ_KEEP_KEYS) && !img))
+        return RZ_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const Pts p{pts->x, pts->y, pts->z, pts->rgb, pts->n};
+    const bool general = point_size > 1 || P.zkind != 0;
+    hipError_t e = general ? launch_raster_points(p, P, point_size, fb, s)
+                           : launch_raster_min(p, P, fb, g_tune, s);
+    if (e == hipSuccess && hq)
+        e = general ? launch_hq_points(p, P, point_size, num, den, fb, acc, s)
+                    : launch_hq_accum(p, P, num, den, fb, acc, g_tune_hq, s);
+    const int64_t npix = (int64_t)P.width * P.height;
+    if (e == hipSuccess && !(flags & RZ_KEEP_KEYS))
+        e = hq ? launch_resolve_hq(fb, acc, npix, background, img, status, s)
+               : launch_resolve_min(fb, npix, background, img, s);
     return e == hipSuccess ? RZ_OK : hip_fail(e);
 }
 
@@ -259,8 +302,11 @@ int rz_resolve_hq(uint64_t *fb, uint64_t *acc, int64_t npix, uint32_t background
 
 int rz_set_launch(const rz_launch *l)
 {
-    if (!l)
-        return RZ_EINVAL;
+    if (!l) {   // back to the library defaults
+        g_tune = Tune();
+        g_tune_hq = kHqTune;
+        return RZ_OK;
+    }
     if (!(l->block == 64 || l->block == 128 || l->block == 256 || l->block == 512))
         return RZ_EINVAL;
     if (!(l->ppt == 4 || l->ppt == 8 || l->ppt == 16))
@@ -272,6 +318,7 @@ int rz_set_launch(const rz_launch *l)
     g_tune.early_out = l->early_out;
     g_tune.xcd_remap = l->xcd_remap;
     g_tune.bin = l->bin;
+    g_tune_hq = g_tune;
     return RZ_OK;
 }
 

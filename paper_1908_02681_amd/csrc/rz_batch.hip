@@ -60,7 +60,7 @@ struct MvResolve {
 
 // Depth passes of views[0 .. nv) over one chunk: the points are loaded
 // once and stay in registers while each view is rasterized in turn.
-template <int PPT, bool VEC, bool XCD, int BIN>
+template <int PPT, bool VEC, bool XCD, int BIN, bool PW>
 __global__ void __launch_bounds__(512) k_mv_raster_min(Pts p, const MvView *__restrict__ views,
                                                        int32_t nv, int64_t nchunks)
 {
@@ -77,12 +77,12 @@ __global__ void __launch_bounds__(512) k_mv_raster_min(Pts p, const MvView *__re
     for (int32_t k = 0; k < nv; ++k) {
         const Proj P = views[k].P;
         if (BIN == kBinWave) {
-            raster_chunk_wave<PPT>(P, views[k].fb, x, y, z, c, in,
+            raster_chunk_wave<PPT, PW>(P, views[k].fb, x, y, z, c, in,
                                    s_waves + (threadIdx.x >> 6) * kWaveTileWords);
         } else {
             if (BIN == kBinBlock && k > 0)
                 __syncthreads();   // previous view's tile fully flushed
-            raster_chunk<PPT, true, BIN == kBinBlock>(P, views[k].fb, x, y, z, c, in, s_tile,
+            raster_chunk<PPT, true, BIN == kBinBlock, PW>(P, views[k].fb, x, y, z, c, in, s_tile,
                                                       s_box);
         }
     }
@@ -191,8 +191,11 @@ hipError_t mv_launch_ppt(bool hq, bool pw, const Pts &p, const MvView *views, in
     else if (hq)
         hipLaunchKernelGGL((k_mv_hq_accum<PPT, VEC, XCD, BIN, false>), dim3((uint32_t)grid),
                            dim3(t.block), lds, s, p, views, nv, nchunks);
+    else if (pw)
+        hipLaunchKernelGGL((k_mv_raster_min<PPT, VEC, XCD, BIN, true>), dim3((uint32_t)grid),
+                           dim3(t.block), lds, s, p, views, nv, nchunks);
     else
-        hipLaunchKernelGGL((k_mv_raster_min<PPT, VEC, XCD, BIN>), dim3((uint32_t)grid),
+        hipLaunchKernelGGL((k_mv_raster_min<PPT, VEC, XCD, BIN, false>), dim3((uint32_t)grid),
                            dim3(t.block), lds, s, p, views, nv, nchunks);
     return hipGetLastError();
 }
@@ -276,6 +279,7 @@ struct rz_batch {
     int32_t nviews = 0;
     int32_t nhq = 0;
     bool hq_pw = false;                   // some splatting view uses a piecewise map
+    bool any_pw = false;                  // some view uses a piecewise map
     int64_t resolve_blocks = 0;
     void *dmem = nullptr;                 // one allocation: tables + checksum word
     MvView *d_raster = nullptr;           // all views
@@ -296,8 +300,8 @@ hipError_t enqueue(rz_batch *b, hipStream_t s)
     const int32_t K = b->opts.views_per_group;
     hipError_t e = hipSuccess;
     for (int32_t g = 0; g < b->nviews && e == hipSuccess; g += K)
-        e = mv_launch(false, false, b->pts, b->d_raster + g, std::min(K, b->nviews - g), b->tune,
-                      s);
+        e = mv_launch(false, b->any_pw, b->pts, b->d_raster + g, std::min(K, b->nviews - g),
+                      b->tune, s);
     for (int32_t g = 0; g < b->nhq && e == hipSuccess; g += K)
         e = mv_launch(true, b->hq_pw, b->pts, b->d_accum + g, std::min(K, b->nhq - g), b->tune,
                       s);
@@ -384,6 +388,8 @@ int rz_batch_plan(const rz_points *pts, const rz_batch_view *views, int32_t nvie
         memset(&m, 0, sizeof(m));
         if ((rc = make_proj(&v.view, &v.depth, &m.P)))
             return rc;
+        if (m.P.zkind != 0)   // float depth encodings: one-view calls only
+            return RZ_EINVAL;
         const bool hq = v.mode == RZ_MODE_HQ;
         if (!hq && v.mode != RZ_MODE_ATOMICMIN)
             return RZ_EINVAL;
@@ -428,6 +434,8 @@ int rz_batch_plan(const rz_points *pts, const rz_batch_view *views, int32_t nvie
     b->nhq = (int32_t)accum.size();
     for (const MvView &m : accum)
         b->hq_pw = b->hq_pw || m.P.nr > 0;
+    for (const MvView &m : raster)
+        b->any_pw = b->any_pw || m.P.nr > 0;
     b->resolve_blocks = blocks;
     b->opts = o;
     b->tune = tune_of(o.launch);

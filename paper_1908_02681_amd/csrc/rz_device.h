@@ -52,12 +52,10 @@ __device__ __forceinline__ T ldnt(const T *p) { return __builtin_nontemporal_loa
 template <typename T>
 __device__ __forceinline__ void stnt(T v, T *p) { __builtin_nontemporal_store(v, p); }
 
-// 0 <= t < 2^40, integral: split into two exact 32-bit halves.
+// 0 <= t < 2^52, integral: t + 2^52 is exact and its 52 mantissa bits are t.
 __device__ __forceinline__ uint64_t to_u64(double t)
 {
-    const uint32_t hi = (uint32_t)(t * 0x1p-32);
-    const uint32_t lo = (uint32_t)(t - (double)hi * 0x1p32);
-    return ((uint64_t)hi << 32) | lo;
+    return (uint64_t)__double_as_longlong(t + 0x1p52) & 0xFFFFFFFFFFFFFull;
 }
 
 // Piecewise depth map (section 2.1, sub-ranges with their own precision):
@@ -98,10 +96,12 @@ __device__ __forceinline__ bool in_window(const Proj &P, uint32_t eps_num, uint3
     return lhs <= rhs;
 }
 
-// The fragment of one point: pixel coordinates and 40-bit depth (section
-// 2.1).  Returns false when the point is discarded.
-__device__ __forceinline__ bool fragment(const Proj &P, float x, float y, float z,
-                                         uint32_t &px, uint32_t &py, uint64_t &q)
+// Pixel of one point (section 2.1's projection in single precision) and its
+// clip w.  Returns false when the point is culled (w <= 0 or off screen).
+// Straight-line code: the pixel of a culled point is 0, never a conversion
+// of an out-of-range float.
+__device__ __forceinline__ bool project(const Proj &P, float x, float y, float z, uint32_t &px,
+                                        uint32_t &py, float &cw)
 {
     float cx = P.m[0] * x;
     cx = cx + P.m[1] * y;
@@ -111,36 +111,83 @@ __device__ __forceinline__ bool fragment(const Proj &P, float x, float y, float 
     cy = cy + P.m[5] * y;
     cy = cy + P.m[6] * z;
     cy = cy + P.m[7];
-    float cw = P.m[8] * x;
+    cw = P.m[8] * x;
     cw = cw + P.m[9] * y;
     cw = cw + P.m[10] * z;
     cw = cw + P.m[11];
-    if (!(cw > 0.0f))
-        return false;
     const float nx = cx / cw;
     const float ny = cy / cw;
     const float fx = (nx + 1.0f) * P.hw;
     const float fy = (ny + 1.0f) * P.hh;
-    if (!(fx >= 0.0f && fx < P.fw && fy >= 0.0f && fy < P.fh))
-        return false;
-    px = (uint32_t)(int32_t)fx;
-    py = (uint32_t)(int32_t)fy;
+    const bool vis = cw > 0.0f && fx >= 0.0f && fx < P.fw && fy >= 0.0f && fy < P.fh;
+    px = (uint32_t)(int32_t)(vis ? fx : 0.0f);
+    py = (uint32_t)(int32_t)(vis ? fy : 0.0f);
+    return vis;
+}
 
-    // depth in double precision (section 1, section 2.1)
+// Depth in double precision (section 1, section 2.1): row 3 of VP.
+__device__ __forceinline__ double depth_of(const Proj &P, float x, float y, float z)
+{
     double d = P.v[0] * (double)x;
     d = d + P.v[1] * (double)y;
     d = d + P.v[2] * (double)z;
     d = d + P.v[3];
+    return d;
+}
+
+// The fragment of one point: pixel coordinates and 40-bit depth (section
+// 2.1).  Returns false when the point is discarded; q is then meaningless.
+// Integer depth maps only (P.zkind == 0).  PW = false: linear or scale map
+// only (P.nr == 0), so the piecewise tables are never read; PW = true serves
+// every integer map.  Straight-line code apart from one wave-uniform skip
+// of the depth when no lane of the wave is on screen.
+template <bool PW>
+__device__ __forceinline__ bool fragment(const Proj &P, float x, float y, float z,
+                                         uint32_t &px, uint32_t &py, uint64_t &q)
+{
+    float cw;
+    const bool vis = project(P, x, y, z, px, py, cw);
+    q = 0;
+    if (!__any(vis))
+        return false;
+    const double d = depth_of(P, x, y, z);
+    const bool in_range = d >= P.near_ && d < P.far_;
+    if (!PW || P.nr == 0)
+        q = to_u64(fmin(floor((d - P.o) * P.s), kQMax));   // d < near gives garbage, unused
+    else
+        q = piecewise_q(P, in_range ? d : P.near_);
+    return vis && in_range;
+}
+
+// fragment() for every depth encoding: the integer maps, the 24-bit window
+// depth of the perspective matrix (RZ_DEPTH_GL24) and the complemented
+// reversed float depth (RZ_DEPTH_F32REV).
+__device__ __forceinline__ bool fragment_any(const Proj &P, float x, float y, float z,
+                                             uint32_t &px, uint32_t &py, uint64_t &q)
+{
+    if (P.zkind == 0)
+        return fragment<true>(P, x, y, z, px, py, q);
+    float cw;
+    if (!project(P, x, y, z, px, py, cw))
+        return false;
+    const double d = depth_of(P, x, y, z);
     if (!(d >= P.near_ && d < P.far_))
         return false;
-    if (P.nr == 0) {
-        double tf = floor((d - P.o) * P.s);
-        if (tf > kQMax)
-            tf = kQMax;
-        q = to_u64(tf);
-    } else {
-        q = piecewise_q(P, d);
+    if (P.zkind == RZ_DEPTH_F32REV) {
+        const float zr = P.nearf / cw;
+        q = 0xFFFFFFFFull - (uint64_t)__float_as_uint(zr);
+        return true;
     }
+    float cz = P.mz[0] * x;
+    cz = cz + P.mz[1] * y;
+    cz = cz + P.mz[2] * z;
+    cz = cz + P.mz[3];
+    const float nz = cz / cw;
+    if (!(nz >= -1.0f && nz <= 1.0f))
+        return false;
+    const float zw = (nz + 1.0f) * 0.5f;
+    const float t = zw * 16777215.0f;
+    q = (uint64_t)(uint32_t)floor((double)t + 0.5);
     return true;
 }
 
@@ -279,7 +326,7 @@ __device__ __forceinline__ Box block_box(const uint32_t (&px)[PPT], const uint32
 // With BIN every thread of the workgroup must call it; it returns with the
 // workgroup past its last barrier but threads possibly still flushing, so a
 // caller that reuses s_tile or s_box must synchronise first.
-template <int PPT, bool EARLY, bool BIN>
+template <int PPT, bool EARLY, bool BIN, bool PW>
 __device__ __forceinline__ void raster_chunk(const Proj &P, uint64_t *__restrict__ fb,
                                              const float (&x)[PPT], const float (&y)[PPT],
                                              const float (&z)[PPT], const uint32_t (&c)[PPT],
@@ -293,7 +340,7 @@ __device__ __forceinline__ void raster_chunk(const Proj &P, uint64_t *__restrict
     for (int j = 0; j < PPT; ++j) {
         uint64_t q = 0;
         uint32_t a = 0, b = 0;
-        live[j] = in[j] && fragment(P, x[j], y[j], z[j], a, b, q);
+        live[j] = fragment<PW>(P, x[j], y[j], z[j], a, b, q) & in[j];
         px[j] = a;
         py[j] = b;
         pix[j] = b * (uint32_t)P.width + a;
@@ -421,7 +468,7 @@ __device__ __forceinline__ Box wave_box(const uint32_t (&px)[PPT], const uint32_
 // raster_chunk with BIN, but every wave gathers its own 64 * PPT fragments
 // in its own 8 KiB slice (w_tile) and flushes it, so no workgroup barrier
 // is needed.  Same result bits as raster_chunk.
-template <int PPT>
+template <int PPT, bool PW>
 __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__restrict__ fb,
                                                   const float (&x)[PPT], const float (&y)[PPT],
                                                   const float (&z)[PPT], const uint32_t (&c)[PPT],
@@ -434,7 +481,7 @@ __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__res
     for (int j = 0; j < PPT; ++j) {
         uint64_t q = 0;
         uint32_t a = 0, b = 0;
-        live[j] = in[j] && fragment(P, x[j], y[j], z[j], a, b, q);
+        live[j] = fragment<PW>(P, x[j], y[j], z[j], a, b, q) & in[j];
         px[j] = a;
         py[j] = b;
         pix[j] = b * (uint32_t)P.width + a;
@@ -536,7 +583,7 @@ __device__ __forceinline__ void accum_chunk(const Proj &P, uint32_t eps_num, uin
     for (int j = 0; j < PPT; ++j) {
         uint32_t a = 0, b = 0;
         uint64_t qq = 0;
-        ok[j] = in[j] && fragment(P, x[j], y[j], z[j], a, b, qq);
+        ok[j] = fragment<PW>(P, x[j], y[j], z[j], a, b, qq) & in[j];
         px[j] = a;
         py[j] = b;
         pix[j] = b * (uint32_t)P.width + a;
@@ -642,7 +689,7 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
     for (int j = 0; j < PPT; ++j) {
         uint32_t a = 0, b = 0;
         uint64_t qq = 0;
-        ok[j] = in[j] && fragment(P, x[j], y[j], z[j], a, b, qq);
+        ok[j] = fragment<PW>(P, x[j], y[j], z[j], a, b, qq) & in[j];
         px[j] = a;
         py[j] = b;
         pix[j] = b * (uint32_t)P.width + a;

@@ -13,6 +13,10 @@ struct Proj {
     float m[12];          // rows 0, 1 and 3 of (float)VP, row-major
     float fw, fh;         // framebuffer size as float
     float hw, hh;         // half of it
+    float mz[4];          // row 2 of (float)VP (window depth encodings)
+    float nearf;          // near as float (reversed float depth)
+    int32_t zkind;        // 0: integer map (linear, scale, piecewise);
+                          // RZ_DEPTH_GL24 or RZ_DEPTH_F32REV otherwise
     double v[4];          // row 3 of VP in double: the depth row
     double near_, far_;
     double o, s;          // q = floor((d - o) * s)
@@ -27,7 +31,9 @@ struct Proj {
     uint64_t rbase[9];    // first integer of each range; rbase[nr] = 2^40 - 1
 };
 
-// Launch shape of the point kernels.
+// Launch shape of the point kernels.  The defaults are those of the depth
+// pass; the splat accumulate pass defaults to kHqTune (measured on the
+// 50M-point terrain: 128 threads, 8 points each).
 struct Tune {
     int block = 64;        // threads per workgroup: 64, 128, 256 or 512
     int ppt = 16;          // points per thread: 4, 8 or 16
@@ -35,6 +41,8 @@ struct Tune {
     int xcd_remap = 0;     // give each XCD a contiguous range of chunks
     int bin = 2;           // 0 none, 1 workgroup LDS tile, 2 per-wave LDS tile
 };
+
+constexpr Tune kHqTune = {128, 8, 1, 0, 2};
 
 constexpr uint64_t kDepthOnes = 0xFFFFFFFFFF000000ull;
 constexpr uint64_t kRgbMask = 0xFFFFFFull;
@@ -56,5 +64,11 @@ hipError_t launch_resolve_min(uint64_t *fb, int64_t npix, uint32_t bg, uint32_t 
 hipError_t launch_resolve_hq(uint64_t *fb, uint64_t *acc, int64_t npix, uint32_t bg,
                              uint32_t *img, uint32_t *status, hipStream_t s);
 hipError_t launch_clear(uint64_t *fb, uint64_t *acc, int64_t npix, uint32_t bg, hipStream_t s);
+// Points of size k >= 1 and every depth encoding (one fragment per covered
+// pixel, early-out plus global atomics).
+hipError_t launch_raster_points(const Pts &p, const Proj &P, int32_t k, uint64_t *fb,
+                                hipStream_t s);
+hipError_t launch_hq_points(const Pts &p, const Proj &P, int32_t k, uint32_t eps_num,
+                            uint32_t eps_den, const uint64_t *fb, uint64_t *acc, hipStream_t s);
 
 }  // namespace rz

@@ -19,7 +19,7 @@ using namespace dev;
 
 // Depth pass of section 2.1 for one view: one workgroup per chunk of
 // blockDim * PPT consecutive points.
-template <int PPT, bool VEC, bool EARLY, bool XCD, int BIN>
+template <int PPT, bool VEC, bool EARLY, bool XCD, int BIN, bool PW>
 __global__ void __launch_bounds__(512) k_raster_min(Pts p, Proj P, uint64_t *__restrict__ fb,
                                                     int64_t nchunks)
 {
@@ -34,10 +34,10 @@ __global__ void __launch_bounds__(512) k_raster_min(Pts p, Proj P, uint64_t *__r
     bool in[PPT];
     load_points<PPT, VEC>(p, chunk * (int64_t)blockDim.x * PPT, x, y, z, c, in);
     if (BIN == kBinWave)
-        raster_chunk_wave<PPT>(P, fb, x, y, z, c, in,
+        raster_chunk_wave<PPT, PW>(P, fb, x, y, z, c, in,
                                s_waves + (threadIdx.x >> 6) * kWaveTileWords);
     else
-        raster_chunk<PPT, EARLY, BIN == kBinBlock>(P, fb, x, y, z, c, in, s_tile, s_box);
+        raster_chunk<PPT, EARLY, BIN == kBinBlock, PW>(P, fb, x, y, z, c, in, s_tile, s_box);
 }
 
 // Accumulation pass of section 2.2 for one view.
@@ -143,7 +143,7 @@ size_t wave_lds(int bin, int block)
     return bin == kBinWave ? (size_t)(block / 64) * kWaveTileWords * sizeof(uint64_t) : 0;
 }
 
-template <int PPT, bool VEC, bool EARLY, int BIN>
+template <int PPT, bool VEC, bool EARLY, int BIN, bool PW>
 hipError_t raster_min_ppt(const Pts &p, const Proj &P, uint64_t *fb, const Tune &t,
                           hipStream_t s)
 {
@@ -151,10 +151,11 @@ hipError_t raster_min_ppt(const Pts &p, const Proj &P, uint64_t *fb, const Tune 
     const size_t lds = wave_lds(BIN, t.block);
     if (t.xcd_remap) {
         const int64_t grid = (nchunks + kXcds - 1) / kXcds * kXcds;
-        hipLaunchKernelGGL((k_raster_min<PPT, VEC, EARLY, true, BIN>), dim3((uint32_t)grid),
+        hipLaunchKernelGGL((k_raster_min<PPT, VEC, EARLY, true, BIN, PW>), dim3((uint32_t)grid),
                            dim3(t.block), lds, s, p, P, fb, nchunks);
     } else {
-        hipLaunchKernelGGL((k_raster_min<PPT, VEC, EARLY, false, BIN>), dim3((uint32_t)nchunks),
+        hipLaunchKernelGGL((k_raster_min<PPT, VEC, EARLY, false, BIN, PW>),
+                           dim3((uint32_t)nchunks),
                            dim3(t.block), lds, s, p, P, fb, nchunks);
     }
     return hipGetLastError();
@@ -182,17 +183,25 @@ bool planes_aligned(const Pts &p)
     return aligned16(p.x) && aligned16(p.y) && aligned16(p.z) && aligned16(p.rgb);
 }
 
+template <int PPT, bool VEC, bool PW>
+hipError_t raster_min_bin(const Pts &p, const Proj &P, uint64_t *fb, const Tune &t,
+                          hipStream_t s)
+{
+    switch (t.bin) {
+    case kBinBlock: return raster_min_ppt<PPT, VEC, true, kBinBlock, PW>(p, P, fb, t, s);
+    case kBinWave: return raster_min_ppt<PPT, VEC, true, kBinWave, PW>(p, P, fb, t, s);
+    default:
+        return t.early_out ? raster_min_ppt<PPT, VEC, true, kBinNone, PW>(p, P, fb, t, s)
+                           : raster_min_ppt<PPT, VEC, false, kBinNone, PW>(p, P, fb, t, s);
+    }
+}
+
 template <int PPT, bool VEC>
 hipError_t raster_min_vec(const Pts &p, const Proj &P, uint64_t *fb, const Tune &t,
                           hipStream_t s)
 {
-    switch (t.bin) {
-    case kBinBlock: return raster_min_ppt<PPT, VEC, true, kBinBlock>(p, P, fb, t, s);
-    case kBinWave: return raster_min_ppt<PPT, VEC, true, kBinWave>(p, P, fb, t, s);
-    default:
-        return t.early_out ? raster_min_ppt<PPT, VEC, true, kBinNone>(p, P, fb, t, s)
-                           : raster_min_ppt<PPT, VEC, false, kBinNone>(p, P, fb, t, s);
-    }
+    return P.nr ? raster_min_bin<PPT, VEC, true>(p, P, fb, t, s)
+                : raster_min_bin<PPT, VEC, false>(p, P, fb, t, s);
 }
 
 template <int PPT>

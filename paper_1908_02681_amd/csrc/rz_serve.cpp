@@ -36,6 +36,7 @@ int make_proj(const rz_view *v, const rz_depth_map *dm, Proj *P);
 int check_hq(const rz_hq_params *hq, const Proj &P, uint32_t *num, uint32_t *den);
 int hip_fail(hipError_t e);
 const Tune &current_tune();
+const Tune &current_tune_hq();
 
 namespace {
 
@@ -187,7 +188,7 @@ int launch(rz_server *s, Req *r)
         e = launch_raster_min(p, r->P, fb, t, st);
     if (r->r.mode == RZ_MODE_HQ) {
         if (e == hipSuccess)
-            e = launch_hq_accum(p, r->P, r->num, r->den, fb, acc, t, st);
+            e = launch_hq_accum(p, r->P, r->num, r->den, fb, acc, current_tune_hq(), st);
         if (e == hipSuccess)
             e = launch_resolve_hq(fb, acc, (int64_t)r->npix, r->r.background, r->r.img, status,
                                   st);
@@ -304,6 +305,8 @@ int validate(rz_server *s, const rz_request *q, Req *r)
     int rc = make_proj(&q->view, &q->depth, &r->P);
     if (rc)
         return rc;
+    if (r->P.zkind != 0)   // float depth encodings: one-view calls only
+        return RZ_EINVAL;
     if (q->mode == RZ_MODE_HQ) {
         rz_hq_params hp = q->hq;
         if (hp.eps_den == 0) {

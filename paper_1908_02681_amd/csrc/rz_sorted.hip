@@ -2,25 +2,31 @@
 // (section 2.1) and splat accumulation (section 2.2) for clouds in no
 // particular order, where one global atomic per fragment would hit random
 // framebuffer lines.  The fragments are first sorted by 32x32 screen tile in
-// two scatter levels, so that every write of the sort is part of a long run:
-//   A   k_sort_count   histogram of fragment tiles (LDS per workgroup, then
-//                      one global add per tile)
-//   B   k_sort_scan    tile bucket starts, coarse bucket starts and the
-//                      work lists of passes C2, D and E
-//   C1  k_sort_coarse  fragments again, each workgroup step ranks its 8192
-//                      points by coarse bucket (256x256 pixels) in LDS and
-//                      reserves one run per bucket: key + pixel in bucket
-//   C2  k_sort_fine    per chunk of a coarse bucket: the same into the 64
-//                      tile buckets it covers: key + pixel in tile
+// two scatter levels, every write of the sort part of a run:
+//   A   k_sort_count   per workgroup range of points: fragments per tile
+//                      (LDS histogram, added to the totals) and per coarse
+//                      bucket (256x256 px)
+//   B   k_sort_prefix  per coarse bucket: each workgroup's offset (prefix
+//                      over workgroups)
+//       k_sort_scan    bucket starts and the work lists of C2, D and E
+//   C1  k_sort_coarse  the fragments again; each workgroup appends to its
+//                      own run of every coarse bucket through LDS cursors:
+//                      key + pixel in bucket
+//   C2  k_sort_fine    per chunk of 8192 entries of a coarse bucket: ranked
+//                      by tile in LDS, one global atomic per tile reserves
+//                      the chunk's run in the tile bucket: key + pixel in
+//                      tile
 //   D   k_sort_raster  per chunk of a tile bucket: LDS minimum, then one
 //                      coalesced global atomic per touched pixel
 //   E   k_sort_accum   per chunk of a tile bucket: eps window against the
 //                      finished depth pass, LDS sums, one flush per pixel
-// Tiles are numbered coarse bucket first ("slots"): slot = coarse * 64 +
-// 8 * (tile row in bucket) + (tile column in bucket), so a coarse bucket is
-// the contiguous union of its 64 tile buckets.  Every reduction is a
-// minimum or an integer sum, so the result is the oracle's bit for bit
-// whatever order the fragments land in.
+// Only C2 places entries with global atomics, one per (chunk, tile).  Tiles
+// are numbered coarse bucket first ("slots"): slot = coarse * 64 + 8 * (tile
+// row in bucket) + (tile column in bucket), so a coarse bucket is the
+// contiguous union of its 64 tile buckets; inside a coarse bucket the runs
+// of A's workgroups follow in workgroup order.  Every reduction is a minimum or an
+// integer sum, so the result is the oracle's bit for bit whatever order the
+// fragments land in.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -45,12 +51,14 @@ constexpr int kCoarseShift = 3;               // 8 x 8 tiles per coarse bucket
 constexpr int kSlotsPerCoarse = 1 << (2 * kCoarseShift);
 constexpr int kMaxCoarse = 256;
 constexpr int kMaxSlots = kMaxCoarse * kSlotsPerCoarse;   // pass A histogram: 64 KiB
-constexpr int kGroups = 512;                  // workgroups of passes A and C1
+constexpr int kGroups = 512;                  // workgroups of passes A and C1 (<= 1024)
 constexpr int kSortBlock = 1024;
 constexpr int kSortPpt = 8;                   // 8192 points per workgroup step
 constexpr int kStep = kSortBlock * kSortPpt;
 constexpr uint32_t kChunk = 8192;             // bucket entries per work item (C2, D, E)
 constexpr int kUnroll = 4;                    // bucket entries in flight per thread (D, E)
+constexpr int kPrefixCols = 32;               // pass B: columns per workgroup
+constexpr int kPrefixSegs = 32;               // pass B: workgroup segments per column
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -58,7 +66,8 @@ struct Layout {
     int32_t ntx = 0, nty = 0, ccols = 0, crows = 0, ncoarse = 0, nslots = 0, groups = 0;
     int64_t per_wg = 0;
     int64_t cchunks_max = 0, fchunks_max = 0;   // bounds on the work lists
-    size_t total = 0, fstart = 0, fchunk = 0, fcursor = 0, ccursor = 0, cchunk = 0;
+    size_t ccounts = 0, total = 0, ctotal = 0, fstart = 0, fchunk = 0;
+    size_t fcursor = 0, cchunk = 0;
     size_t xkeys = 0, xlpc = 0, ykeys = 0, ylps = 0, bytes = 0;
 };
 
@@ -85,11 +94,12 @@ Layout layout(int64_t n, int32_t w, int32_t h)
         o = align256(o + bytes);
         return at;
     };
+    L.ccounts = take((size_t)L.groups * L.ncoarse * 4);
     L.total = take((size_t)L.nslots * 4);
+    L.ctotal = take((size_t)L.ncoarse * 4);
     L.fstart = take(((size_t)L.nslots + 1) * 4);
     L.fchunk = take(((size_t)L.nslots + 1) * 4);
     L.fcursor = take((size_t)L.nslots * 4);
-    L.ccursor = take((size_t)L.ncoarse * 4);
     L.cchunk = take(((size_t)L.ncoarse + 1) * 4);
     L.xkeys = take((size_t)n * 8);
     L.xlpc = take((size_t)n * 2);
@@ -140,18 +150,13 @@ __device__ __forceinline__ uint32_t lds_rank(uint32_t *hist, uint32_t bin, bool 
     return live ? atomicAdd(&hist[bin], 1u) : 0u;
 }
 
-__global__ void k_sort_zero(uint32_t *p, int32_t n)
-{
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n)
-        p[i] = 0u;
-}
-
-// Pass A: fragments per tile.  Each workgroup takes a contiguous range of
-// points, counts in LDS and adds its non-zero counts to total[].
-template <bool VEC>
+// Pass A: fragments per tile (added to total[], zero on entry) and per
+// coarse bucket in this workgroup's contiguous range of points
+// (ccounts[g][coarse]).
+template <bool VEC, bool PW>
 __global__ void __launch_bounds__(kSortBlock) k_sort_count(Pts p, Proj P, uint32_t *total,
-                                                           int32_t ccols, int32_t nslots,
+                                                           uint32_t *ccounts, int32_t ccols,
+                                                           int32_t nslots, int32_t ncoarse,
                                                            int64_t per_wg)
 {
     extern __shared__ uint32_t hist[];
@@ -170,7 +175,7 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_count(Pts p, Proj P, uint32
         for (int j = 0; j < kSortPpt; ++j) {
             uint32_t px = 0, py = 0;
             uint64_t qq = 0;
-            const bool live = in[j] && fragment(P, x[j], y[j], z[j], px, py, qq);
+            const bool live = fragment<PW>(P, x[j], y[j], z[j], px, py, qq) & in[j];
             lds_rank(hist, live ? slot_of(px, py, ccols) : 0u, live);
         }
     }
@@ -180,18 +185,75 @@ __global__ void __launch_bounds__(kSortBlock) k_sort_count(Pts p, Proj P, uint32
         if (v)
             atomicAdd(&total[i], v);
     }
+    if ((int32_t)threadIdx.x < ncoarse) {
+        uint32_t sum = 0;
+        for (int k = 0; k < kSlotsPerCoarse; ++k)
+            sum += hist[threadIdx.x * kSlotsPerCoarse + k];
+        ccounts[(int64_t)blockIdx.x * ncoarse + threadIdx.x] = sum;
+    }
 }
 
-// Pass B: one workgroup of 1024 threads, 16 slots each (nslots <= 16384).
+__global__ void k_sort_zero(uint32_t *p, int32_t n)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0u;
+}
+
+// Pass B, first part: for every column of the [groups][coarse] count matrix,
+// the exclusive prefix over groups (in place) and the column total.  A
+// workgroup takes kPrefixCols columns; each of its kPrefixSegs segments sums
+// a run of up to kPrefixSegs groups, the segment sums are scanned in LDS, and
+// the segments write their offsets (groups <= 1024).
+__global__ void __launch_bounds__(kPrefixCols * kPrefixSegs)
+    k_sort_prefix(uint32_t *m, int32_t groups, int32_t cols, uint32_t *total)
+{
+    __shared__ uint32_t s_seg[kPrefixSegs][kPrefixCols];
+    const int tt = threadIdx.x % kPrefixCols, seg = threadIdx.x / kPrefixCols;
+    const int32_t t = blockIdx.x * kPrefixCols + tt;
+    const bool on = t < cols;
+    const int32_t g0 = seg * kPrefixSegs;
+    uint32_t c[kPrefixSegs];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPrefixSegs; ++k) {
+        const int32_t g = g0 + k;
+        c[k] = on && g < groups ? m[(int64_t)g * cols + t] : 0u;
+        sum += c[k];
+    }
+    s_seg[seg][tt] = sum;
+    __syncthreads();
+    if (seg == 0) {   // exclusive scan over the segments of column tt
+        uint32_t run = 0;
+        for (int k = 0; k < kPrefixSegs; ++k) {
+            const uint32_t v = s_seg[k][tt];
+            s_seg[k][tt] = run;
+            run += v;
+        }
+        if (on)
+            total[t] = run;
+    }
+    __syncthreads();
+    uint32_t run = s_seg[seg][tt];
+#pragma unroll
+    for (int k = 0; k < kPrefixSegs; ++k) {
+        const int32_t g = g0 + k;
+        if (on && g < groups)
+            m[(int64_t)g * cols + t] = run;
+        run += c[k];
+    }
+}
+
+// Pass B, second part: one workgroup of 1024 threads, 16 slots each
+// (nslots <= 16384).
 //   fstart  exclusive scan of the tile totals (tile bucket starts), and
 //           fstart[nslots] = all fragments; fcursor = fstart;
 //   fchunk  exclusive scan of ceil(total / kChunk): work items of D and E;
-//   ccursor first entry of each coarse bucket (= fstart of its first slot);
 //   cchunk  exclusive scan of ceil(coarse total / kChunk): work items of C2.
 __global__ void __launch_bounds__(1024) k_sort_scan(const uint32_t *total, uint32_t *fstart,
                                                     uint32_t *fchunk, uint32_t *fcursor,
-                                                    uint32_t *ccursor, uint32_t *cchunk,
-                                                    int32_t nslots, int32_t ncoarse)
+                                                    uint32_t *cchunk, int32_t nslots,
+                                                    int32_t ncoarse)
 {
     constexpr int K = kMaxSlots / 1024;
     static_assert(kSlotsPerCoarse % K == 0, "a coarse bucket spans whole threads");
@@ -239,7 +301,6 @@ __global__ void __launch_bounds__(1024) k_sort_scan(const uint32_t *total, uint3
         const int32_t last = kThreadsPerCoarse * threadIdx.x + kThreadsPerCoarse - 1;
         const uint32_t end = s_sum[last];
         const uint32_t beg = threadIdx.x ? s_sum[last - kThreadsPerCoarse] : 0u;
-        ccursor[threadIdx.x] = beg;
         cn = (end - beg + kChunk - 1) / kChunk;
     }
     __syncthreads();
@@ -258,55 +319,43 @@ __global__ void __launch_bounds__(1024) k_sort_scan(const uint32_t *total, uint3
 }
 
 // Pass C1: the fragments of pass A again (same ranges, same arithmetic).
-// Each step of 8192 points is ranked per coarse bucket in LDS; one global
-// atomic per bucket reserves the step's run, written contiguously.
-template <bool VEC>
-__global__ void __launch_bounds__(kSortBlock) k_sort_coarse(Pts p, Proj P, uint32_t *ccursor,
+// Workgroup g owns the run of every coarse bucket that starts at the
+// bucket's start plus g's offset from pass B; LDS cursors hand out its
+// places.
+template <bool VEC, bool PW>
+__global__ void __launch_bounds__(kSortBlock) k_sort_coarse(Pts p, Proj P,
+                                                            const uint32_t *__restrict__ coff,
+                                                            const uint32_t *__restrict__ fstart,
                                                             uint64_t *xkeys, uint16_t *xlpc,
                                                             int32_t ccols, int32_t ncoarse,
                                                             int64_t per_wg)
 {
-    __shared__ uint32_t s_cnt[kMaxCoarse], s_base[kMaxCoarse];
+    __shared__ uint32_t s_cur[kMaxCoarse];
     const uint64_t end = (uint64_t)p.n;   // bucket arrays hold n entries
+    if ((int32_t)threadIdx.x < ncoarse)
+        s_cur[threadIdx.x] = fstart[threadIdx.x * kSlotsPerCoarse] +
+                             coff[(int64_t)blockIdx.x * ncoarse + threadIdx.x];
+    __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * per_wg;
     Pts q = p;
     q.n = lo + per_wg < p.n ? lo + per_wg : p.n;
     for (int64_t base = lo; base < q.n; base += kStep) {
-        if ((int32_t)threadIdx.x < ncoarse)
-            s_cnt[threadIdx.x] = 0u;
-        __syncthreads();
         float x[kSortPpt], y[kSortPpt], z[kSortPpt];
         uint32_t c[kSortPpt];
         bool in[kSortPpt];
         load_points<kSortPpt, VEC>(q, base, x, y, z, c, in);
-        uint64_t key[kSortPpt];
-        uint32_t cb[kSortPpt], lpc[kSortPpt], rank[kSortPpt];
-        bool live[kSortPpt];
 #pragma unroll
         for (int j = 0; j < kSortPpt; ++j) {
             uint32_t px = 0, py = 0;
             uint64_t qq = 0;
-            live[j] = in[j] && fragment(P, x[j], y[j], z[j], px, py, qq);
-            key[j] = (qq << 24) | ((uint64_t)c[j] & kRgbMask);
-            cb[j] = live[j] ? slot_of(px, py, ccols) >> (2 * kCoarseShift) : 0u;
-            lpc[j] = ((py & 255u) << 8) | (px & 255u);
-            rank[j] = lds_rank(s_cnt, cb[j], live[j]);
-        }
-        __syncthreads();
-        if ((int32_t)threadIdx.x < ncoarse) {
-            const uint32_t k = s_cnt[threadIdx.x];
-            s_base[threadIdx.x] = k ? atomicAdd(&ccursor[threadIdx.x], k) : 0u;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kSortPpt; ++j) {
-            const uint64_t pos = (uint64_t)s_base[cb[j]] + rank[j];
-            if (live[j] && pos < end) {   // pos < end always: A and C1 agree
-                xkeys[pos] = key[j];
-                xlpc[pos] = (uint16_t)lpc[j];
+            const bool live = fragment<PW>(P, x[j], y[j], z[j], px, py, qq) & in[j];
+            const uint32_t cb = live ? slot_of(px, py, ccols) >> (2 * kCoarseShift) : 0u;
+            const uint64_t pos = lds_rank(s_cur, cb, live);
+            if (live && pos < end) {   // pos < end always: A and C1 agree
+                xkeys[pos] = (qq << 24) | ((uint64_t)c[j] & kRgbMask);
+                xlpc[pos] = (uint16_t)(((py & 255u) << 8) | (px & 255u));
             }
         }
-        __syncthreads();   // s_cnt and s_base are reused by the next step
     }
 }
 
@@ -518,11 +567,12 @@ __global__ void __launch_bounds__(256) k_sort_accum(const uint64_t *__restrict__
 hipError_t sort_passes(const Pts &p, const Proj &P, const Layout &L, char *ws, bool vec,
                        hipStream_t s)
 {
+    uint32_t *ccounts = (uint32_t *)(ws + L.ccounts);
     uint32_t *total = (uint32_t *)(ws + L.total);
+    uint32_t *ctotal = (uint32_t *)(ws + L.ctotal);
     uint32_t *fstart = (uint32_t *)(ws + L.fstart);
     uint32_t *fchunk = (uint32_t *)(ws + L.fchunk);
     uint32_t *fcursor = (uint32_t *)(ws + L.fcursor);
-    uint32_t *ccursor = (uint32_t *)(ws + L.ccursor);
     uint32_t *cchunk = (uint32_t *)(ws + L.cchunk);
     uint64_t *xkeys = (uint64_t *)(ws + L.xkeys);
     uint16_t *xlpc = (uint16_t *)(ws + L.xlpc);
@@ -531,20 +581,37 @@ hipError_t sort_passes(const Pts &p, const Proj &P, const Layout &L, char *ws, b
     hipLaunchKernelGGL(k_sort_zero, dim3((L.nslots + 255) / 256), dim3(256), 0, s, total,
                        L.nslots);
     const size_t lds = (size_t)L.nslots * sizeof(uint32_t);
-    if (vec)
-        hipLaunchKernelGGL((k_sort_count<true>), dim3(L.groups), dim3(kSortBlock), lds, s, p, P,
-                           total, L.ccols, L.nslots, L.per_wg);
+    const dim3 g(L.groups), b(kSortBlock);
+    const bool pw = P.nr != 0;
+    if (vec && pw)
+        hipLaunchKernelGGL((k_sort_count<true, true>), g, b, lds, s, p, P, total, ccounts,
+                           L.ccols, L.nslots, L.ncoarse, L.per_wg);
+    else if (vec)
+        hipLaunchKernelGGL((k_sort_count<true, false>), g, b, lds, s, p, P, total, ccounts,
+                           L.ccols, L.nslots, L.ncoarse, L.per_wg);
+    else if (pw)
+        hipLaunchKernelGGL((k_sort_count<false, true>), g, b, lds, s, p, P, total, ccounts,
+                           L.ccols, L.nslots, L.ncoarse, L.per_wg);
     else
-        hipLaunchKernelGGL((k_sort_count<false>), dim3(L.groups), dim3(kSortBlock), lds, s, p, P,
-                           total, L.ccols, L.nslots, L.per_wg);
+        hipLaunchKernelGGL((k_sort_count<false, false>), g, b, lds, s, p, P, total, ccounts,
+                           L.ccols, L.nslots, L.ncoarse, L.per_wg);
+    hipLaunchKernelGGL(k_sort_prefix, dim3((L.ncoarse + kPrefixCols - 1) / kPrefixCols),
+                       dim3(kPrefixCols * kPrefixSegs), 0, s, ccounts, L.groups, L.ncoarse,
+                       ctotal);
     hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, total, fstart, fchunk, fcursor,
-                       ccursor, cchunk, L.nslots, L.ncoarse);
-    if (vec)
-        hipLaunchKernelGGL((k_sort_coarse<true>), dim3(L.groups), dim3(kSortBlock), 0, s, p, P,
-                           ccursor, xkeys, xlpc, L.ccols, L.ncoarse, L.per_wg);
+                       cchunk, L.nslots, L.ncoarse);
+    if (vec && pw)
+        hipLaunchKernelGGL((k_sort_coarse<true, true>), g, b, 0, s, p, P, ccounts, fstart, xkeys,
+                           xlpc, L.ccols, L.ncoarse, L.per_wg);
+    else if (vec)
+        hipLaunchKernelGGL((k_sort_coarse<true, false>), g, b, 0, s, p, P, ccounts, fstart, xkeys,
+                           xlpc, L.ccols, L.ncoarse, L.per_wg);
+    else if (pw)
+        hipLaunchKernelGGL((k_sort_coarse<false, true>), g, b, 0, s, p, P, ccounts, fstart, xkeys,
+                           xlpc, L.ccols, L.ncoarse, L.per_wg);
     else
-        hipLaunchKernelGGL((k_sort_coarse<false>), dim3(L.groups), dim3(kSortBlock), 0, s, p, P,
-                           ccursor, xkeys, xlpc, L.ccols, L.ncoarse, L.per_wg);
+        hipLaunchKernelGGL((k_sort_coarse<false, false>), g, b, 0, s, p, P, ccounts, fstart,
+                           xkeys, xlpc, L.ccols, L.ncoarse, L.per_wg);
     hipLaunchKernelGGL(k_sort_fine, dim3((uint32_t)L.cchunks_max), dim3(kSortBlock), 0, s, xkeys,
                        xlpc, fstart, cchunk, fcursor, ykeys, ylps, L.ncoarse, p.n);
     return hipGetLastError();
@@ -578,6 +645,8 @@ int rasterize_sorted(const rz_points *pts, const rz_view *view, const rz_depth_m
     Proj P;
     if ((rc = make_proj(view, depth, &P)))
         return rc;
+    if (P.zkind != 0)   // float depth encodings: one-view calls only
+        return RZ_EINVAL;
     uint32_t num = 1, den = 100;
     if (hq && (rc = check_hq(hq, P, &num, &den)))
         return rc;

@@ -28,6 +28,8 @@ RZ_STATUS_HQ_OVERFLOW = 1
 DEPTH_LINEAR = 0
 DEPTH_SCALE = 1
 DEPTH_PIECEWISE = 2
+DEPTH_GL24 = 3      # depth pass only: 24-bit window depth of the perspective matrix
+DEPTH_F32REV = 4    # depth pass only: reversed single-precision depth
 
 CLEAR_DEPTH = 0xFFFFFFFFFF000000
 
@@ -115,6 +117,9 @@ SIGNATURES = {
     "rasterize_sorted": ([P(rz_points), P(rz_view), P(rz_depth_map), P(rz_hq_params), c_uint32,
                           c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_uint32,
                           c_void_p], ctypes.c_int),
+    "rasterize_points": ([P(rz_points), P(rz_view), P(rz_depth_map), P(rz_hq_params), c_int32,
+                          c_uint32, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32, c_void_p],
+                         ctypes.c_int),
     "rz_clear": ([c_void_p, c_void_p, c_int64, c_uint32, c_void_p], ctypes.c_int),
     "rz_hq_accumulate": ([P(rz_points), P(rz_view), P(rz_depth_map), P(rz_hq_params), c_void_p,
                           c_void_p, c_void_p], ctypes.c_int),
@@ -365,6 +370,32 @@ def hq_accumulate(points: Points, view, fb, acc, depth=None, eps=(1, 100), strea
     return acc
 
 
+def rasterize_points(points: Points, view, depth=None, hq=False, eps=(1, 100), point_size=1,
+                     background=0, fb=None, acc=None, img=None, status=None, keep_keys=False,
+                     stream=None):
+    """Points of point_size x point_size pixels and every depth encoding
+    (float encodings: depth pass only).  Returns (fb, acc, img, status); acc
+    and status are None without hq."""
+    torch = _torch()
+    _require_gpu(points.x, fb, acc, img, status)
+    if fb is None or (hq and acc is None):
+        fb, acc = new_framebuffer(view, background, hq=hq, stream=stream)
+    if img is None and not keep_keys:
+        img = torch.empty(_npix(view), dtype=torch.int32, device="cuda")
+    if hq and status is None:
+        status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ps, vs = points.struct(), view_struct(view)
+    ds = depth if isinstance(depth, rz_depth_map) else depth_struct(*(depth or (DEPTH_LINEAR, 0.0)))
+    hp = ctypes.byref(rz_hq_params(int(eps[0]), int(eps[1]))) if hq else None
+    rc = load().rasterize_points(ctypes.byref(ps), ctypes.byref(vs), ctypes.byref(ds), hp,
+                                 int(point_size), int(background) & 0xFFFFFFFF, _ptr(fb),
+                                 _ptr(acc) if hq else None, None if keep_keys else _ptr(img),
+                                 _ptr(status) if hq else None,
+                                 RZ_KEEP_KEYS if keep_keys else 0, _stream(stream))
+    _check(rc, "rasterize_points")
+    return fb, (acc if hq else None), (None if keep_keys else img), (status if hq else None)
+
+
 def sorted_workspace_bytes(n: int, width: int, height: int) -> int:
     """Workspace the screen-sorted path needs for n points at width x height."""
     b = load().rz_sorted_workspace_bytes(int(n), int(width), int(height))
@@ -411,9 +442,15 @@ def rasterize_sorted(points: Points, view, depth=None, hq=False, eps=(1, 100), b
 
 
 def set_launch(block=64, ppt=16, early_out=1, xcd_remap=0, bin=2):
-    """Launch shape of the point kernels (defaults = the library's)."""
+    """Launch shape of both point passes of the one-view calls."""
     _check(load().rz_set_launch(ctypes.byref(rz_launch(block, ppt, early_out, xcd_remap, bin))),
            "rz_set_launch")
+
+
+def reset_launch():
+    """Back to the library's default launch shapes (they differ between the
+    depth and the splat pass)."""
+    _check(load().rz_set_launch(None), "rz_set_launch")
 
 
 def get_launch() -> dict:

@@ -36,7 +36,8 @@ def declared_functions():
 def test_header_declares_the_entry_points():
     names = declared_functions()
     for n in ("rasterize_atomicmin", "rasterize_hq_splat", "rz_clear", "rz_resolve_min",
-              "rz_resolve_hq", "rz_error_string", "rasterize_sorted", "rz_sorted_workspace_bytes"):
+              "rz_resolve_hq", "rz_error_string", "rasterize_sorted", "rz_sorted_workspace_bytes",
+              "rasterize_points"):
         assert n in names
 
 
@@ -155,6 +156,35 @@ def test_sorted_path_validation(rz):
     assert call(fb=0) == E and call(img=0) == E
 
 
+def test_points_and_float_depth_validation(rz):
+    """Checks of rasterize_points and of the float depth encodings made
+    before any launch."""
+    lib = rz.load()
+    ps = rz.rz_points(1, 1, 1, 1, 10)
+    vs = rz.view_struct(_View())
+    E = rz.RZ_EINVAL
+
+    def call(k=2, depth=(0, 0.0), hq=None, acc=1):
+        ds = rz.depth_struct(*depth)
+        return lib.rasterize_points(ctypes.byref(ps), ctypes.byref(vs), ctypes.byref(ds),
+                                    hq and ctypes.byref(hq), k, 0, ctypes.c_void_p(1),
+                                    acc and ctypes.c_void_p(acc), ctypes.c_void_p(1), None, 0,
+                                    None)
+    assert call(k=0) == E and call(k=17) == E
+    assert call(hq=rz.rz_hq_params(1, 100), acc=0) == E
+    for kind in (rz.DEPTH_GL24, rz.DEPTH_F32REV):
+        assert call(depth=(kind, 0.0), hq=rz.rz_hq_params(1, 100)) == E   # depth pass only
+        ds = rz.depth_struct(kind, 0.0)
+        hq = rz.rz_hq_params(1, 100)
+        assert lib.rasterize_hq_splat(ctypes.byref(ps), ctypes.byref(vs), ctypes.byref(ds),
+                                      ctypes.byref(hq), 0, ctypes.c_void_p(1), ctypes.c_void_p(1),
+                                      ctypes.c_void_p(1), None, 0, None) == E
+        assert lib.rasterize_sorted(ctypes.byref(ps), ctypes.byref(vs), ctypes.byref(ds), None, 0,
+                                    ctypes.c_void_p(1), None, ctypes.c_void_p(1), None,
+                                    ctypes.c_void_p(256 * 4096), 1 << 30, 0, None) == E
+    assert call(depth=(5, 0.0)) == E                                        # unknown kind
+
+
 def test_launch_shape_validation(rz):
     lib = rz.load()
     before = rz.get_launch()
@@ -164,6 +194,8 @@ def test_launch_shape_validation(rz):
     rz.set_launch(128, 4, 0, 0)
     assert rz.get_launch()["block"] == 128 and rz.get_launch()["ppt"] == 4
     rz.set_launch(**before)
+    rz.reset_launch()
+    assert rz.get_launch() == {"block": 64, "ppt": 16, "early_out": 1, "xcd_remap": 0, "bin": 2}
 
 
 def test_binding_refuses_without_gpu(rz):

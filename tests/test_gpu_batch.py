@@ -23,7 +23,7 @@ def rz():
     from paper_1908_02681_amd import rz as binding
     binding.load()
     yield binding
-    binding.set_launch()
+    binding.reset_launch()
 
 
 SIZES = [(64, 48), (160, 120), (97, 61), (200, 150), (33, 257)]

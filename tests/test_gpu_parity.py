@@ -25,7 +25,7 @@ def rz():
     from paper_1908_02681_amd import rz as binding
     binding.load()
     yield binding
-    binding.set_launch()
+    binding.reset_launch()
 
 
 def gpu_min(rz, pts, view, depth=None, bg=0):
@@ -175,7 +175,7 @@ def test_every_launch_shape_is_bit_identical(rz, oracle):
             _, sums, img, *_ = gpu_hq(rz, pts, view)
             assert np.array_equal(sums, ok_sums) and np.array_equal(img, ok_img)
     finally:
-        rz.set_launch()
+        rz.reset_launch()
 
 
 @pytest.mark.parametrize("bin_", [0, 1, 2])
@@ -198,7 +198,7 @@ def test_tile_fallback_and_sparse_screens(rz, oracle, bin_):
         v2 = gen.terrain_view(300, 200, extent=100.0, distance=60.0, near=0.5, far=400.0)
         check_scene(rz, oracle, t, v2, label=f"clipped terrain bin={bin_}")
     finally:
-        rz.set_launch()
+        rz.reset_launch()
 
 
 def test_unaligned_planes_take_the_scalar_path(rz, oracle):
