@@ -26,6 +26,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gpoints/s rasterized (atomicMin, HQ splat); served p50/p99 ms vs plain loop"
 HBM_PEAK_GBS = 8000.0
+# wave64 VALU issue without packed FP32: 256 CUs x 4 SIMDs, one instruction
+# per SIMD every 4 cycles, 64 lanes, 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 64 * 2.4e9
 
 
 def log(msg):
@@ -525,6 +528,19 @@ def main():
         rec = tr.get(a.workload if a.path == "direct" else f"{a.workload}:{a.path}", {}).get(dom)
         if rec and rec.get("source_hash") == kernel_source_hash(a.path):
             traffic = rec["bytes_per_launch"]
+    # VALU issue of the dominant kernel: lane instructions per point from the
+    # recorded counter pass (profiles/valu_terrain50m.md), rate from this run
+    valu = None
+    vfile = os.path.join(ROOT, "profiles", "valu_issue.json")
+    if os.path.exists(vfile) and a.path == "direct" and not general:
+        with open(vfile) as f:
+            vrec = json.load(f).get(a.workload, {}).get(dom)
+        if vrec and vrec.get("source_hash") == kernel_source_hash("direct"):
+            rate = vrec["lane_instr_per_point"] * n / (dk["ms"] * 1e-3)
+            valu = {"lane_instr_per_point": vrec["lane_instr_per_point"],
+                    "achieved_T_per_s": round(rate / 1e12, 2),
+                    "peak_T_per_s": VALU_ISSUE_PEAK / 1e12,
+                    "frac": round(rate / VALU_ISSUE_PEAK, 4)}
     out = {
         "metric": METRIC,
         "value": round((2 if with_hq else 1) * n / (ms_per_step * 1e-3) / 1e9, 4),
@@ -553,6 +569,7 @@ def main():
             "kernels_ms": {k: round(v["ms"], 4) for k, v in kern.items()},
             "kernels_GBps": {k: round(v["GBps"], 1) for k, v in kern.items()},
             "evented_ms_per_step": round(float(avg.sum()), 4),
+            "valu_issue": valu,
             "launch": rz.get_launch(),
         },
     }
