@@ -55,6 +55,10 @@ def configure(lib):
     lib.rzo_hq_accumulate.argtypes = [P, P, P, P, i64] + cam + [i32, u32, u32, P, P]
     lib.rzo_hq_resolve.argtypes = [P, P, i64, u32, P]
     lib.rzo_hq_resolve.restype = None
+    lib.rzo_merge_min.argtypes = [P, P, i64]
+    lib.rzo_merge_min.restype = None
+    lib.rzo_merge_sum.argtypes = [P, P, i64]
+    lib.rzo_merge_sum.restype = None
     return lib
 
 
@@ -191,3 +195,17 @@ def render_hq(x, y, z, rgb, vp, near, far, width, height, kind=LINEAR, scale=0.0
     out = sums.copy()
     img = hq_resolve(sums, fb, bg)
     return keys, out, img
+
+
+def merge_min(dst, src):
+    """Sort-last composition of depth passes: dst = min(dst, src) per pixel."""
+    assert dst.dtype == np.uint64 and src.dtype == np.uint64 and dst.shape == src.shape
+    _load().rzo_merge_min(_ptr(dst), _ptr(np.ascontiguousarray(src)), dst.shape[0])
+    return dst
+
+
+def merge_sum(dst, src):
+    """Sort-last composition of splat sums ((npix, 4) exact words): dst += src."""
+    assert dst.dtype == np.uint64 and src.dtype == np.uint64 and dst.shape == src.shape
+    _load().rzo_merge_sum(_ptr(dst), _ptr(np.ascontiguousarray(src)), dst.shape[0])
+    return dst

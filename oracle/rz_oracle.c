@@ -469,3 +469,26 @@ void rzo_hq_resolve(uint64_t *sums, uint64_t *fb, int64_t npix, uint32_t bg,
         fb[p] = RZO_DEPTH_ONES | ((uint64_t)bg & RZO_RGB_MASK);
     }
 }
+
+/*
+ * Sort-last composition (the sharded form of both passes): the depth passes
+ * of disjoint parts of a cloud, each into a full framebuffer, combine into
+ * the depth pass of the whole cloud by a per-pixel minimum; the splat sums
+ * of the parts, each accumulated against the combined depth pass, add up to
+ * the sums of the whole cloud.
+ */
+void rzo_merge_min(uint64_t *dst, const uint64_t *src, int64_t npix)
+{
+    int64_t p;
+    for (p = 0; p < npix; p++)
+        if (src[p] < dst[p])
+            dst[p] = src[p];
+}
+
+/* sums: four exact words per pixel (R, G, B, count) */
+void rzo_merge_sum(uint64_t *dst, const uint64_t *src, int64_t npix)
+{
+    int64_t i;
+    for (i = 0; i < 4 * npix; i++)
+        dst[i] += src[i];
+}

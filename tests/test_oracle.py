@@ -677,3 +677,56 @@ def test_point_size_splat_window_per_covered_pixel(oracle):
                     want[p] += np.array([c & 255, (c >> 8) & 255, (c >> 16) & 255, 1], np.uint64)
     assert (sums == want).all()
     assert (sums[:, 3] > 1).sum() > 50
+
+
+# --------------------------------------------------------------------------
+# sort-last composition (sharding across devices, design only)
+# --------------------------------------------------------------------------
+
+def _parts(n, k, seed):
+    """k disjoint parts of range(n): contiguous ranges, then a shuffle of them."""
+    cut = np.sort(np.random.default_rng(seed).choice(np.arange(1, n), k - 1, replace=False))
+    return np.split(np.arange(n), cut)
+
+
+def test_sort_last_depth_merge(oracle):
+    """The depth pass of a whole cloud is the per-pixel minimum of the depth
+    passes of any partition of it (min is associative and commutative)."""
+    W, H = 40, 24
+    v, x, y, z, rgb = _random_scene(41, 3000, W, H)
+    full = oracle.raster_min(x, y, z, rgb, v.vp, v.near, v.far, W, H, bg=0x010203)
+    for k, seed in ((2, 1), (5, 2)):
+        acc = None
+        for idx in _parts(x.size, k, seed):
+            fb = oracle.raster_min(x[idx], y[idx], z[idx], rgb[idx], v.vp, v.near, v.far, W, H,
+                                   bg=0x010203)
+            acc = fb if acc is None else oracle.merge_min(acc, fb)
+        assert (acc == full).all()
+    assert (full != oracle.clear_value(0x010203)).sum() > 100
+
+
+def test_sort_last_splat_merge(oracle):
+    """Splat sums of the parts, each taken against the combined depth pass,
+    add up to the sums of the whole cloud; the resolved images agree."""
+    c, v = _small_terrain()
+    W, H = v.width, v.height
+    keys, want_sums, want_img = oracle.render_hq(c.x, c.y, c.z, c.rgb, v.vp, v.near, v.far, W, H)
+    merged = None
+    parts = _parts(c.n, 4, 3)
+    for idx in parts:
+        fb = oracle.raster_min(c.x[idx], c.y[idx], c.z[idx], c.rgb[idx], v.vp, v.near, v.far, W, H)
+        merged = fb if merged is None else oracle.merge_min(merged, fb)
+    assert (merged == keys).all()
+    sums = np.zeros((W * H, 4), np.uint64)
+    for idx in parts:
+        part = oracle.hq_accumulate(c.x[idx], c.y[idx], c.z[idx], c.rgb[idx], v.vp, v.near, v.far,
+                                    W, H, merged)
+        oracle.merge_sum(sums, part)
+    assert (sums == want_sums).all()
+    assert (oracle.hq_resolve(sums, merged.copy()) == want_img).all()
+    # the parts alone, against their own depth passes, would not add up
+    own = np.zeros((W * H, 4), np.uint64)
+    for idx in parts:
+        own += oracle.render_hq(c.x[idx], c.y[idx], c.z[idx], c.rgb[idx], v.vp, v.near, v.far,
+                                W, H)[1]
+    assert (own[:, 3] > want_sums[:, 3]).any()

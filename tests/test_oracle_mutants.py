@@ -72,6 +72,9 @@ MUTANTS = {
         "rzo_span(p % w, 1, w, &x0, &x1);\n        rzo_span(p / w, 1, h, &y0, &y1);\n        for (yy = y0; yy < y1; yy++) {"),
     "splat window of the centre pixel": ("const uint64_t qmin = fb[pp] >> 24;",
                                          "const uint64_t qmin = fb[p] >> 24;"),
+    "merge keeps the larger key": ("if (src[p] < dst[p])\n            dst[p] = src[p];",
+                                   "if (src[p] > dst[p])\n            dst[p] = src[p];"),
+    "merge sum drops the count": ("for (i = 0; i < 4 * npix; i++)", "for (i = 0; i < 4 * npix; i += 4)"),
 }
 
 PINS = [
@@ -103,6 +106,8 @@ PINS = [
     *[(T.test_point_size_is_a_min_filter, {"k": k}) for k in (2, 3, 4, 5)],
     *[(T.test_point_size_splat_sums_are_box_sums, {"k": k}) for k in (2, 3)],
     (T.test_point_size_splat_window_per_covered_pixel, {}),
+    (T.test_sort_last_depth_merge, {}),
+    (T.test_sort_last_splat_merge, {}),
 ]
 
 
