@@ -340,6 +340,11 @@ def main():
                     help="direct: one atomic per fragment; sorted: screen-tile sort first")
     ap.add_argument("--point-size", type=int, default=1,
                     help="points of k x k pixels (direct path)")
+    ap.add_argument("--flush-mall", action="store_true",
+                    help="also time steps with a 1 GiB device fill before each (cold caches)")
+    ap.add_argument("--shards", type=int, default=0,
+                    help="also time one device's share of a sort-last split into G parts: "
+                         "its depth pass (N/G points, full framebuffer) and the merge kernels")
     ap.add_argument("--depth", choices=("linear", "gl24", "f32rev"), default="linear",
                     help="depth encoding; gl24 and f32rev have no splat frame")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -573,6 +578,25 @@ def main():
             "launch": rz.get_launch(),
         },
     }
+    if a.shards > 1:
+        out["detail"]["sort_last"] = time_sort_last(rz, pts, view, a.shards, a.steps)
+    if a.flush_mall:
+        # the same steps, each after a 1 GiB fill that evicts L2 and the
+        # 256 MB infinity cache; only the evented kernel time counts
+        junk = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+        fl = np.zeros(5)
+        for k in range(a.steps):
+            junk.fill_(k)
+            torch.cuda.synchronize()
+            step(events[k])
+            torch.cuda.synchronize()
+            fl += [events[k][i].elapsed_time(events[k][i + 1]) for i in range(5)]
+        fl /= a.steps
+        del junk
+        out["detail"]["mall_flushed"] = {
+            "evented_ms_per_step": round(float(fl.sum()), 4),
+            "atomicmin_frame_ms": round(fl[0] + fl[1], 4),
+            "hq_frame_ms": round(fl[2] + fl[3] + fl[4], 4) if with_hq else None}
     if a.calibrate_copy:
         src = torch.empty(a.calibrate_copy // 4, dtype=torch.int32, device="cuda").fill_(1)
         dst = torch.empty_like(src)
@@ -585,6 +609,42 @@ def main():
         log("[bench] timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(cloud, view, eps)
     print(json.dumps(out), flush=True)
+
+
+def time_sort_last(rz, pts, view, G, steps):
+    """One device's share of a G-way sort-last split: the depth pass of its
+    N/G points into a full framebuffer, and the per-pixel merges that a
+    reduction of the framebuffers applies (timed locally; no transfer)."""
+    import torch
+    n, npix = pts.n, view.width * view.height
+    share = (n // G) // 4 * 4                      # keep the planes 16-byte aligned
+    part = rz.Points(pts.x[:share], pts.y[:share], pts.z[:share], pts.rgb[:share])
+    fb, _ = rz.new_framebuffer(view, 0)
+    other, _ = rz.new_framebuffer(view, 0)
+    rz.rasterize_atomicmin(pts, view, fb=other, keep_keys=True)
+    acc = torch.zeros(2 * npix, dtype=torch.int64, device="cuda")
+    acc2 = torch.ones(2 * npix, dtype=torch.int64, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    t = np.zeros(3)
+    for _ in range(steps):
+        rz.clear(fb, None, npix)
+        ev[0].record()
+        rz.rasterize_atomicmin(part, view, fb=fb, keep_keys=True)
+        ev[1].record()
+        rz.merge_min(fb, other, npix)
+        ev[2].record()
+        rz.merge_sum(acc, acc2, npix)
+        ev[3].record()
+        torch.cuda.synchronize()
+        t += [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+    t /= steps
+    return {"shards": G, "points_per_shard": share,
+            "local_depth_pass_ms": round(t[0], 4),
+            "local_depth_pass_GBps": round(16 * share / (t[0] * 1e-3) / 1e9, 1),
+            "merge_min_ms": round(t[1], 4),
+            "merge_min_GBps": round(24 * npix / (t[1] * 1e-3) / 1e9, 1),
+            "merge_sum_ms": round(t[2], 4),
+            "merge_sum_GBps": round(48 * npix / (t[2] * 1e-3) / 1e9, 1)}
 
 
 KERNEL_SOURCES = {

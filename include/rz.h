@@ -283,6 +283,25 @@ typedef struct rz_launch {
 int rz_set_launch(const rz_launch *launch);
 int rz_get_launch(rz_launch *launch);
 
+/* ---- sort-last composition ------------------------------------------ */
+/*
+ * Combining the passes of disjoint parts of a cloud, each rendered into a
+ * full framebuffer (by a device each, or one after the other): the depth
+ * pass of the whole is the per-pixel minimum of the parts' depth passes
+ * (section 2.1's minimum is associative), and the splat sums of the whole
+ * are the sums of the parts' accumulate passes taken against that combined
+ * depth pass (section 2.2).  Across devices the same per-pixel operations
+ * are a MIN and a SUM reduction of the framebuffers.
+ *   rz_merge_min  dst[p] = min(dst[p], src[p]) for p < npix (u64 keys).
+ *   rz_merge_sum  dst[2p + k] += src[2p + k] for k = 0, 1 (packed sums as in
+ *                 acc; exact while the merged counts stay within the range
+ *                 of rasterize_hq_splat).
+ * Device pointers, 16-byte aligned; dst and src must not overlap.  Errors:
+ * RZ_EINVAL, RZ_EHIP.
+ */
+int rz_merge_min(uint64_t *dst, const uint64_t *src, int64_t npix, void *stream);
+int rz_merge_sum(uint64_t *dst, const uint64_t *src, int64_t npix, void *stream);
+
 /* ---- batched multi-view rendering ------------------------------------ */
 /*
  * Many views of one resident cloud in one submission.  Views are taken in

@@ -120,6 +120,8 @@ SIGNATURES = {
     "rasterize_points": ([P(rz_points), P(rz_view), P(rz_depth_map), P(rz_hq_params), c_int32,
                           c_uint32, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32, c_void_p],
                          ctypes.c_int),
+    "rz_merge_min": ([c_void_p, c_void_p, c_int64, c_void_p], ctypes.c_int),
+    "rz_merge_sum": ([c_void_p, c_void_p, c_int64, c_void_p], ctypes.c_int),
     "rz_clear": ([c_void_p, c_void_p, c_int64, c_uint32, c_void_p], ctypes.c_int),
     "rz_hq_accumulate": ([P(rz_points), P(rz_view), P(rz_depth_map), P(rz_hq_params), c_void_p,
                           c_void_p, c_void_p], ctypes.c_int),
@@ -439,6 +441,22 @@ def rasterize_sorted(points: Points, view, depth=None, hq=False, eps=(1, 100), b
                                  RZ_KEEP_KEYS if keep_keys else 0, _stream(stream))
     _check(rc, "rasterize_sorted")
     return fb, (acc if hq else None), (None if keep_keys else img), (status if hq else None)
+
+
+def merge_min(dst, src, npix=None, stream=None):
+    """Sort-last composition of depth passes: dst = min(dst, src) per pixel."""
+    _require_gpu(dst, src)
+    n = dst.numel() if npix is None else int(npix)
+    _check(load().rz_merge_min(_ptr(dst), _ptr(src), n, _stream(stream)), "rz_merge_min")
+    return dst
+
+
+def merge_sum(dst, src, npix=None, stream=None):
+    """Sort-last composition of packed splat sums (2 words per pixel)."""
+    _require_gpu(dst, src)
+    n = dst.numel() // 2 if npix is None else int(npix)
+    _check(load().rz_merge_sum(_ptr(dst), _ptr(src), n, _stream(stream)), "rz_merge_sum")
+    return dst
 
 
 def set_launch(block=64, ppt=16, early_out=1, xcd_remap=0, bin=2):

@@ -37,7 +37,7 @@ def test_header_declares_the_entry_points():
     names = declared_functions()
     for n in ("rasterize_atomicmin", "rasterize_hq_splat", "rz_clear", "rz_resolve_min",
               "rz_resolve_hq", "rz_error_string", "rasterize_sorted", "rz_sorted_workspace_bytes",
-              "rasterize_points"):
+              "rasterize_points", "rz_merge_min", "rz_merge_sum"):
         assert n in names
 
 
@@ -183,6 +183,18 @@ def test_points_and_float_depth_validation(rz):
                                     ctypes.c_void_p(1), None, ctypes.c_void_p(1), None,
                                     ctypes.c_void_p(256 * 4096), 1 << 30, 0, None) == E
     assert call(depth=(5, 0.0)) == E                                        # unknown kind
+
+
+def test_merge_validation(rz):
+    lib = rz.load()
+    E = rz.RZ_EINVAL
+    P = ctypes.c_void_p
+    for fn in (lib.rz_merge_min, lib.rz_merge_sum):
+        assert fn(P(256), P(1 << 20), -1, None) == E
+        assert fn(P(256), P(1 << 20), 0, None) == rz.RZ_OK       # nothing to do
+        assert fn(None, P(1 << 20), 4, None) == E
+        assert fn(P(256 + 8), P(1 << 20), 4, None) == E          # not 16-byte aligned
+        assert fn(P(4096), P(4096 + 16), 4, None) == E           # overlapping
 
 
 def test_launch_shape_validation(rz):
