@@ -26,7 +26,8 @@
  *     bottom of the image (OpenGL window convention).
  *   - The view-projection matrix vp is row-major and maps column vectors:
  *     clip = vp * (x, y, z, 1).  Pixel positions are computed in float32
- *     from (float)vp: ndc = clip.xy / clip.w, window = (ndc + 1) * size / 2,
+ *     from (float)vp: ndc = clip.xy * (1 / clip.w) with the reciprocal
+ *     rounded once, window = (ndc + 1) * size / 2,
  *     pixel = floor(window) in [0, size).  The depth d is row 3 of vp in
  *     double precision (the clip w: linear view depth for a perspective
  *     matrix).  A fragment is kept iff clip.w > 0, the pixel is inside the
@@ -90,7 +91,7 @@ extern "C" {
 /* Encodings of a graphics depth buffer, for comparing precision with the
    40-bit integers (sections 1 and 2.1); depth pass only (rasterize_atomicmin
    and rasterize_points without hq; any other call returns RZ_EINVAL):
-   RZ_DEPTH_GL24: z_ndc = clip.z / clip.w in single precision (row 2 of the
+   RZ_DEPTH_GL24: z_ndc = clip.z * (1 / clip.w) in single precision (row 2 of the
    float matrix, same operation order as the other rows), z_win =
    (z_ndc + 1) * 0.5, depth = round(z_win * (2^24 - 1)) (ties up) as a 24-bit
    integer; fragments with z_ndc outside [-1, 1] are discarded.

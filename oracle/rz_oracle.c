@@ -30,7 +30,8 @@
  *  - depth d is the clip-space w of the view-projection (row 3), computed in
  *    double precision; for a perspective matrix it is the linear view depth;
  *  - projection to pixels is done in single precision: clip = VPf * p with
- *    VPf = (float)VP, ndc = clip.xy / clip.w, window = (ndc + 1) * size / 2,
+ *    VPf = (float)VP, ndc = clip.xy * (1 / clip.w) (the reciprocal correctly
+ *    rounded once, as a perspective divide does), window = (ndc + 1) * size / 2,
  *    pixel = floor(window), half-open [0, size), row 0 at the bottom;
  *  - fragments with w <= 0, outside the window, or with d outside
  *    [near, far) are discarded;
@@ -54,7 +55,7 @@
  * depth buffer, the precision the paper's 40-bit integers are set against
  * (sections 1 and 2.1); they are for the depth pass only:
  *  - "gl24": window depth of the perspective matrix in single precision,
- *    z_ndc = clip.z / clip.w (row 2 of the float matrix, same operation
+ *    z_ndc = clip.z * (1 / clip.w) (row 2 of the float matrix, same operation
  *    order as the other rows), z_win = (z_ndc + 1) / 2, kept as a 24-bit
  *    unsigned normalised integer round(z_win * (2^24 - 1)) (rounding to
  *    nearest, ties up), fragments with z_ndc outside [-1, 1] discarded;
@@ -209,7 +210,7 @@ static int rzo_fragment(const rzo_cam *c, float x, float y, float z,
 {
     const float *m = c->m;
     const double *v = c->vp;
-    float cx, cy, cw, nx, ny, fx, fy;
+    float cx, cy, cw, iw, nx, ny, fx, fy;
     double d;
     int32_t px, py;
 
@@ -230,8 +231,9 @@ static int rzo_fragment(const rzo_cam *c, float x, float y, float z,
         return 0;
 
     /* perspective divide and viewport */
-    nx = cx / cw;
-    ny = cy / cw;
+    iw = 1.0f / cw;
+    nx = cx * iw;
+    ny = cy * iw;
     fx = (nx + 1.0f) * c->hw;
     fy = (ny + 1.0f) * c->hh;
     if (!(fx >= 0.0f && fx < c->fw && fy >= 0.0f && fy < c->fh))
@@ -255,7 +257,7 @@ static int rzo_fragment(const rzo_cam *c, float x, float y, float z,
         cz = cz + m[9] * y;
         cz = cz + m[10] * z;
         cz = cz + m[11];
-        nz = cz / cw;
+        nz = cz * iw;
         if (!(nz >= -1.0f && nz <= 1.0f))
             return 0;
         zw = (nz + 1.0f) * 0.5f;

@@ -96,12 +96,14 @@ __device__ __forceinline__ bool in_window(const Proj &P, uint32_t eps_num, uint3
     return lhs <= rhs;
 }
 
-// Pixel of one point (section 2.1's projection in single precision) and its
-// clip w.  Returns false when the point is culled (w <= 0 or off screen).
+// Pixel of one point (section 2.1's projection in single precision), its
+// clip w and 1 / w (rounded once; x and y are scaled by it, as a
+// perspective divide does).  Returns false when the point is culled (w <= 0
+// or off screen).
 // Straight-line code: the pixel of a culled point is 0, never a conversion
 // of an out-of-range float.
 __device__ __forceinline__ bool project(const Proj &P, float x, float y, float z, uint32_t &px,
-                                        uint32_t &py, float &cw)
+                                        uint32_t &py, float &cw, float &iw)
 {
     float cx = P.m[0] * x;
     cx = cx + P.m[1] * y;
@@ -115,8 +117,9 @@ __device__ __forceinline__ bool project(const Proj &P, float x, float y, float z
     cw = cw + P.m[9] * y;
     cw = cw + P.m[10] * z;
     cw = cw + P.m[11];
-    const float nx = cx / cw;
-    const float ny = cy / cw;
+    iw = 1.0f / cw;
+    const float nx = cx * iw;
+    const float ny = cy * iw;
     const float fx = (nx + 1.0f) * P.hw;
     const float fy = (ny + 1.0f) * P.hh;
     const bool vis = cw > 0.0f && fx >= 0.0f && fx < P.fw && fy >= 0.0f && fy < P.fh;
@@ -145,8 +148,8 @@ template <bool PW>
 __device__ __forceinline__ bool fragment(const Proj &P, float x, float y, float z,
                                          uint32_t &px, uint32_t &py, uint64_t &q)
 {
-    float cw;
-    const bool vis = project(P, x, y, z, px, py, cw);
+    float cw, iw;
+    const bool vis = project(P, x, y, z, px, py, cw, iw);
     q = 0;
     if (!__any(vis))
         return false;
@@ -167,8 +170,8 @@ __device__ __forceinline__ bool fragment_any(const Proj &P, float x, float y, fl
 {
     if (P.zkind == 0)
         return fragment<true>(P, x, y, z, px, py, q);
-    float cw;
-    if (!project(P, x, y, z, px, py, cw))
+    float cw, iw;
+    if (!project(P, x, y, z, px, py, cw, iw))
         return false;
     const double d = depth_of(P, x, y, z);
     if (!(d >= P.near_ && d < P.far_))
@@ -182,7 +185,7 @@ __device__ __forceinline__ bool fragment_any(const Proj &P, float x, float y, fl
     cz = cz + P.mz[1] * y;
     cz = cz + P.mz[2] * z;
     cz = cz + P.mz[3];
-    const float nz = cz / cw;
+    const float nz = cz * iw;
     if (!(nz >= -1.0f && nz <= 1.0f))
         return false;
     const float zw = (nz + 1.0f) * 0.5f;

@@ -16,7 +16,8 @@ MUTANTS = {
     "wrong w row": ("cw = m[12] * x;", "cw = m[8] * x;"),
     "viewport sign": ("fx = (nx + 1.0f) * c->hw;", "fx = (nx - 1.0f) * c->hw;"),
     "half sizes swapped": ("fy = (ny + 1.0f) * c->hh;", "fy = (ny + 1.0f) * c->hw;"),
-    "ndc divides by x": ("ny = cy / cw;", "ny = cy / cx;"),
+    "ndc scales by the wrong reciprocal": ("ny = cy * iw;", "ny = cy / cx;"),
+    "reciprocal of the wrong row": ("iw = 1.0f / cw;", "iw = 1.0f / cx;"),
     "window edge inclusive": ("fx < c->fw", "fx <= c->fw"),
     "depth from row 2": ("d = v[12] * (double)x;", "d = v[8] * (double)x;"),
     "depth offset dropped": ("d = d + v[15];", ""),
