@@ -449,22 +449,21 @@ template <int PPT>
 __device__ __forceinline__ Box wave_box(const uint32_t (&px)[PPT], const uint32_t (&py)[PPT],
                                         const bool (&live)[PPT])
 {
-    uint32_t m[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+    static_assert(PPT % 2 == 0, "points are taken in pairs");
+    uint32_t lx = 0xFFFFFFFFu, ly = 0xFFFFFFFFu, hx = 0u, hy = 0u;
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        const uint32_t a = live[j] ? px[j] : 0xFFFFFFFFu;
-        const uint32_t b = live[j] ? py[j] : 0xFFFFFFFFu;
-        const uint32_t c = live[j] ? ~px[j] : 0xFFFFFFFFu;
-        const uint32_t d = live[j] ? ~py[j] : 0xFFFFFFFFu;
-        m[0] = a < m[0] ? a : m[0];
-        m[1] = b < m[1] ? b : m[1];
-        m[2] = c < m[2] ? c : m[2];
-        m[3] = d < m[3] ? d : m[3];
+    for (int j = 0; j < PPT; j += 2) {   // pairs: three-operand min and max
+        const uint32_t a0 = live[j] ? px[j] : 0xFFFFFFFFu, a1 = live[j + 1] ? px[j + 1] : 0xFFFFFFFFu;
+        const uint32_t b0 = live[j] ? py[j] : 0xFFFFFFFFu, b1 = live[j + 1] ? py[j + 1] : 0xFFFFFFFFu;
+        const uint32_t c0 = live[j] ? px[j] : 0u, c1 = live[j + 1] ? px[j + 1] : 0u;
+        const uint32_t d0 = live[j] ? py[j] : 0u, d1 = live[j + 1] ? py[j + 1] : 0u;
+        lx = min(lx, min(a0, a1));
+        ly = min(ly, min(b0, b1));
+        hx = max(hx, max(c0, c1));
+        hy = max(hy, max(d0, d1));
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-        m[k] = wave_min(m[k]);
-    return Box{m[0], m[1], ~m[2], ~m[3]};
+    // no live lane: lx = ~0 > hx = 0, an empty box
+    return Box{wave_min(lx), wave_min(ly), ~wave_min(~hx), ~wave_min(~hy)};
 }
 
 // Depth pass over one chunk with a private LDS tile per wave: like
