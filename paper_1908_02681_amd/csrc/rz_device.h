@@ -212,44 +212,66 @@ __device__ __forceinline__ int64_t chunk_index()
 // load instruction of a wave reads one contiguous 1 KiB span per plane.
 // Scalar form (tail chunk or unaligned planes): same point indices, bounds
 // checked one by one.
-template <int PPT, bool VEC>
-__device__ __forceinline__ void load_points(const Pts &p, int64_t base, float (&x)[PPT],
+template <int PPT>
+__device__ __forceinline__ bool chunk_full(const Pts &p, int64_t base)
+{
+    return base + 4 * (int64_t)blockDim.x * (PPT / 4) <= p.n;
+}
+
+template <int PPT>
+__device__ __forceinline__ void load_full(const Pts &p, int64_t base, float (&x)[PPT],
+                                          float (&y)[PPT], float (&z)[PPT], uint32_t (&c)[PPT])
+{
+    const int64_t stride = 4 * (int64_t)blockDim.x;
+    const int64_t first = base + 4 * (int64_t)threadIdx.x;
+#pragma unroll
+    for (int g = 0; g < PPT / 4; ++g) {
+        const int64_t i = first + g * stride;
+        const f32x4 vx = ldnt(reinterpret_cast<const f32x4 *>(p.x + i));
+        const f32x4 vy = ldnt(reinterpret_cast<const f32x4 *>(p.y + i));
+        const f32x4 vz = ldnt(reinterpret_cast<const f32x4 *>(p.z + i));
+        const u32x4 vc = ldnt(reinterpret_cast<const u32x4 *>(p.rgb + i));
+        x[4 * g + 0] = vx.x; x[4 * g + 1] = vx.y; x[4 * g + 2] = vx.z; x[4 * g + 3] = vx.w;
+        y[4 * g + 0] = vy.x; y[4 * g + 1] = vy.y; y[4 * g + 2] = vy.z; y[4 * g + 3] = vy.w;
+        z[4 * g + 0] = vz.x; z[4 * g + 1] = vz.y; z[4 * g + 2] = vz.z; z[4 * g + 3] = vz.w;
+        c[4 * g + 0] = vc.x; c[4 * g + 1] = vc.y; c[4 * g + 2] = vc.z; c[4 * g + 3] = vc.w;
+    }
+}
+
+template <int PPT>
+__device__ __forceinline__ void load_ragged(const Pts &p, int64_t base, float (&x)[PPT],
                                             float (&y)[PPT], float (&z)[PPT],
                                             uint32_t (&c)[PPT], bool (&in)[PPT])
 {
     const int64_t stride = 4 * (int64_t)blockDim.x;
     const int64_t first = base + 4 * (int64_t)threadIdx.x;
-    const bool full = VEC && base + stride * (PPT / 4) <= p.n;
-    if (full) {
 #pragma unroll
-        for (int g = 0; g < PPT / 4; ++g) {
-            const int64_t i = first + g * stride;
-            const f32x4 vx = ldnt(reinterpret_cast<const f32x4 *>(p.x + i));
-            const f32x4 vy = ldnt(reinterpret_cast<const f32x4 *>(p.y + i));
-            const f32x4 vz = ldnt(reinterpret_cast<const f32x4 *>(p.z + i));
-            const u32x4 vc = ldnt(reinterpret_cast<const u32x4 *>(p.rgb + i));
-            x[4 * g + 0] = vx.x; x[4 * g + 1] = vx.y; x[4 * g + 2] = vx.z; x[4 * g + 3] = vx.w;
-            y[4 * g + 0] = vy.x; y[4 * g + 1] = vy.y; y[4 * g + 2] = vy.z; y[4 * g + 3] = vy.w;
-            z[4 * g + 0] = vz.x; z[4 * g + 1] = vz.y; z[4 * g + 2] = vz.z; z[4 * g + 3] = vz.w;
-            c[4 * g + 0] = vc.x; c[4 * g + 1] = vc.y; c[4 * g + 2] = vc.z; c[4 * g + 3] = vc.w;
+    for (int g = 0; g < PPT / 4; ++g) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                in[4 * g + k] = true;
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = first + g * stride + k;
+            const bool ok = i < p.n;
+            in[4 * g + k] = ok;
+            x[4 * g + k] = ok ? p.x[i] : 0.0f;
+            y[4 * g + k] = ok ? p.y[i] : 0.0f;
+            z[4 * g + k] = ok ? p.z[i] : 0.0f;
+            c[4 * g + k] = ok ? p.rgb[i] : 0u;
         }
+    }
+}
+
+template <int PPT, bool VEC>
+__device__ __forceinline__ void load_points(const Pts &p, int64_t base, float (&x)[PPT],
+                                            float (&y)[PPT], float (&z)[PPT],
+                                            uint32_t (&c)[PPT], bool (&in)[PPT])
+{
+    if (VEC && chunk_full<PPT>(p, base)) {
+        load_full<PPT>(p, base, x, y, z, c);
+#pragma unroll
+        for (int j = 0; j < PPT; ++j)
+            in[j] = true;
     } else {
-#pragma unroll
-        for (int g = 0; g < PPT / 4; ++g) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int64_t i = first + g * stride + k;
-                const bool ok = i < p.n;
-                in[4 * g + k] = ok;
-                x[4 * g + k] = ok ? p.x[i] : 0.0f;
-                y[4 * g + k] = ok ? p.y[i] : 0.0f;
-                z[4 * g + k] = ok ? p.z[i] : 0.0f;
-                c[4 * g + k] = ok ? p.rgb[i] : 0u;
-            }
-        }
+        load_ragged<PPT>(p, base, x, y, z, c, in);
     }
 }
 
@@ -498,7 +520,6 @@ __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__res
     }
     const Box box = wave_box<PPT>(px, py, live);
     const uint32_t lane = threadIdx.x & 63u;
-    bool direct[PPT];
     bool tiled = false;
     uint32_t bw = 0, bh = 0;
     if (box.x0 <= box.x1) {
@@ -507,19 +528,19 @@ __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__res
         tiled = (uint64_t)bw * bh <= kWaveTileMin;
     }
     if (tiled) {
+        // the box bounds every live fragment of the wave, so all of them
+        // land in the tile: entry (py - y0) * bw + (px - x0), computed
+        // modulo 2^32 as py * bw + px - org
         const uint32_t area = bw * bh;
+        const uint32_t org = box.y0 * bw + box.x0;
         for (uint32_t i = lane; i < area; i += 64)
             w_tile[i] = ~0ull;
         wave_sync();
 #pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-            const uint32_t tx = px[j] - box.x0, ty = py[j] - box.y0;
-            const bool inside = live[j] && tx < bw && ty < bh;
-            direct[j] = live[j] && !inside;
-            if (inside)
-                __hip_atomic_fetch_min(&w_tile[ty * bw + tx], key[j], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
+        for (int j = 0; j < PPT; ++j)
+            if (live[j])
+                __hip_atomic_fetch_min(&w_tile[py[j] * bw + px[j] - org], key[j],
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         wave_sync();
         const float inv_bw = 1.0f / (float)bw;
         for (uint32_t i = lane; i < area; i += 64) {
@@ -535,25 +556,22 @@ __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__res
             }
         }
         wave_sync();   // the tile is free for the next use
-    } else {
-#pragma unroll
-        for (int j = 0; j < PPT; ++j)
-            direct[j] = live[j];
+        return;
     }
-    // fragments outside the tile: usually none in the whole wave
-    bool any_direct = false;
+    // the wave's fragments spread too far for the tile (or there are none)
+    bool any_live = false;
 #pragma unroll
     for (int j = 0; j < PPT; ++j)
-        any_direct = any_direct || direct[j];
-    if (__any(any_direct)) {
+        any_live = any_live || live[j];
+    if (__any(any_live)) {
         uint64_t cur[PPT];
 #pragma unroll
         for (int j = 0; j < PPT; ++j)
-            cur[j] = __hip_atomic_load(fb + (direct[j] ? pix[j] : 0u), __ATOMIC_RELAXED,
+            cur[j] = __hip_atomic_load(fb + (live[j] ? pix[j] : 0u), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
         for (int j = 0; j < PPT; ++j)
-            if (direct[j] && key[j] < cur[j])
+            if (live[j] && key[j] < cur[j])
                 __hip_atomic_fetch_min(fb + pix[j], key[j], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -721,7 +739,6 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
     }
     const Box box = wave_box<PPT>(px, py, ok);
     const uint32_t lane = threadIdx.x & 63u;
-    bool direct[PPT];
     bool tiled = false;
     uint32_t bw = 0, bh = 0;
     if (box.x0 <= box.x1) {
@@ -730,17 +747,17 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
         tiled = (uint64_t)bw * bh <= kWaveTileHq;
     }
     if (tiled) {
+        // every accepted fragment of the wave lies in the box (see
+        // raster_chunk_wave)
         const uint32_t area = bw * bh;
+        const uint32_t org = box.y0 * bw + box.x0;
         for (uint32_t i = lane; i < 2 * area; i += 64)
             w_tile[i] = 0ull;
         wave_sync();
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-            const uint32_t tx = px[j] - box.x0, ty = py[j] - box.y0;
-            const bool inside = ok[j] && tx < bw && ty < bh;
-            direct[j] = ok[j] && !inside;
-            if (inside) {
-                uint64_t *t = &w_tile[2 * (ty * bw + tx)];
+            if (ok[j]) {
+                uint64_t *t = &w_tile[2 * (py[j] * bw + px[j] - org)];
                 __hip_atomic_fetch_add(t, w0[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 __hip_atomic_fetch_add(t + 1, w1[j], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -761,14 +778,11 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
             }
         }
         wave_sync();
-    } else {
-#pragma unroll
-        for (int j = 0; j < PPT; ++j)
-            direct[j] = ok[j];
+        return;
     }
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        if (direct[j]) {
+        if (ok[j]) {
             uint64_t *a = acc + 2 * (uint64_t)pix[j];
             __hip_atomic_fetch_add(a, w0[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(a + 1, w1[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -32,10 +32,20 @@ __global__ void __launch_bounds__(512) k_raster_min(Pts p, Proj P, uint64_t *__r
     float x[PPT], y[PPT], z[PPT];
     uint32_t c[PPT];
     bool in[PPT];
-    load_points<PPT, VEC>(p, chunk * (int64_t)blockDim.x * PPT, x, y, z, c, in);
+    const int64_t base = chunk * (int64_t)blockDim.x * PPT;
+    uint64_t *w_tile = s_waves + (threadIdx.x >> 6) * kWaveTileWords;
+    if (BIN == kBinWave && VEC && chunk_full<PPT>(p, base)) {
+        // every chunk but the last: no per-point bounds flags to carry
+        load_full<PPT>(p, base, x, y, z, c);
+#pragma unroll
+        for (int j = 0; j < PPT; ++j)
+            in[j] = true;
+        raster_chunk_wave<PPT, PW>(P, fb, x, y, z, c, in, w_tile);
+        return;
+    }
+    load_points<PPT, VEC>(p, base, x, y, z, c, in);
     if (BIN == kBinWave)
-        raster_chunk_wave<PPT, PW>(P, fb, x, y, z, c, in,
-                               s_waves + (threadIdx.x >> 6) * kWaveTileWords);
+        raster_chunk_wave<PPT, PW>(P, fb, x, y, z, c, in, w_tile);
     else
         raster_chunk<PPT, EARLY, BIN == kBinBlock, PW>(P, fb, x, y, z, c, in, s_tile, s_box);
 }
@@ -56,10 +66,19 @@ __global__ void __launch_bounds__(512) k_hq_accum(Pts p, Proj P, uint32_t eps_nu
     float x[PPT], y[PPT], z[PPT];
     uint32_t c[PPT];
     bool in[PPT];
-    load_points<PPT, VEC>(p, chunk * (int64_t)blockDim.x * PPT, x, y, z, c, in);
+    const int64_t base = chunk * (int64_t)blockDim.x * PPT;
+    uint64_t *w_tile = s_waves + (threadIdx.x >> 6) * kWaveTileWords;
+    if (BIN == kBinWave && VEC && chunk_full<PPT>(p, base)) {
+        load_full<PPT>(p, base, x, y, z, c);
+#pragma unroll
+        for (int j = 0; j < PPT; ++j)
+            in[j] = true;
+        accum_chunk_wave<PPT, PW>(P, eps_num, eps_den, fb, acc, x, y, z, c, in, w_tile);
+        return;
+    }
+    load_points<PPT, VEC>(p, base, x, y, z, c, in);
     if (BIN == kBinWave)
-        accum_chunk_wave<PPT, PW>(P, eps_num, eps_den, fb, acc, x, y, z, c, in,
-                                  s_waves + (threadIdx.x >> 6) * kWaveTileWords);
+        accum_chunk_wave<PPT, PW>(P, eps_num, eps_den, fb, acc, x, y, z, c, in, w_tile);
     else
         accum_chunk<PPT, BIN == kBinBlock, PW>(P, eps_num, eps_den, fb, acc, x, y, z, c, in,
                                                s_tile, s_box);
