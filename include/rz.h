@@ -25,7 +25,9 @@
  *   - Framebuffers are row-major, width * height elements, row 0 at the
  *     bottom of the image (OpenGL window convention).
  *   - The view-projection matrix vp is row-major and maps column vectors:
- *     clip = vp * (x, y, z, 1).  Pixel positions are computed in float32
+ *     clip = vp * (x, y, z, 1), each row evaluated as fused multiply-adds
+ *     (one rounding each) in the order fma(r2, z, fma(r1, y, fma(r0, x, r3))).
+ *     Pixel positions are computed in float32
  *     from (float)vp: ndc = clip.xy * (1 / clip.w) with the reciprocal
  *     rounded once, window = (ndc + 1) * size / 2,
  *     pixel = floor(window) in [0, size).  The depth d is row 3 of vp in

@@ -11,8 +11,9 @@
  * Plain, single-threaded and literal: every point is visited in input order,
  * every pixel in row order, one step of the method after the other.  Build
  * with -ffp-contract=off and without fast-math, so that every float and
- * double operation below is one IEEE-754 operation rounded to nearest and no
- * multiply-add is fused.
+ * double operation below is one IEEE-754 operation rounded to nearest: the
+ * only fused multiply-adds are the explicit fmaf / fma calls (one rounding
+ * each, as C99 defines them).
  *
  * What the method computes (section 2.1): each point becomes one fragment,
  * a 64-bit key whose upper 40 bits are an integer depth and whose lower 24
@@ -29,6 +30,10 @@
  * design notes of the repository):
  *  - depth d is the clip-space w of the view-projection (row 3), computed in
  *    double precision; for a perspective matrix it is the linear view depth;
+ *  - the matrix-vector products (clip coordinates and the depth) are chains
+ *    of fused multiply-adds that start from the translation column and add
+ *    the x, y and z terms in that order, as a shader compiler evaluates a
+ *    matrix times a point;
  *  - projection to pixels is done in single precision: clip = VPf * p with
  *    VPf = (float)VP, ndc = clip.xy * (1 / clip.w) (the reciprocal correctly
  *    rounded once, as a perspective divide does), window = (ndc + 1) * size / 2,
@@ -55,8 +60,8 @@
  * depth buffer, the precision the paper's 40-bit integers are set against
  * (sections 1 and 2.1); they are for the depth pass only:
  *  - "gl24": window depth of the perspective matrix in single precision,
- *    z_ndc = clip.z * (1 / clip.w) (row 2 of the float matrix, same operation
- *    order as the other rows), z_win = (z_ndc + 1) / 2, kept as a 24-bit
+ *    z_ndc = clip.z * (1 / clip.w) (row 2 of the float matrix, same fused
+ *    operation order as the other rows), z_win = (z_ndc + 1) / 2, kept as a 24-bit
  *    unsigned normalised integer round(z_win * (2^24 - 1)) (rounding to
  *    nearest, ties up), fragments with z_ndc outside [-1, 1] discarded;
  *  - "f32rev": reversed depth in single precision, z_rev = (float)near /
@@ -214,19 +219,17 @@ static int rzo_fragment(const rzo_cam *c, float x, float y, float z,
     double d;
     int32_t px, py;
 
-    /* clip coordinates in single precision, left to right */
-    cx = m[0] * x;
-    cx = cx + m[1] * y;
-    cx = cx + m[2] * z;
-    cx = cx + m[3];
-    cy = m[4] * x;
-    cy = cy + m[5] * y;
-    cy = cy + m[6] * z;
-    cy = cy + m[7];
-    cw = m[12] * x;
-    cw = cw + m[13] * y;
-    cw = cw + m[14] * z;
-    cw = cw + m[15];
+    /* clip coordinates in single precision: start from the translation
+       column, then add the x, y and z terms, each with one rounding */
+    cx = fmaf(m[0], x, m[3]);
+    cx = fmaf(m[1], y, cx);
+    cx = fmaf(m[2], z, cx);
+    cy = fmaf(m[4], x, m[7]);
+    cy = fmaf(m[5], y, cy);
+    cy = fmaf(m[6], z, cy);
+    cw = fmaf(m[12], x, m[15]);
+    cw = fmaf(m[13], y, cw);
+    cw = fmaf(m[14], z, cw);
     if (!(cw > 0.0f))
         return 0;
 
@@ -241,11 +244,10 @@ static int rzo_fragment(const rzo_cam *c, float x, float y, float z,
     px = (int32_t)fx;
     py = (int32_t)fy;
 
-    /* depth in double precision (section 1, section 2.1) */
-    d = v[12] * (double)x;
-    d = d + v[13] * (double)y;
-    d = d + v[14] * (double)z;
-    d = d + v[15];
+    /* depth in double precision (section 1, section 2.1), same order */
+    d = fma(v[12], (double)x, v[15]);
+    d = fma(v[13], (double)y, d);
+    d = fma(v[14], (double)z, d);
     if (!(d >= c->near_ && d < c->far_))
         return 0;
 
@@ -253,10 +255,9 @@ static int rzo_fragment(const rzo_cam *c, float x, float y, float z,
     if (c->kind == RZO_GL24) {
         /* window depth of the perspective matrix, 24-bit normalised */
         float cz, nz, zw, t;
-        cz = m[8] * x;
-        cz = cz + m[9] * y;
-        cz = cz + m[10] * z;
-        cz = cz + m[11];
+        cz = fmaf(m[8], x, m[11]);
+        cz = fmaf(m[9], y, cz);
+        cz = fmaf(m[10], z, cz);
         nz = cz * iw;
         if (!(nz >= -1.0f && nz <= 1.0f))
             return 0;

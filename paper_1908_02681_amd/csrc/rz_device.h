@@ -8,8 +8,9 @@
 //
 // Every file that includes this header must be compiled with
 // -ffp-contract=off; the pragma below repeats it, so that the projection is
-// the exact IEEE operation sequence stated in include/rz.h (no fused
-// multiply-add, correctly rounded f32 division, no flush of denormals).
+// the exact IEEE operation sequence stated in include/rz.h (fused
+// multiply-adds only where written as such, correctly rounded f32 division,
+// no flush of denormals).
 //
 // Code style rule for the point kernels: decisions are kept in separate
 // boolean flags computed with selects; no element of a register array is
@@ -96,8 +97,9 @@ __device__ __forceinline__ bool in_window(const Proj &P, uint32_t eps_num, uint3
     return lhs <= rhs;
 }
 
-// Pixel of one point (section 2.1's projection in single precision), its
-// clip w and 1 / w (rounded once; x and y are scaled by it, as a
+// Pixel of one point (section 2.1's projection in single precision: each
+// clip coordinate a chain of fused multiply-adds from the translation
+// column through the x, y and z terms), its clip w and 1 / w (rounded once; x and y are scaled by it, as a
 // perspective divide does).  Returns false when the point is culled (w <= 0
 // or off screen).
 // Straight-line code: the pixel of a culled point is 0, never a conversion
@@ -105,18 +107,15 @@ __device__ __forceinline__ bool in_window(const Proj &P, uint32_t eps_num, uint3
 __device__ __forceinline__ bool project(const Proj &P, float x, float y, float z, uint32_t &px,
                                         uint32_t &py, float &cw, float &iw)
 {
-    float cx = P.m[0] * x;
-    cx = cx + P.m[1] * y;
-    cx = cx + P.m[2] * z;
-    cx = cx + P.m[3];
-    float cy = P.m[4] * x;
-    cy = cy + P.m[5] * y;
-    cy = cy + P.m[6] * z;
-    cy = cy + P.m[7];
-    cw = P.m[8] * x;
-    cw = cw + P.m[9] * y;
-    cw = cw + P.m[10] * z;
-    cw = cw + P.m[11];
+    float cx = __builtin_fmaf(P.m[0], x, P.m[3]);
+    cx = __builtin_fmaf(P.m[1], y, cx);
+    cx = __builtin_fmaf(P.m[2], z, cx);
+    float cy = __builtin_fmaf(P.m[4], x, P.m[7]);
+    cy = __builtin_fmaf(P.m[5], y, cy);
+    cy = __builtin_fmaf(P.m[6], z, cy);
+    cw = __builtin_fmaf(P.m[8], x, P.m[11]);
+    cw = __builtin_fmaf(P.m[9], y, cw);
+    cw = __builtin_fmaf(P.m[10], z, cw);
     iw = 1.0f / cw;
     const float nx = cx * iw;
     const float ny = cy * iw;
@@ -128,13 +127,13 @@ __device__ __forceinline__ bool project(const Proj &P, float x, float y, float z
     return vis;
 }
 
-// Depth in double precision (section 1, section 2.1): row 3 of VP.
+// Depth in double precision (section 1, section 2.1): row 3 of VP, fused
+// in the same order as the clip coordinates.
 __device__ __forceinline__ double depth_of(const Proj &P, float x, float y, float z)
 {
-    double d = P.v[0] * (double)x;
-    d = d + P.v[1] * (double)y;
-    d = d + P.v[2] * (double)z;
-    d = d + P.v[3];
+    double d = __builtin_fma(P.v[0], (double)x, P.v[3]);
+    d = __builtin_fma(P.v[1], (double)y, d);
+    d = __builtin_fma(P.v[2], (double)z, d);
     return d;
 }
 
@@ -181,10 +180,9 @@ __device__ __forceinline__ bool fragment_any(const Proj &P, float x, float y, fl
         q = 0xFFFFFFFFull - (uint64_t)__float_as_uint(zr);
         return true;
     }
-    float cz = P.mz[0] * x;
-    cz = cz + P.mz[1] * y;
-    cz = cz + P.mz[2] * z;
-    cz = cz + P.mz[3];
+    float cz = __builtin_fmaf(P.mz[0], x, P.mz[3]);
+    cz = __builtin_fmaf(P.mz[1], y, cz);
+    cz = __builtin_fmaf(P.mz[2], z, cz);
     const float nz = cz * iw;
     if (!(nz >= -1.0f && nz <= 1.0f))
         return false;

@@ -11,17 +11,18 @@ from oracle import oracle as O
 from tests import test_oracle as T
 
 MUTANTS = {
-    "transposed matrix": ("cx = cx + m[1] * y;", "cx = cx + m[4] * y;"),
-    "dropped translation": ("cx = cx + m[3];", ""),
-    "wrong w row": ("cw = m[12] * x;", "cw = m[8] * x;"),
+    "transposed matrix": ("cx = fmaf(m[1], y, cx);", "cx = fmaf(m[4], y, cx);"),
+    "dropped translation": ("cx = fmaf(m[0], x, m[3]);", "cx = m[0] * x;"),
+    "wrong w row": ("cw = fmaf(m[12], x, m[15]);", "cw = fmaf(m[8], x, m[15]);"),
     "viewport sign": ("fx = (nx + 1.0f) * c->hw;", "fx = (nx - 1.0f) * c->hw;"),
     "half sizes swapped": ("fy = (ny + 1.0f) * c->hh;", "fy = (ny + 1.0f) * c->hw;"),
     "ndc scales by the wrong reciprocal": ("ny = cy * iw;", "ny = cy / cx;"),
     "reciprocal of the wrong row": ("iw = 1.0f / cw;", "iw = 1.0f / cx;"),
     "window edge inclusive": ("fx < c->fw", "fx <= c->fw"),
-    "depth from row 2": ("d = v[12] * (double)x;", "d = v[8] * (double)x;"),
-    "depth offset dropped": ("d = d + v[15];", ""),
-    "depth in single precision": ("d = d + v[15];", "d = d + v[15];\n    d = (double)cw;"),
+    "depth from row 2": ("d = fma(v[12], (double)x, v[15]);", "d = fma(v[8], (double)x, v[15]);"),
+    "depth offset dropped": ("d = fma(v[12], (double)x, v[15]);", "d = v[12] * (double)x;"),
+    "depth in single precision": ("d = fma(v[14], (double)z, d);",
+                                  "d = fma(v[14], (double)z, d);\n    d = (double)cw;"),
     "far inclusive": ("d < c->far_", "d <= c->far_"),
     "near exclusive": ("d >= c->near_", "d > c->near_"),
     "round instead of floor": ("    t = (d - c->o) * c->s;\n    tf = floor(t);",
@@ -57,7 +58,7 @@ MUTANTS = {
         "img[p] = (uint32_t)(fb[p] & RZO_RGB_MASK);\n        fb[p] = RZO_DEPTH_ONES;"),
     "splat background lost": ("img[p] = bg & 0xFFFFFFu;", "img[p] = 0;"),
     "splat sums not cleared": ("        sums[4 * p + 3] = 0;\n", ""),
-    "gl24 z from the w row": ("cz = cz + m[10] * z;", "cz = cz + m[14] * z;"),
+    "gl24 z from the w row": ("cz = fmaf(m[10], z, cz);", "cz = fmaf(m[14], z, cz);"),
     "gl24 window offset dropped": ("zw = (nz + 1.0f) * 0.5f;", "zw = nz * 0.5f;"),
     "gl24 truncates": ("*q = (uint64_t)floor((double)t + 0.5);", "*q = (uint64_t)floor((double)t);"),
     "gl24 not clipped": ("        if (!(nz >= -1.0f && nz <= 1.0f))\n            return 0;\n", ""),
