@@ -305,6 +305,29 @@ int rz_get_launch(rz_launch *launch);
 int rz_merge_min(uint64_t *dst, const uint64_t *src, int64_t npix, void *stream);
 int rz_merge_sum(uint64_t *dst, const uint64_t *src, int64_t npix, void *stream);
 
+/* ---- arithmetic self-check ------------------------------------------- */
+/*
+ * The perspective divide of section 2.1 needs 1 / w rounded once (the IEEE
+ * quotient).  The kernels take it from the hardware reciprocal estimate
+ * with one fused Newton-Raphson correction, and fall back to the full IEEE
+ * division for denormal w and w >= 2^126.  rz_check_reciprocal runs that
+ * same device function over the float bit patterns first_bits ..
+ * first_bits + count - 1 and adds to *mismatches (a device counter the
+ * caller zeroes) the number of positive w (including +inf) whose result
+ * differs in any bit from 1.0f / w.  Patterns of w <= 0 and NaN are not
+ * counted (the kernels cull those points).  Zero over all 2^31 positive
+ * patterns is what the kernels' bit-exactness relies on; a caller moving
+ * the library to another device or compiler can re-run it.  With flags =
+ * RZ_CHECK_ESTIMATE_ONLY the corrected estimate is checked without the
+ * fallback (it must be exact on [2^-126, 2^126), the range where the
+ * kernels use it alone).
+ * Errors: RZ_EINVAL (unknown flags, count < 0, first_bits + count > 2^32,
+ * mismatches NULL or not 8-byte aligned), RZ_EHIP.
+ */
+#define RZ_CHECK_ESTIMATE_ONLY 1u
+int rz_check_reciprocal(uint32_t first_bits, int64_t count, uint64_t *mismatches, uint32_t flags,
+                        void *stream);
+
 /* ---- batched multi-view rendering ------------------------------------ */
 /*
  * Many views of one resident cloud in one submission.  Views are taken in

@@ -97,6 +97,36 @@ __device__ __forceinline__ bool in_window(const Proj &P, uint32_t eps_num, uint3
     return lhs <= rhs;
 }
 
+// True when the predicate holds on any active lane of the wave: the ballot
+// mask itself (HIP's __any goes through an int and costs two more vector
+// instructions per call).
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+
+// The IEEE quotient 1 / w for w > 0, without the full division sequence:
+// one Newton-Raphson correction of the hardware estimate, r + r * (1 - w r)
+// with both steps fused (Markstein's method).  Run over every positive
+// float on gfx950, it equals the correctly rounded reciprocal for all w in
+// [2^-126, 2^126) and misses only for denormal w, w >= 2^126 and +inf;
+// those lanes take the division.  For w <= 0 or NaN the value is never
+// used (every caller culls the point), so it is left as it comes.
+__device__ __forceinline__ float recip_newton(float w)
+{
+    const float r = __builtin_amdgcn_rcpf(w);
+    const float e = __builtin_fmaf(-w, r, 1.0f);
+    return __builtin_fmaf(r, e, r);
+}
+
+__device__ __forceinline__ float recip_rn(float w)
+{
+    float f = recip_newton(w);
+    const bool slow = (w > 0.0f) & ((w < 0x1p-126f) | (w >= 0x1p126f));
+    if (wave_any(slow)) {   // wave-uniform; no lane needs it in practice
+        const float q = 1.0f / w;
+        f = slow ? q : f;
+    }
+    return f;
+}
+
 // Pixel of one point (section 2.1's projection in single precision: each
 // clip coordinate a chain of fused multiply-adds from the translation
 // column through the x, y and z terms), its clip w and 1 / w (rounded once; x and y are scaled by it, as a
@@ -116,12 +146,12 @@ __device__ __forceinline__ bool project(const Proj &P, float x, float y, float z
     cw = __builtin_fmaf(P.m[8], x, P.m[11]);
     cw = __builtin_fmaf(P.m[9], y, cw);
     cw = __builtin_fmaf(P.m[10], z, cw);
-    iw = 1.0f / cw;
+    iw = recip_rn(cw);
     const float nx = cx * iw;
     const float ny = cy * iw;
     const float fx = (nx + 1.0f) * P.hw;
     const float fy = (ny + 1.0f) * P.hh;
-    const bool vis = cw > 0.0f && fx >= 0.0f && fx < P.fw && fy >= 0.0f && fy < P.fh;
+    const bool vis = (cw > 0.0f) & (fx >= 0.0f) & (fx < P.fw) & (fy >= 0.0f) & (fy < P.fh);
     px = (uint32_t)(int32_t)(vis ? fx : 0.0f);
     py = (uint32_t)(int32_t)(vis ? fy : 0.0f);
     return vis;
@@ -150,7 +180,7 @@ __device__ __forceinline__ bool fragment(const Proj &P, float x, float y, float 
     float cw, iw;
     const bool vis = project(P, x, y, z, px, py, cw, iw);
     q = 0;
-    if (!__any(vis))
+    if (!wave_any(vis))
         return false;
     const double d = depth_of(P, x, y, z);
     const bool in_range = d >= P.near_ && d < P.far_;
@@ -561,7 +591,7 @@ __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__res
 #pragma unroll
     for (int j = 0; j < PPT; ++j)
         any_live = any_live || live[j];
-    if (__any(any_live)) {
+    if (wave_any(any_live)) {
         uint64_t cur[PPT];
 #pragma unroll
         for (int j = 0; j < PPT; ++j)

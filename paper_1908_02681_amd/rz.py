@@ -25,6 +25,7 @@ RZ_EBUDGET = -5
 RZ_ESTATE = -6
 RZ_KEEP_KEYS = 1
 RZ_STATUS_HQ_OVERFLOW = 1
+RZ_CHECK_ESTIMATE_ONLY = 1
 DEPTH_LINEAR = 0
 DEPTH_SCALE = 1
 DEPTH_PIECEWISE = 2
@@ -122,6 +123,7 @@ SIGNATURES = {
                          ctypes.c_int),
     "rz_merge_min": ([c_void_p, c_void_p, c_int64, c_void_p], ctypes.c_int),
     "rz_merge_sum": ([c_void_p, c_void_p, c_int64, c_void_p], ctypes.c_int),
+    "rz_check_reciprocal": ([c_uint32, c_int64, c_void_p, c_uint32, c_void_p], ctypes.c_int),
     "rz_clear": ([c_void_p, c_void_p, c_int64, c_uint32, c_void_p], ctypes.c_int),
     "rz_hq_accumulate": ([P(rz_points), P(rz_view), P(rz_depth_map), P(rz_hq_params), c_void_p,
                           c_void_p, c_void_p], ctypes.c_int),
@@ -457,6 +459,18 @@ def merge_sum(dst, src, npix=None, stream=None):
     n = dst.numel() // 2 if npix is None else int(npix)
     _check(load().rz_merge_sum(_ptr(dst), _ptr(src), n, _stream(stream)), "rz_merge_sum")
     return dst
+
+
+def check_reciprocal(first_bits=0, count=1 << 32, estimate_only=False, stream=None):
+    """Number of positive float patterns in [first_bits, first_bits + count)
+    whose reciprocal, as the kernels compute it (or only its corrected
+    estimate), differs from 1.0f / w; a one-element device tensor."""
+    torch = _torch()
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    flags = RZ_CHECK_ESTIMATE_ONLY if estimate_only else 0
+    _check(load().rz_check_reciprocal(int(first_bits), int(count), _ptr(out), flags,
+                                      _stream(stream)), "rz_check_reciprocal")
+    return out
 
 
 def set_launch(block=64, ppt=16, early_out=1, xcd_remap=0, bin=2):

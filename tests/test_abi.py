@@ -37,7 +37,7 @@ def test_header_declares_the_entry_points():
     names = declared_functions()
     for n in ("rasterize_atomicmin", "rasterize_hq_splat", "rz_clear", "rz_resolve_min",
               "rz_resolve_hq", "rz_error_string", "rasterize_sorted", "rz_sorted_workspace_bytes",
-              "rasterize_points", "rz_merge_min", "rz_merge_sum"):
+              "rasterize_points", "rz_merge_min", "rz_merge_sum", "rz_check_reciprocal"):
         assert n in names
 
 
@@ -195,6 +195,19 @@ def test_merge_validation(rz):
         assert fn(None, P(1 << 20), 4, None) == E
         assert fn(P(256 + 8), P(1 << 20), 4, None) == E          # not 16-byte aligned
         assert fn(P(4096), P(4096 + 16), 4, None) == E           # overlapping
+
+
+def test_reciprocal_check_validation(rz):
+    lib = rz.load()
+    E = rz.RZ_EINVAL
+    P = ctypes.c_void_p
+    assert lib.rz_check_reciprocal(0, -1, P(256), 0, None) == E
+    assert lib.rz_check_reciprocal(1, 1 << 32, P(256), 0, None) == E       # past 2^32 patterns
+    assert lib.rz_check_reciprocal(0xFFFFFFFF, 2, P(256), 0, None) == E
+    assert lib.rz_check_reciprocal(0, 16, None, 0, None) == E
+    assert lib.rz_check_reciprocal(0, 16, P(256 + 4), 0, None) == E       # not 8-byte aligned
+    assert lib.rz_check_reciprocal(0, 16, P(256), 2, None) == E            # unknown flag
+    assert lib.rz_check_reciprocal(0, 0, P(256), rz.RZ_CHECK_ESTIMATE_ONLY, None) == rz.RZ_OK
 
 
 def test_launch_shape_validation(rz):

@@ -233,6 +233,63 @@ def test_degenerate_points(rz, oracle):
     check_scene(rz, oracle, cloud, view, label="degenerate")
 
 
+def test_reciprocal_is_the_ieee_quotient(rz):
+    """The projection's 1 / w, as compiled into the library, equals the
+    IEEE quotient 1.0f / w for every positive float, denormals and +inf
+    included (about a millisecond of GPU time).  The corrected estimate on
+    its own is exact on [2^-126, 2^126), where the kernels use it alone,
+    and not below it, so the check does count what differs."""
+    import torch
+    say("[parity] reciprocal over every positive float")
+    normal = (0x00800000, 0x7E800000 - 0x00800000)   # [2^-126, 2^126)
+    counts = {
+        "all positive": rz.check_reciprocal(1, 0x7F800000),
+        "negative patterns": rz.check_reciprocal(0x80000000, 1 << 31),
+        "estimate, normal range": rz.check_reciprocal(*normal, estimate_only=True),
+        "estimate, denormals": rz.check_reciprocal(1, 0x007FFFFF, estimate_only=True),
+    }
+    torch.cuda.synchronize()
+    counts = {k: int(v.item()) for k, v in counts.items()}
+    say(f"[parity] reciprocal mismatches: {counts}")
+    assert counts["all positive"] == 0 and counts["estimate, normal range"] == 0
+    assert counts["negative patterns"] == 0          # not counted by definition
+    assert counts["estimate, denormals"] > 0
+
+
+@pytest.mark.parametrize("lo,hi", [(124.5, 127.99), (-129.5, -124.5)])
+def test_extreme_clip_w(rz, oracle, lo, hi):
+    """Clip w from about 2^-129 (denormal) to just below 2^128, straddling
+    2^-126 and 2^126, where the kernels switch from the Newton-corrected
+    reciprocal to the IEEE division; every wave mixes both kinds of lanes.
+    Both passes and the point-size kernel match the oracle bit for bit."""
+    import torch
+    rng = np.random.default_rng(11)
+    n, W, H = 20000, 24, 16
+    vp = np.zeros((4, 4))
+    vp[0, 1] = vp[1, 2] = vp[3, 0] = 1.0          # clip = (y, z, 0, x)
+    w = np.exp2(rng.uniform(lo, hi, n)).astype(np.float32)
+    fmax = float(np.finfo(np.float32).max)
+    y = np.clip(w * rng.uniform(-1.1, 1.1, n), -fmax, fmax).astype(np.float32)
+    z = np.clip(w * rng.uniform(-1.1, 1.1, n), -fmax, fmax).astype(np.float32)
+    rgb = rng.integers(0, 1 << 24, n, dtype=np.uint32)
+    view = gen.View(vp, 2.0 ** (lo - 1), 2.0 ** (hi + 1), W, H)
+    cloud = gen.Cloud(w, y, z, rgb)
+    pix, _ = oracle.fragments(w, y, z, vp, view.near, view.far, W, H)
+    big, tiny = w >= np.float32(2.0 ** 126), w < np.float32(2.0 ** -126)
+    edge = big if lo > 0 else tiny
+    say(f"[parity] extreme w {lo}..{hi}: {int((pix[edge] >= 0).sum())} visible in the division range")
+    assert (pix[edge] >= 0).sum() > 1000 and (pix[~edge] >= 0).sum() > 1000
+    keys, _ = check_scene(rz, oracle, cloud, view, label=f"extreme w {lo}..{hi}")
+    assert (keys != np.uint64(oracle.clear_value(0))).sum() > W * H // 2
+    pts = rz.Points.from_cloud(cloud)
+    fb, _ = rz.new_framebuffer(view, 0)
+    rz.rasterize_points(pts, view, None, False, (1, 100), 2, 0, fb=fb, keep_keys=True)
+    got = rz.to_u64(fb)
+    torch.cuda.synchronize()
+    want, _ = oracle.render_atomicmin(w, y, z, rgb, vp, view.near, view.far, W, H, point_size=2)
+    assert np.array_equal(got, want)
+
+
 def test_config2_terrain_full_size(rz, oracle):
     """The 50M-point Morton terrain at 1920x1080, every pixel, both modes."""
     cloud, view = gen.config2()
