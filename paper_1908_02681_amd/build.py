@@ -22,8 +22,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 # -ffp-contract=off: the projection must be the exact IEEE operation sequence
-# of the interface (no fused multiply-add); packed fp32 instructions are
-# disabled for all device code.
+# of the interface (fused multiply-adds only where the source writes them);
+# packed fp32 instructions are disabled for all device code.
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-fno-gpu-rdc", "-Wall", "-Wno-unused-function",

@@ -73,7 +73,11 @@ __global__ void __launch_bounds__(512) k_mv_raster_min(Pts p, const MvView *__re
     float x[PPT], y[PPT], z[PPT];
     uint32_t c[PPT];
     bool in[PPT];
-    load_points<PPT, VEC>(p, chunk * (int64_t)blockDim.x * PPT, x, y, z, c, in);
+    // points past the end load as NaN and are culled: no bounds flags
+    load_points_nan<PPT, VEC>(p, chunk * (int64_t)blockDim.x * PPT, x, y, z, c);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j)
+        in[j] = true;
     for (int32_t k = 0; k < nv; ++k) {
         const Proj P = views[k].P;
         if (BIN == kBinWave) {
@@ -102,7 +106,11 @@ __global__ void __launch_bounds__(512) k_mv_hq_accum(Pts p, const MvView *__rest
     float x[PPT], y[PPT], z[PPT];
     uint32_t c[PPT];
     bool in[PPT];
-    load_points<PPT, VEC>(p, chunk * (int64_t)blockDim.x * PPT, x, y, z, c, in);
+    // points past the end load as NaN and are culled: no bounds flags
+    load_points_nan<PPT, VEC>(p, chunk * (int64_t)blockDim.x * PPT, x, y, z, c);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j)
+        in[j] = true;
     for (int32_t k = 0; k < nv; ++k) {
         const Proj P = views[k].P;
         if (BIN == kBinWave) {

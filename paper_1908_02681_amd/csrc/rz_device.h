@@ -127,6 +127,31 @@ __device__ __forceinline__ float recip_rn(float w)
     return f;
 }
 
+// Translation column of the float matrix (clip x, y, w), the addend of
+// the first fused step of each row.  lane_trans() returns it as per-lane
+// values (an identity DPP move), made once per chunk: a fused multiply-add
+// can take only one scalar-register operand on gfx950, so with the scalar
+// copies every row of every point would need a move first.
+struct Trans {
+    float tx, ty, tw;
+};
+
+__device__ __forceinline__ float lane_copy(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xE4, 0xF, 0xF,
+                                                      false));   // quad_perm [0,1,2,3]
+}
+
+__device__ __forceinline__ Trans lane_trans(const Proj &P)
+{
+    return Trans{lane_copy(P.m[3]), lane_copy(P.m[7]), lane_copy(P.m[11])};
+}
+
+__device__ __forceinline__ Trans scalar_trans(const Proj &P)
+{
+    return Trans{P.m[3], P.m[7], P.m[11]};
+}
+
 // Pixel of one point (section 2.1's projection in single precision: each
 // clip coordinate a chain of fused multiply-adds from the translation
 // column through the x, y and z terms), its clip w and 1 / w (rounded once; x and y are scaled by it, as a
@@ -134,16 +159,16 @@ __device__ __forceinline__ float recip_rn(float w)
 // or off screen).
 // Straight-line code: the pixel of a culled point is 0, never a conversion
 // of an out-of-range float.
-__device__ __forceinline__ bool project(const Proj &P, float x, float y, float z, uint32_t &px,
-                                        uint32_t &py, float &cw, float &iw)
+__device__ __forceinline__ bool project(const Proj &P, const Trans &T, float x, float y, float z,
+                                        uint32_t &px, uint32_t &py, float &cw, float &iw)
 {
-    float cx = __builtin_fmaf(P.m[0], x, P.m[3]);
+    float cx = __builtin_fmaf(P.m[0], x, T.tx);
     cx = __builtin_fmaf(P.m[1], y, cx);
     cx = __builtin_fmaf(P.m[2], z, cx);
-    float cy = __builtin_fmaf(P.m[4], x, P.m[7]);
+    float cy = __builtin_fmaf(P.m[4], x, T.ty);
     cy = __builtin_fmaf(P.m[5], y, cy);
     cy = __builtin_fmaf(P.m[6], z, cy);
-    cw = __builtin_fmaf(P.m[8], x, P.m[11]);
+    cw = __builtin_fmaf(P.m[8], x, T.tw);
     cw = __builtin_fmaf(P.m[9], y, cw);
     cw = __builtin_fmaf(P.m[10], z, cw);
     iw = recip_rn(cw);
@@ -174,11 +199,11 @@ __device__ __forceinline__ double depth_of(const Proj &P, float x, float y, floa
 // every integer map.  Straight-line code apart from one wave-uniform skip
 // of the depth when no lane of the wave is on screen.
 template <bool PW>
-__device__ __forceinline__ bool fragment(const Proj &P, float x, float y, float z,
+__device__ __forceinline__ bool fragment(const Proj &P, const Trans &T, float x, float y, float z,
                                          uint32_t &px, uint32_t &py, uint64_t &q)
 {
     float cw, iw;
-    const bool vis = project(P, x, y, z, px, py, cw, iw);
+    const bool vis = project(P, T, x, y, z, px, py, cw, iw);
     q = 0;
     if (!wave_any(vis))
         return false;
@@ -191,6 +216,13 @@ __device__ __forceinline__ bool fragment(const Proj &P, float x, float y, float 
     return vis && in_range;
 }
 
+template <bool PW>
+__device__ __forceinline__ bool fragment(const Proj &P, float x, float y, float z,
+                                         uint32_t &px, uint32_t &py, uint64_t &q)
+{
+    return fragment<PW>(P, scalar_trans(P), x, y, z, px, py, q);
+}
+
 // fragment() for every depth encoding: the integer maps, the 24-bit window
 // depth of the perspective matrix (RZ_DEPTH_GL24) and the complemented
 // reversed float depth (RZ_DEPTH_F32REV).
@@ -200,7 +232,7 @@ __device__ __forceinline__ bool fragment_any(const Proj &P, float x, float y, fl
     if (P.zkind == 0)
         return fragment<true>(P, x, y, z, px, py, q);
     float cw, iw;
-    if (!project(P, x, y, z, px, py, cw, iw))
+    if (!project(P, scalar_trans(P), x, y, z, px, py, cw, iw))
         return false;
     const double d = depth_of(P, x, y, z);
     if (!(d >= P.near_ && d < P.far_))
@@ -283,6 +315,36 @@ __device__ __forceinline__ void load_ragged(const Pts &p, int64_t base, float (&
             x[4 * g + k] = ok ? p.x[i] : 0.0f;
             y[4 * g + k] = ok ? p.y[i] : 0.0f;
             z[4 * g + k] = ok ? p.z[i] : 0.0f;
+            c[4 * g + k] = ok ? p.rgb[i] : 0u;
+        }
+    }
+}
+
+// The same loads for kernels that carry no per-point bounds flags: points
+// past the end read as NaN, which every projection culls (a NaN coordinate
+// makes clip w NaN, and w > 0 fails), so the chunk code is the same for the
+// last chunk as for all others.
+template <int PPT, bool VEC>
+__device__ __forceinline__ void load_points_nan(const Pts &p, int64_t base, float (&x)[PPT],
+                                                float (&y)[PPT], float (&z)[PPT],
+                                                uint32_t (&c)[PPT])
+{
+    if (VEC && chunk_full<PPT>(p, base)) {
+        load_full<PPT>(p, base, x, y, z, c);
+        return;
+    }
+    const int64_t stride = 4 * (int64_t)blockDim.x;
+    const int64_t first = base + 4 * (int64_t)threadIdx.x;
+    const float nan = __builtin_nanf("");
+#pragma unroll
+    for (int g = 0; g < PPT / 4; ++g) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = first + g * stride + k;
+            const bool ok = i < p.n;
+            x[4 * g + k] = ok ? p.x[i] : nan;
+            y[4 * g + k] = ok ? p.y[i] : nan;
+            z[4 * g + k] = ok ? p.z[i] : nan;
             c[4 * g + k] = ok ? p.rgb[i] : 0u;
         }
     }
@@ -529,22 +591,16 @@ __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__res
     uint32_t px[PPT], py[PPT], pix[PPT];
     uint64_t key[PPT];
     bool live[PPT];
+    const Trans T = lane_trans(P);
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         uint64_t q = 0;
         uint32_t a = 0, b = 0;
-        live[j] = fragment<PW>(P, x[j], y[j], z[j], a, b, q) & in[j];
+        live[j] = fragment<PW>(P, T, x[j], y[j], z[j], a, b, q) & in[j];
         px[j] = a;
         py[j] = b;
         pix[j] = b * (uint32_t)P.width + a;
         key[j] = (q << 24) | ((uint64_t)c[j] & kRgbMask);
-    }
-#pragma unroll
-    for (int j = 1; j < PPT; ++j) {
-        const bool same = live[j] && live[j - 1] && pix[j] == pix[j - 1];
-        const uint64_t lo = key[j] < key[j - 1] ? key[j] : key[j - 1];
-        key[j] = same ? lo : key[j];
-        live[j - 1] = live[j - 1] && !same;
     }
     const Box box = wave_box<PPT>(px, py, live);
     const uint32_t lane = threadIdx.x & 63u;
@@ -586,7 +642,17 @@ __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__res
         wave_sync();   // the tile is free for the next use
         return;
     }
-    // the wave's fragments spread too far for the tile (or there are none)
+    // the wave's fragments spread too far for the tile (or there are none):
+    // runs of one pixel are merged in registers (LDS atomics need no such
+    // help), then each remaining fragment takes an early-out read and a
+    // global atomic
+#pragma unroll
+    for (int j = 1; j < PPT; ++j) {
+        const bool same = live[j] && live[j - 1] && pix[j] == pix[j - 1];
+        const uint64_t lo = key[j] < key[j - 1] ? key[j] : key[j - 1];
+        key[j] = same ? lo : key[j];
+        live[j - 1] = live[j - 1] && !same;
+    }
     bool any_live = false;
 #pragma unroll
     for (int j = 0; j < PPT; ++j)
@@ -733,11 +799,12 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
     uint32_t px[PPT], py[PPT], pix[PPT];
     uint64_t q[PPT];
     bool ok[PPT];
+    const Trans T = lane_trans(P);
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         uint32_t a = 0, b = 0;
         uint64_t qq = 0;
-        ok[j] = fragment<PW>(P, x[j], y[j], z[j], a, b, qq) & in[j];
+        ok[j] = fragment<PW>(P, T, x[j], y[j], z[j], a, b, qq) & in[j];
         px[j] = a;
         py[j] = b;
         pix[j] = b * (uint32_t)P.width + a;
@@ -758,6 +825,9 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
         w0[j] = (uint64_t)(c[j] & 0xFFu) | ((uint64_t)((c[j] >> 8) & 0xFFu) << 32);
         w1[j] = (uint64_t)((c[j] >> 16) & 0xFFu) | (1ull << 32);
     }
+    // runs of one pixel summed in registers: unlike the depth pass's LDS
+    // minimum, the tile's two 64-bit LDS adds per fragment are slower than
+    // this merge on runs of Morton-ordered points
 #pragma unroll
     for (int j = 1; j < PPT; ++j) {
         const bool same = ok[j] && ok[j - 1] && pix[j] == pix[j - 1];

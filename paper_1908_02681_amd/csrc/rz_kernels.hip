@@ -34,16 +34,11 @@ __global__ void __launch_bounds__(512) k_raster_min(Pts p, Proj P, uint64_t *__r
     bool in[PPT];
     const int64_t base = chunk * (int64_t)blockDim.x * PPT;
     uint64_t *w_tile = s_waves + (threadIdx.x >> 6) * kWaveTileWords;
-    if (BIN == kBinWave && VEC && chunk_full<PPT>(p, base)) {
-        // every chunk but the last: no per-point bounds flags to carry
-        load_full<PPT>(p, base, x, y, z, c);
+    // no per-point bounds flags: points past the end load as NaN and are culled
+    load_points_nan<PPT, VEC>(p, base, x, y, z, c);
 #pragma unroll
-        for (int j = 0; j < PPT; ++j)
-            in[j] = true;
-        raster_chunk_wave<PPT, PW>(P, fb, x, y, z, c, in, w_tile);
-        return;
-    }
-    load_points<PPT, VEC>(p, base, x, y, z, c, in);
+    for (int j = 0; j < PPT; ++j)
+        in[j] = true;
     if (BIN == kBinWave)
         raster_chunk_wave<PPT, PW>(P, fb, x, y, z, c, in, w_tile);
     else
@@ -68,15 +63,10 @@ __global__ void __launch_bounds__(512) k_hq_accum(Pts p, Proj P, uint32_t eps_nu
     bool in[PPT];
     const int64_t base = chunk * (int64_t)blockDim.x * PPT;
     uint64_t *w_tile = s_waves + (threadIdx.x >> 6) * kWaveTileWords;
-    if (BIN == kBinWave && VEC && chunk_full<PPT>(p, base)) {
-        load_full<PPT>(p, base, x, y, z, c);
+    load_points_nan<PPT, VEC>(p, base, x, y, z, c);
 #pragma unroll
-        for (int j = 0; j < PPT; ++j)
-            in[j] = true;
-        accum_chunk_wave<PPT, PW>(P, eps_num, eps_den, fb, acc, x, y, z, c, in, w_tile);
-        return;
-    }
-    load_points<PPT, VEC>(p, base, x, y, z, c, in);
+    for (int j = 0; j < PPT; ++j)
+        in[j] = true;
     if (BIN == kBinWave)
         accum_chunk_wave<PPT, PW>(P, eps_num, eps_den, fb, acc, x, y, z, c, in, w_tile);
     else
