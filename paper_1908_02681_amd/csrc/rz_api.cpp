@@ -142,6 +142,8 @@ int make_proj(const rz_view *v, const rz_depth_map *dm, Proj *P)
     P->o = o;
     P->s = s;
     P->z0 = (uint64_t)z0;
+    P->z0d = z0;
+    P->wfp = z0 < 4503599627370496.0 ? 1 : 0;   // 2^52
     P->width = v->width;
     P->height = v->height;
     return RZ_OK;

@@ -59,6 +59,11 @@ __device__ __forceinline__ uint64_t to_u64(double t)
     return (uint64_t)__double_as_longlong(t + 0x1p52) & 0xFFFFFFFFFFFFFull;
 }
 
+// True when the predicate holds on any active lane of the wave: the ballot
+// mask itself (HIP's __any goes through an int and costs two more vector
+// instructions per call).
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+
 // Piecewise depth map (section 2.1, sub-ranges with their own precision):
 // range k with start rb[k] <= d < rb[k+1]; q = rbase[k] + floor((d - rb[k]) *
 // rs[k]), which stays below rbase[k+1] because IEEE rounding is monotone.
@@ -97,10 +102,38 @@ __device__ __forceinline__ bool in_window(const Proj &P, uint32_t eps_num, uint3
     return lhs <= rhs;
 }
 
-// True when the predicate holds on any active lane of the wave: the ballot
-// mask itself (HIP's __any goes through an int and costs two more vector
-// instructions per call).
-__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+// Integer depth below 2^52 as a double (exact): its bits under the
+// exponent of 2^52, minus 2^52.
+__device__ __forceinline__ double int52_to_double(uint64_t v)
+{
+    return __longlong_as_double((long long)(v | 0x4330000000000000ull)) - 0x1p52;
+}
+
+// live && in_window, for the accumulate passes.  Linear maps with z0 < 2^52
+// decide in double precision first: D = q - qmin and S = qmin + z0 are
+// exact there, den * D and num * S are each rounded once, and rounding is
+// monotone, so when the rounded products differ they order the exact ones
+// the same way.  Only equal rounded products (a fragment on the window's
+// edge) take the integer test, in a branch a wave enters only when one of
+// its live lanes needs it.  Same result as in_window for every input; the
+// 64-bit integer products it avoids are quarter-rate instructions.
+template <bool PW>
+__device__ __forceinline__ bool in_window_live(const Proj &P, uint32_t eps_num, uint32_t eps_den,
+                                               uint64_t q, uint64_t qmin, bool live)
+{
+    if ((PW && P.nr != 0) || !P.wfp)
+        return live && in_window<PW>(P, eps_num, eps_den, q, qmin);
+    const double dm = int52_to_double(qmin);
+    const double lhs = (double)eps_den * (int52_to_double(q) - dm);
+    const double rhs = (double)eps_num * (dm + P.z0d);
+    bool ok = live & (lhs < rhs);
+    const bool edge = live & (lhs == rhs);
+    if (wave_any(edge)) {
+        const bool ex = (uint64_t)eps_den * (q - qmin) <= (uint64_t)eps_num * (qmin + P.z0);
+        ok = edge ? ex : ok;
+    }
+    return ok;
+}
 
 // The IEEE quotient 1 / w for w > 0, without the full division sequence:
 // one Newton-Raphson correction of the hardware estimate, r + r * (1 - w r)
@@ -458,7 +491,7 @@ __device__ __forceinline__ void raster_chunk(const Proj &P, uint64_t *__restrict
         live[j] = fragment<PW>(P, x[j], y[j], z[j], a, b, q) & in[j];
         px[j] = a;
         py[j] = b;
-        pix[j] = b * (uint32_t)P.width + a;
+        pix[j] = __umul24(b, (uint32_t)P.width) + a;   // both below 2^15
         key[j] = (q << 24) | ((uint64_t)c[j] & kRgbMask);
     }
 #pragma unroll
@@ -501,7 +534,7 @@ __device__ __forceinline__ void raster_chunk(const Proj &P, uint64_t *__restrict
             if (v != ~0ull) {
                 const uint32_t r = i / bw;
                 const uint32_t col = i - r * bw;
-                uint64_t *dst = fb + (uint64_t)(box.y0 + r) * (uint32_t)P.width + box.x0 + col;
+                uint64_t *dst = fb + (__umul24(box.y0 + r, (uint32_t)P.width) + box.x0 + col);
                 const uint64_t cur = __hip_atomic_load(dst, __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_AGENT);
                 if (v < cur)
@@ -550,10 +583,10 @@ __device__ __forceinline__ void tile_rc(uint32_t i, uint32_t bw, float inv_bw, u
                                         uint32_t &col)
 {
     uint32_t q = (uint32_t)((float)i * inv_bw);
-    q = q * bw > i ? q - 1 : q;
-    q = (q + 1) * bw <= i ? q + 1 : q;
+    q = __umul24(q, bw) > i ? q - 1 : q;          // products below 2^25
+    q = __umul24(q + 1, bw) <= i ? q + 1 : q;
     r = q;
-    col = i - q * bw;
+    col = i - __umul24(q, bw);
 }
 
 // Screen rectangle of the live fragments of one wave (no workgroup barrier).
@@ -599,7 +632,7 @@ __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__res
         live[j] = fragment<PW>(P, T, x[j], y[j], z[j], a, b, q) & in[j];
         px[j] = a;
         py[j] = b;
-        pix[j] = b * (uint32_t)P.width + a;
+        pix[j] = __umul24(b, (uint32_t)P.width) + a;   // both below 2^15
         key[j] = (q << 24) | ((uint64_t)c[j] & kRgbMask);
     }
     const Box box = wave_box<PPT>(px, py, live);
@@ -623,7 +656,7 @@ __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__res
 #pragma unroll
         for (int j = 0; j < PPT; ++j)
             if (live[j])
-                __hip_atomic_fetch_min(&w_tile[py[j] * bw + px[j] - org], key[j],
+                __hip_atomic_fetch_min(&w_tile[__umul24(py[j], bw) + px[j] - org], key[j],
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         wave_sync();
         const float inv_bw = 1.0f / (float)bw;
@@ -632,7 +665,7 @@ __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__res
             if (v != ~0ull) {
                 uint32_t r, col;
                 tile_rc(i, bw, inv_bw, r, col);
-                uint64_t *dst = fb + (uint64_t)(box.y0 + r) * (uint32_t)P.width + box.x0 + col;
+                uint64_t *dst = fb + (__umul24(box.y0 + r, (uint32_t)P.width) + box.x0 + col);
                 const uint64_t cur = __hip_atomic_load(dst, __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_AGENT);
                 if (v < cur)
@@ -700,7 +733,7 @@ __device__ __forceinline__ void accum_chunk(const Proj &P, uint32_t eps_num, uin
         ok[j] = fragment<PW>(P, x[j], y[j], z[j], a, b, qq) & in[j];
         px[j] = a;
         py[j] = b;
-        pix[j] = b * (uint32_t)P.width + a;
+        pix[j] = __umul24(b, (uint32_t)P.width) + a;   // both below 2^15
         q[j] = qq;
     }
     // eps window against the finished depth pass: all loads first
@@ -712,7 +745,7 @@ __device__ __forceinline__ void accum_chunk(const Proj &P, uint32_t eps_num, uin
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const uint64_t qmin = fbv[j] >> 24;
-        ok[j] = ok[j] && in_window<PW>(P, eps_num, eps_den, q[j], qmin);
+        ok[j] = in_window_live<PW>(P, eps_num, eps_den, q[j], qmin, ok[j]);
     }
     uint64_t w0[PPT], w1[PPT];
 #pragma unroll
@@ -765,7 +798,7 @@ __device__ __forceinline__ void accum_chunk(const Proj &P, uint32_t eps_num, uin
                 const uint32_t r = i / bw;
                 const uint32_t col = i - r * bw;
                 uint64_t *dst =
-                    acc + 2 * ((uint64_t)(box.y0 + r) * (uint32_t)P.width + box.x0 + col);
+                    acc + 2 * (uint64_t)(__umul24(box.y0 + r, (uint32_t)P.width) + box.x0 + col);
                 __hip_atomic_fetch_add(dst, a0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_fetch_add(dst + 1, a1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
@@ -807,7 +840,7 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
         ok[j] = fragment<PW>(P, T, x[j], y[j], z[j], a, b, qq) & in[j];
         px[j] = a;
         py[j] = b;
-        pix[j] = b * (uint32_t)P.width + a;
+        pix[j] = __umul24(b, (uint32_t)P.width) + a;   // both below 2^15
         q[j] = qq;
     }
     uint64_t fbv[PPT];
@@ -817,7 +850,7 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const uint64_t qmin = fbv[j] >> 24;
-        ok[j] = ok[j] && in_window<PW>(P, eps_num, eps_den, q[j], qmin);
+        ok[j] = in_window_live<PW>(P, eps_num, eps_den, q[j], qmin, ok[j]);
     }
     uint64_t w0[PPT], w1[PPT];
 #pragma unroll
@@ -855,7 +888,7 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             if (ok[j]) {
-                uint64_t *t = &w_tile[2 * (py[j] * bw + px[j] - org)];
+                uint64_t *t = &w_tile[2 * (__umul24(py[j], bw) + px[j] - org)];
                 __hip_atomic_fetch_add(t, w0[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 __hip_atomic_fetch_add(t + 1, w1[j], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -870,7 +903,7 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
                 uint32_t r, col;
                 tile_rc(i, bw, inv_bw, r, col);
                 uint64_t *dst =
-                    acc + 2 * ((uint64_t)(box.y0 + r) * (uint32_t)P.width + box.x0 + col);
+                    acc + 2 * (uint64_t)(__umul24(box.y0 + r, (uint32_t)P.width) + box.x0 + col);
                 __hip_atomic_fetch_add(dst, a0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_fetch_add(dst + 1, a1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }

@@ -29,6 +29,9 @@ struct Proj {
     double rs[8];         // values per unit
     double rinv[8];       // 1 / rs
     uint64_t rbase[9];    // first integer of each range; rbase[nr] = 2^40 - 1
+    double z0d;           // z0 as a double (exact when wfp is set)
+    int32_t wfp;          // z0 < 2^52: the eps window may be pre-tested in double
+    int32_t pad2_;
 };
 
 // Launch shape of the point kernels.  The defaults are those of the depth

@@ -146,6 +146,27 @@ def test_background_and_scale_map(rz, oracle):
     check_scene(rz, oracle, cloud, view, depth=(1, 1000.0), bg=0x3A2B1C, label="mm map, bg")
 
 
+def test_window_with_large_depth_offset(rz, oracle):
+    """A thin depth range far from the camera (near 10 km, far 10 km + 1 m)
+    puts the linear map's offset z0 = floor(near * s) above 2^52, where the
+    accumulate kernels skip their double-precision pre-test of the eps
+    window and use the integer test alone; dense enough that many pixels
+    average several fragments."""
+    rng = np.random.default_rng(21)
+    n = 400_000
+    W, H = 96, 64
+    view = gen.make_view((0, 0, 10000.5), (0, 0, 0), (0, 1, 0), 0.5, W, H, 10000.0, 10001.0)
+    o, s, z0 = oracle.depth_constants(view.vp, view.near, view.far, W, H)
+    assert z0 >= 2 ** 52
+    x = rng.uniform(-45, 45, n).astype(np.float32)
+    y = rng.uniform(-30, 30, n).astype(np.float32)
+    z = rng.uniform(-0.45, 0.45, n).astype(np.float32)
+    rgb = rng.integers(0, 1 << 24, n, dtype=np.uint32)
+    _, sums = check_scene(rz, oracle, gen.Cloud(x, y, z, rgb), view, eps=(1, 100000),
+                          label="z0 above 2^52")
+    assert (sums[:, 3] > 1).sum() > W * H // 4
+
+
 @pytest.mark.parametrize("n", [0, 1, 3, 63, 1000, 4097, 2048 * 8 + 5, 123_457])
 def test_ragged_sizes(rz, oracle, n):
     cloud = gen.terrain(max(n, 1), 5, extent=50.0, amplitude=5.0, wavelength=20.0)
