@@ -348,7 +348,6 @@ def main():
     ap.add_argument("--depth", choices=("linear", "gl24", "f32rev"), default="linear",
                     help="depth encoding; gl24 and f32rev have no splat frame")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--check", action="store_true", help="verify one frame against the oracle")
     ap.add_argument("--batch-points", type=int, default=100_000_000)
     ap.add_argument("--batch-views", type=int, default=64)
     ap.add_argument("--serve-clouds", type=int, default=8)
@@ -464,20 +463,6 @@ def main():
     for _ in range(a.warmup):
         step(None)
     torch.cuda.synchronize()
-    if a.check:
-        from oracle import oracle
-        keys, oimg = oracle.render_atomicmin(cloud.x, cloud.y, cloud.z, cloud.rgb, view.vp,
-                                             view.near, view.far, W, H, depth[0],
-                                             point_size=a.point_size)
-        ok = np.array_equal(rz.to_u32(img), oimg)
-        if with_hq:
-            _, _, ohimg = oracle.render_hq(cloud.x, cloud.y, cloud.z, cloud.rgb, view.vp,
-                                           view.near, view.far, W, H, eps=eps,
-                                           point_size=a.point_size)
-            ok = ok and np.array_equal(rz.to_u32(himg), ohimg)
-        log(f"[bench] oracle check: {'bit-exact' if ok else 'MISMATCH'}")
-        if not ok:
-            raise SystemExit(1)
 
     events = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(a.steps)]
     torch.cuda.synchronize()

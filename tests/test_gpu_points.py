@@ -128,6 +128,14 @@ def test_one_millimetre_at_one_kilometre(rz, oracle):
     assert shown[0] == 1.0 and shown[F32REV] == 1.0 and shown[GL24] < 0.2
 
 
+def test_full_size_terrain(rz, oracle):
+    """The 50M-point terrain at 1920x1080, every pixel: points of 2 x 2
+    pixels (depth and splat frames) and the 24-bit window depth."""
+    cloud, view = gen.config2()
+    check(rz, oracle, cloud, view, k=2, label="50M terrain, point size 2")
+    check(rz, oracle, cloud, view, depth=(GL24, 0.0), k=1, hq=False, label="50M terrain, gl24")
+
+
 @pytest.mark.parametrize("n", [0, 1, 1023, 1025])
 def test_ragged_and_unaligned(rz, oracle, n):
     cloud, view = gen.config1(n=max(n, 2) + 1)
