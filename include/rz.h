@@ -29,7 +29,7 @@
  *     (one rounding each) in the order fma(r2, z, fma(r1, y, fma(r0, x, r3))).
  *     Pixel positions are computed in float32
  *     from (float)vp: ndc = clip.xy * (1 / clip.w) with the reciprocal
- *     rounded once, window = (ndc + 1) * size / 2,
+ *     rounded once, window = fma(ndc, size / 2, size / 2),
  *     pixel = floor(window) in [0, size).  The depth d is row 3 of vp in
  *     double precision (the clip w: linear view depth for a perspective
  *     matrix).  A fragment is kept iff clip.w > 0, the pixel is inside the

@@ -36,7 +36,8 @@
  *    matrix times a point;
  *  - projection to pixels is done in single precision: clip = VPf * p with
  *    VPf = (float)VP, ndc = clip.xy * (1 / clip.w) (the reciprocal correctly
- *    rounded once, as a perspective divide does), window = (ndc + 1) * size / 2,
+ *    rounded once, as a perspective divide does), window = ndc * (size / 2) +
+ *    size / 2 in one fused step (the viewport transform's scale and offset),
  *    pixel = floor(window), half-open [0, size), row 0 at the bottom;
  *  - fragments with w <= 0, outside the window, or with d outside
  *    [near, far) are discarded;
@@ -237,8 +238,8 @@ static int rzo_fragment(const rzo_cam *c, float x, float y, float z,
     iw = 1.0f / cw;
     nx = cx * iw;
     ny = cy * iw;
-    fx = (nx + 1.0f) * c->hw;
-    fy = (ny + 1.0f) * c->hh;
+    fx = fmaf(nx, c->hw, c->hw);
+    fy = fmaf(ny, c->hh, c->hh);
     if (!(fx >= 0.0f && fx < c->fw && fy >= 0.0f && fy < c->fh))
         return 0;
     px = (int32_t)fx;

@@ -160,13 +160,14 @@ __device__ __forceinline__ float recip_rn(float w)
     return f;
 }
 
-// Translation column of the float matrix (clip x, y, w), the addend of
-// the first fused step of each row.  lane_trans() returns it as per-lane
+// Translation column of the float matrix (clip x, y, w) and of the depth
+// row in double, the addend of the first fused step of each row.  lane_trans() returns it as per-lane
 // values (an identity DPP move), made once per chunk: a fused multiply-add
 // can take only one scalar-register operand on gfx950, so with the scalar
 // copies every row of every point would need a move first.
 struct Trans {
     float tx, ty, tw;
+    double td;   // the depth row's translation (double precision)
 };
 
 __device__ __forceinline__ float lane_copy(float v)
@@ -175,14 +176,22 @@ __device__ __forceinline__ float lane_copy(float v)
                                                       false));   // quad_perm [0,1,2,3]
 }
 
+__device__ __forceinline__ double lane_copy(double v)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __float_as_uint(lane_copy(__uint_as_float((uint32_t)b)));
+    const uint32_t hi = __float_as_uint(lane_copy(__uint_as_float((uint32_t)(b >> 32))));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 __device__ __forceinline__ Trans lane_trans(const Proj &P)
 {
-    return Trans{lane_copy(P.m[3]), lane_copy(P.m[7]), lane_copy(P.m[11])};
+    return Trans{lane_copy(P.m[3]), lane_copy(P.m[7]), lane_copy(P.m[11]), lane_copy(P.v[3])};
 }
 
 __device__ __forceinline__ Trans scalar_trans(const Proj &P)
 {
-    return Trans{P.m[3], P.m[7], P.m[11]};
+    return Trans{P.m[3], P.m[7], P.m[11], P.v[3]};
 }
 
 // Pixel of one point (section 2.1's projection in single precision: each
@@ -207,8 +216,8 @@ __device__ __forceinline__ bool project(const Proj &P, const Trans &T, float x, 
     iw = recip_rn(cw);
     const float nx = cx * iw;
     const float ny = cy * iw;
-    const float fx = (nx + 1.0f) * P.hw;
-    const float fy = (ny + 1.0f) * P.hh;
+    const float fx = __builtin_fmaf(nx, P.hw, P.hw);   // viewport: scale and offset
+    const float fy = __builtin_fmaf(ny, P.hh, P.hh);
     const bool vis = (cw > 0.0f) & (fx >= 0.0f) & (fx < P.fw) & (fy >= 0.0f) & (fy < P.fh);
     px = (uint32_t)(int32_t)(vis ? fx : 0.0f);
     py = (uint32_t)(int32_t)(vis ? fy : 0.0f);
@@ -217,12 +226,18 @@ __device__ __forceinline__ bool project(const Proj &P, const Trans &T, float x, 
 
 // Depth in double precision (section 1, section 2.1): row 3 of VP, fused
 // in the same order as the clip coordinates.
-__device__ __forceinline__ double depth_of(const Proj &P, float x, float y, float z)
+__device__ __forceinline__ double depth_of(const Proj &P, const Trans &T, float x, float y,
+                                           float z)
 {
-    double d = __builtin_fma(P.v[0], (double)x, P.v[3]);
+    double d = __builtin_fma(P.v[0], (double)x, T.td);
     d = __builtin_fma(P.v[1], (double)y, d);
     d = __builtin_fma(P.v[2], (double)z, d);
     return d;
+}
+
+__device__ __forceinline__ double depth_of(const Proj &P, float x, float y, float z)
+{
+    return depth_of(P, scalar_trans(P), x, y, z);
 }
 
 // The fragment of one point: pixel coordinates and 40-bit depth (section
@@ -240,7 +255,7 @@ __device__ __forceinline__ bool fragment(const Proj &P, const Trans &T, float x,
     q = 0;
     if (!wave_any(vis))
         return false;
-    const double d = depth_of(P, x, y, z);
+    const double d = depth_of(P, T, x, y, z);
     const bool in_range = d >= P.near_ && d < P.far_;
     if (!PW || P.nr == 0)
         q = to_u64(fmin(floor((d - P.o) * P.s), kQMax));   // d < near gives garbage, unused

@@ -14,8 +14,8 @@ MUTANTS = {
     "transposed matrix": ("cx = fmaf(m[1], y, cx);", "cx = fmaf(m[4], y, cx);"),
     "dropped translation": ("cx = fmaf(m[0], x, m[3]);", "cx = m[0] * x;"),
     "wrong w row": ("cw = fmaf(m[12], x, m[15]);", "cw = fmaf(m[8], x, m[15]);"),
-    "viewport sign": ("fx = (nx + 1.0f) * c->hw;", "fx = (nx - 1.0f) * c->hw;"),
-    "half sizes swapped": ("fy = (ny + 1.0f) * c->hh;", "fy = (ny + 1.0f) * c->hw;"),
+    "viewport sign": ("fx = fmaf(nx, c->hw, c->hw);", "fx = fmaf(nx, c->hw, -c->hw);"),
+    "half sizes swapped": ("fy = fmaf(ny, c->hh, c->hh);", "fy = fmaf(ny, c->hw, c->hw);"),
     "ndc scales by the wrong reciprocal": ("ny = cy * iw;", "ny = cy / cx;"),
     "reciprocal of the wrong row": ("iw = 1.0f / cw;", "iw = 1.0f / cx;"),
     "window edge inclusive": ("fx < c->fw", "fx <= c->fw"),
