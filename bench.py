@@ -638,15 +638,24 @@ KERNEL_SOURCES = {
 }
 
 
+def code_tokens(text):
+    """C++ source without comments and with whitespace runs collapsed: edits
+    to comments or layout leave a recorded measurement valid."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash(path="direct"):
-    """Hash of the sources the measured kernels are built from: recorded HBM
-    traffic is reported only while it still matches."""
+    """Hash of the code the measured kernels are built from: recorded HBM
+    traffic and instruction counts are reported only while it still matches."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1908_02681_amd", "csrc")
     for f in KERNEL_SOURCES[path]:
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(d, f), encoding="utf-8") as fh:
+            h.update(code_tokens(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -132,8 +132,9 @@ typedef struct rz_hq_params {
     /* eps = eps_num / eps_den (section 2.2 uses 1/100).  A fragment of depth
        q joins pixel p iff eps_den * (q - qmin) <= eps_num * (qmin + z0),
        qmin = nearest depth of p, z0 = floor(o * s) (so that q + z0 is
-       proportional to d); for RZ_DEPTH_PIECEWISE see there.  1 <= eps_den <= 2^20, eps_num <= 2^20, and
-       eps_num * (2^40 + z0) < 2^63 (else RZ_EDEPTHRANGE). */
+       proportional to d); for RZ_DEPTH_PIECEWISE see there.
+       1 <= eps_den <= 2^20, eps_num <= 2^20, and eps_num * (2^40 + z0) <
+       2^63 (else RZ_EDEPTHRANGE). */
     uint32_t eps_num;
     uint32_t eps_den;
 } rz_hq_params;

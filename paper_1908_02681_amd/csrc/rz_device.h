@@ -1,6 +1,8 @@
 // Device-side building blocks of the point rasterizer for gfx950 (MI355X),
-// shared by the single-view kernels (rz_kernels.hip) and the multi-view
-// batch kernels (rz_batch.hip).
+// shared by the one-view kernels (rz_kernels.hip), the multi-view batch
+// kernels (rz_batch.hip), the general point-size and float-depth kernels
+// (rz_general.hip), the screen-sorted path (rz_sorted.hip) and the
+// reciprocal self-check (rz_check.hip).
 //
 // Method: Schuetz & Wimmer, "Rendering Point Clouds with Compute Shaders"
 // (arXiv 1908.02681), section 2.1 (atomicMin rasterization, resolve/clear)
@@ -161,10 +163,11 @@ __device__ __forceinline__ float recip_rn(float w)
 }
 
 // Translation column of the float matrix (clip x, y, w) and of the depth
-// row in double, the addend of the first fused step of each row.  lane_trans() returns it as per-lane
-// values (an identity DPP move), made once per chunk: a fused multiply-add
-// can take only one scalar-register operand on gfx950, so with the scalar
-// copies every row of every point would need a move first.
+// row in double, the addend of the first fused step of each row.
+// lane_trans() returns it as per-lane values (identity DPP moves), made once
+// per chunk: a fused multiply-add can take only one scalar-register operand
+// on gfx950, so with the scalar copies every row of every point would need
+// a move first.
 struct Trans {
     float tx, ty, tw;
     double td;   // the depth row's translation (double precision)
@@ -196,9 +199,10 @@ __device__ __forceinline__ Trans scalar_trans(const Proj &P)
 
 // Pixel of one point (section 2.1's projection in single precision: each
 // clip coordinate a chain of fused multiply-adds from the translation
-// column through the x, y and z terms), its clip w and 1 / w (rounded once; x and y are scaled by it, as a
-// perspective divide does).  Returns false when the point is culled (w <= 0
-// or off screen).
+// column through the x, y and z terms), its clip w and 1 / w (rounded once;
+// x and y are scaled by it, as a perspective divide does, and the viewport
+// maps them with one fused scale and offset).  Returns false when the point
+// is culled (w <= 0 or off screen).
 // Straight-line code: the pixel of a culled point is 0, never a conversion
 // of an out-of-range float.
 __device__ __forceinline__ bool project(const Proj &P, const Trans &T, float x, float y, float z,
@@ -613,8 +617,10 @@ __device__ __forceinline__ Box wave_box(const uint32_t (&px)[PPT], const uint32_
     uint32_t lx = 0xFFFFFFFFu, ly = 0xFFFFFFFFu, hx = 0u, hy = 0u;
 #pragma unroll
     for (int j = 0; j < PPT; j += 2) {   // pairs: three-operand min and max
-        const uint32_t a0 = live[j] ? px[j] : 0xFFFFFFFFu, a1 = live[j + 1] ? px[j + 1] : 0xFFFFFFFFu;
-        const uint32_t b0 = live[j] ? py[j] : 0xFFFFFFFFu, b1 = live[j + 1] ? py[j + 1] : 0xFFFFFFFFu;
+        const uint32_t a0 = live[j] ? px[j] : 0xFFFFFFFFu,
+                       a1 = live[j + 1] ? px[j + 1] : 0xFFFFFFFFu;
+        const uint32_t b0 = live[j] ? py[j] : 0xFFFFFFFFu,
+                       b1 = live[j + 1] ? py[j + 1] : 0xFFFFFFFFu;
         const uint32_t c0 = live[j] ? px[j] : 0u, c1 = live[j + 1] ? px[j + 1] : 0u;
         const uint32_t d0 = live[j] ? py[j] : 0u, d1 = live[j + 1] ? py[j + 1] : 0u;
         lx = min(lx, min(a0, a1));
