@@ -311,6 +311,68 @@ def test_extreme_clip_w(rz, oracle, lo, hi):
     assert np.array_equal(got, want)
 
 
+def test_largest_screen(rz, oracle):
+    """The largest screen the interface accepts, 32768 x 32768 (8 GiB of
+    keys): a 300k-point cloud spread over it.  Every touched pixel holds the
+    minimum key of its fragments (from the oracle's per-point fragments) and
+    shows its colour after the resolve; no other pixel is written, and the
+    resolve leaves the whole framebuffer cleared."""
+    import torch
+    rng = np.random.default_rng(31)
+    n, side, bg = 300_000, 32768, 0x0A0B0C
+    view = gen.make_view((0.0, 0.0, 5.0), (0.0, 0.0, 0.0), (0, 1, 0), 60.0, side, side, 0.1, 100.0)
+    x = rng.uniform(-3.2, 3.2, n).astype(np.float32)
+    y = rng.uniform(-3.2, 3.2, n).astype(np.float32)
+    z = rng.uniform(-1.0, 1.0, n).astype(np.float32)
+    z[: n // 3] = z[n // 3: 2 * (n // 3)]               # repeated depths for the colour tie rule
+    x[: n // 3] = x[n // 3: 2 * (n // 3)]
+    y[: n // 3] = y[n // 3: 2 * (n // 3)]
+    rgb = rng.integers(0, 1 << 24, n, dtype=np.uint32)
+    pix, q = oracle.fragments(x, y, z, view.vp, view.near, view.far, side, side)
+    keep = pix >= 0
+    assert keep.mean() > 0.5 and (pix[keep] >= side * side // 2).any()
+    keys = (q[keep] << np.uint64(24)) | (rgb[keep].astype(np.uint64) & np.uint64(0xFFFFFF))
+    order = np.lexsort((keys, pix[keep]))
+    p_sorted, k_sorted = pix[keep][order], keys[order]
+    first = np.r_[True, p_sorted[1:] != p_sorted[:-1]]
+    want_pix, want_key = p_sorted[first], k_sorted[first]
+    say(f"[parity] {side}x{side}: {len(want_pix)} touched pixels")
+    pts = rz.Points.from_cloud(gen.Cloud(x, y, z, rgb))
+    fb, _ = rz.new_framebuffer(view, bg)
+    rz.rasterize_atomicmin(pts, view, background=bg, fb=fb, keep_keys=True)
+    idx = torch.from_numpy(want_pix).cuda()
+    got = fb[idx].cpu().numpy().view(np.uint64)
+    clear = int(np.uint64(oracle.clear_value(bg)).view(np.int64))
+    written = int((fb != clear).sum().item())
+    img = rz.resolve_min(fb, side * side, bg)
+    colours = img[idx].cpu().numpy().view(np.uint32)
+    still = int((fb != clear).sum().item())
+    torch.cuda.synchronize()
+    assert np.array_equal(got, want_key)
+    assert written == len(want_pix)
+    assert np.array_equal(colours, (want_key & np.uint64(0xFFFFFF)).astype(np.uint32))
+    assert still == 0
+    del fb, img
+    torch.cuda.empty_cache()
+
+
+def test_large_screen_splatting(rz, oracle):
+    """8192 x 8192 (64M pixels), both methods against the oracle at every
+    pixel, with a dense cluster so that pixels average several fragments."""
+    rng = np.random.default_rng(32)
+    n, side = 1_000_000, 8192
+    view = gen.make_view((0.0, 0.0, 5.0), (0.0, 0.0, 0.0), (0, 1, 0), 60.0, side, side, 0.1, 100.0)
+    x = rng.uniform(-3.2, 3.2, n).astype(np.float32)
+    y = rng.uniform(-3.2, 3.2, n).astype(np.float32)
+    z = rng.uniform(-1.0, 1.0, n).astype(np.float32)
+    x[: n // 2] = rng.normal(0, 0.01, n // 2).astype(np.float32)
+    y[: n // 2] = rng.normal(0, 0.01, n // 2).astype(np.float32)
+    rgb = rng.integers(0, 1 << 24, n, dtype=np.uint32)
+    _, sums = check_scene(rz, oracle, gen.Cloud(x, y, z, rgb), view, bg=0x203040,
+                          label="8192x8192")
+    assert (sums[:, 3] > 1).sum() > 1000
+
+
 def test_config2_terrain_full_size(rz, oracle):
     """The 50M-point Morton terrain at 1920x1080, every pixel, both modes."""
     cloud, view = gen.config2()
