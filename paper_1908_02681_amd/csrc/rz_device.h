@@ -250,22 +250,35 @@ __device__ __forceinline__ double depth_of(const Proj &P, float x, float y, floa
 // only (P.nr == 0), so the piecewise tables are never read; PW = true serves
 // every integer map.  Straight-line code apart from one wave-uniform skip
 // of the depth when no lane of the wave is on screen.
+// tq: q as a double for the linear and scale maps (meaningless for the
+// piecewise map).
 template <bool PW>
 __device__ __forceinline__ bool fragment(const Proj &P, const Trans &T, float x, float y, float z,
-                                         uint32_t &px, uint32_t &py, uint64_t &q)
+                                         uint32_t &px, uint32_t &py, uint64_t &q, double &tq)
 {
     float cw, iw;
     const bool vis = project(P, T, x, y, z, px, py, cw, iw);
     q = 0;
+    tq = 0.0;
     if (!wave_any(vis))
         return false;
     const double d = depth_of(P, T, x, y, z);
     const bool in_range = d >= P.near_ && d < P.far_;
-    if (!PW || P.nr == 0)
-        q = to_u64(fmin(floor((d - P.o) * P.s), kQMax));   // d < near gives garbage, unused
-    else
+    if (!PW || P.nr == 0) {
+        tq = fmin(floor((d - P.o) * P.s), kQMax);   // d < near gives garbage, unused
+        q = to_u64(tq);
+    } else {
         q = piecewise_q(P, in_range ? d : P.near_);
+    }
     return vis && in_range;
+}
+
+template <bool PW>
+__device__ __forceinline__ bool fragment(const Proj &P, const Trans &T, float x, float y, float z,
+                                         uint32_t &px, uint32_t &py, uint64_t &q)
+{
+    double tq;
+    return fragment<PW>(P, T, x, y, z, px, py, q, tq);
 }
 
 template <bool PW>
@@ -852,26 +865,56 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
 {
     uint32_t px[PPT], py[PPT], pix[PPT];
     uint64_t q[PPT];
+    double tq[PPT];
     bool ok[PPT];
     const Trans T = lane_trans(P);
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         uint32_t a = 0, b = 0;
         uint64_t qq = 0;
-        ok[j] = fragment<PW>(P, T, x[j], y[j], z[j], a, b, qq) & in[j];
+        double t = 0.0;
+        ok[j] = fragment<PW>(P, T, x[j], y[j], z[j], a, b, qq, t) & in[j];
         px[j] = a;
         py[j] = b;
         pix[j] = __umul24(b, (uint32_t)P.width) + a;   // both below 2^15
         q[j] = qq;
+        tq[j] = t;
     }
     uint64_t fbv[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j)
         fbv[j] = fb[ok[j] ? pix[j] : 0u];
+    if (PW && P.nr != 0) {
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        const uint64_t qmin = fbv[j] >> 24;
-        ok[j] = in_window_live<PW>(P, eps_num, eps_den, q[j], qmin, ok[j]);
+        for (int j = 0; j < PPT; ++j)
+            ok[j] = ok[j] && in_window<PW>(P, eps_num, eps_den, q[j], fbv[j] >> 24);
+    } else if (!P.wfp) {   // linear or scale map, z0 >= 2^52: integer test only
+#pragma unroll
+        for (int j = 0; j < PPT; ++j)
+            ok[j] = ok[j] && in_window<false>(P, eps_num, eps_den, to_u64(tq[j]), fbv[j] >> 24);
+    } else {
+        // the double-precision pre-test of in_window_live(), with q as the
+        // double the fragment floored, and one integer fallback per chunk
+        bool edge[PPT];
+        bool any_edge = false;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const double dm = int52_to_double(fbv[j] >> 24);
+            const double lhs = (double)eps_den * (tq[j] - dm);
+            const double rhs = (double)eps_num * (dm + P.z0d);
+            edge[j] = ok[j] & (lhs == rhs);
+            ok[j] = ok[j] & (lhs < rhs);
+            any_edge = any_edge | edge[j];
+        }
+        if (wave_any(any_edge)) {   // reads the pixels again: rare
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+                const uint64_t qmin = fb[edge[j] ? pix[j] : 0u] >> 24;
+                const bool ex = (uint64_t)eps_den * (to_u64(tq[j]) - qmin) <=
+                                (uint64_t)eps_num * (qmin + P.z0);
+                ok[j] = edge[j] ? ex : ok[j];
+            }
+        }
     }
     uint64_t w0[PPT], w1[PPT];
 #pragma unroll
