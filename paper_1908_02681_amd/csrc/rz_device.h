@@ -645,6 +645,33 @@ __device__ __forceinline__ Box wave_box(const uint32_t (&px)[PPT], const uint32_
     return Box{wave_min(lx), wave_min(ly), ~wave_min(~hx), ~wave_min(~hy)};
 }
 
+// wave_box() for the wave kernels, one select fewer per coordinate: a point
+// that is off screen has pixel 0 (project()), which cannot raise a maximum,
+// so the maxima are taken over all points; the minima only over the live
+// ones.  Points on screen but outside [near, far) may widen the rectangle,
+// which then still bounds every live fragment.
+template <int PPT>
+__device__ __forceinline__ Box wave_box_live_min(const uint32_t (&px)[PPT],
+                                                 const uint32_t (&py)[PPT],
+                                                 const bool (&live)[PPT])
+{
+    static_assert(PPT % 2 == 0, "points are taken in pairs");
+    uint32_t lx = 0xFFFFFFFFu, ly = 0xFFFFFFFFu, hx = 0u, hy = 0u;
+#pragma unroll
+    for (int j = 0; j < PPT; j += 2) {   // pairs: three-operand min and max
+        const uint32_t a0 = live[j] ? px[j] : 0xFFFFFFFFu,
+                       a1 = live[j + 1] ? px[j + 1] : 0xFFFFFFFFu;
+        const uint32_t b0 = live[j] ? py[j] : 0xFFFFFFFFu,
+                       b1 = live[j + 1] ? py[j + 1] : 0xFFFFFFFFu;
+        lx = min(lx, min(a0, a1));
+        ly = min(ly, min(b0, b1));
+        hx = max(hx, max(px[j], px[j + 1]));
+        hy = max(hy, max(py[j], py[j + 1]));
+    }
+    // no live lane: lx = ~0 > hx, an empty box
+    return Box{wave_min(lx), wave_min(ly), ~wave_min(~hx), ~wave_min(~hy)};
+}
+
 // Depth pass over one chunk with a private LDS tile per wave: like
 // raster_chunk with BIN, but every wave gathers its own 64 * PPT fragments
 // in its own 8 KiB slice (w_tile) and flushes it, so no workgroup barrier
@@ -666,10 +693,9 @@ __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__res
         live[j] = fragment<PW>(P, T, x[j], y[j], z[j], a, b, q) & in[j];
         px[j] = a;
         py[j] = b;
-        pix[j] = __umul24(b, (uint32_t)P.width) + a;   // both below 2^15
         key[j] = (q << 24) | ((uint64_t)c[j] & kRgbMask);
     }
-    const Box box = wave_box<PPT>(px, py, live);
+    const Box box = wave_box_live_min<PPT>(px, py, live);
     const uint32_t lane = threadIdx.x & 63u;
     bool tiled = false;
     uint32_t bw = 0, bh = 0;
@@ -713,6 +739,9 @@ __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__res
     // runs of one pixel are merged in registers (LDS atomics need no such
     // help), then each remaining fragment takes an early-out read and a
     // global atomic
+#pragma unroll
+    for (int j = 0; j < PPT; ++j)
+        pix[j] = __umul24(py[j], (uint32_t)P.width) + px[j];   // both below 2^15
 #pragma unroll
     for (int j = 1; j < PPT; ++j) {
         const bool same = live[j] && live[j - 1] && pix[j] == pix[j - 1];
@@ -924,15 +953,19 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
     }
     // runs of one pixel summed in registers: unlike the depth pass's LDS
     // minimum, the tile's two 64-bit LDS adds per fragment are slower than
-    // this merge on runs of Morton-ordered points
+    // this merge on runs of Morton-ordered points.  Only within each group
+    // of four consecutive points: the next group lies 4 * blockDim points
+    // further on.
 #pragma unroll
     for (int j = 1; j < PPT; ++j) {
+        if (j % 4 == 0)
+            continue;
         const bool same = ok[j] && ok[j - 1] && pix[j] == pix[j - 1];
         w0[j] += same ? w0[j - 1] : 0ull;
         w1[j] += same ? w1[j - 1] : 0ull;
         ok[j - 1] = ok[j - 1] && !same;
     }
-    const Box box = wave_box<PPT>(px, py, ok);
+    const Box box = wave_box_live_min<PPT>(px, py, ok);
     const uint32_t lane = threadIdx.x & 63u;
     bool tiled = false;
     uint32_t bw = 0, bh = 0;
