@@ -189,8 +189,7 @@ int rasterize_atomicmin(const rz_points *pts, const rz_view *view, const rz_dept
         return RZ_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const Pts p{pts->x, pts->y, pts->z, pts->rgb, pts->n};
-    hipError_t e = P.zkind ? launch_raster_points(p, P, 1, fb, s)
-                           : launch_raster_min(p, P, fb, g_tune, s);
+    hipError_t e = launch_raster_min(p, P, fb, g_tune, s);   // every encoding
     if (e != hipSuccess)
         return hip_fail(e);
     if (!(flags & RZ_KEEP_KEYS)) {
@@ -264,7 +263,9 @@ int rasterize_points(const rz_points *pts, const rz_view *view, const rz_depth_m
         return RZ_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const Pts p{pts->x, pts->y, pts->z, pts->rgb, pts->n};
-    const bool general = point_size > 1 || P.zkind != 0;
+    // one-pixel points of every encoding take the depth-pass kernels (float
+    // encodings are depth-only: check_hq rejects them with splatting)
+    const bool general = point_size > 1;
     hipError_t e = general ? launch_raster_points(p, P, point_size, fb, s)
                            : launch_raster_min(p, P, fb, g_tune, s);
     if (e == hipSuccess && hq)

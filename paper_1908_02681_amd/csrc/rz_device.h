@@ -319,6 +319,49 @@ __device__ __forceinline__ bool fragment_any(const Proj &P, float x, float y, fl
     return true;
 }
 
+// fragment_any() for one float encoding, straight-line like fragment(): the
+// same arithmetic, with selects in place of the early returns, and the
+// 24-bit code converted only from a value inside the window.
+template <int ZK>
+__device__ __forceinline__ bool fragment_zk(const Proj &P, const Trans &T, float x, float y,
+                                            float z, uint32_t &px, uint32_t &py, uint64_t &q)
+{
+    static_assert(ZK == RZ_DEPTH_GL24 || ZK == RZ_DEPTH_F32REV, "float encodings only");
+    float cw, iw;
+    const bool vis = project(P, T, x, y, z, px, py, cw, iw);
+    q = 0;
+    if (!wave_any(vis))
+        return false;
+    const double d = depth_of(P, T, x, y, z);
+    const bool in_range = (d >= P.near_) & (d < P.far_);
+    if (ZK == RZ_DEPTH_F32REV) {
+        const float zr = P.nearf / cw;
+        q = 0xFFFFFFFFull - (uint64_t)__float_as_uint(zr);
+        return vis & in_range;
+    }
+    float cz = __builtin_fmaf(P.mz[0], x, P.mz[3]);
+    cz = __builtin_fmaf(P.mz[1], y, cz);
+    cz = __builtin_fmaf(P.mz[2], z, cz);
+    const float nz = cz * iw;
+    const bool clip = (nz >= -1.0f) & (nz <= 1.0f);
+    const float zw = (nz + 1.0f) * 0.5f;
+    const float t = zw * 16777215.0f;
+    q = (uint64_t)(uint32_t)floor((double)(clip ? t : 0.0f) + 0.5);
+    return vis & in_range & clip;
+}
+
+// The fragment of the kernels templated on the depth encoding: ZK = 0 for
+// the integer maps, else RZ_DEPTH_GL24 or RZ_DEPTH_F32REV.
+template <bool PW, int ZK>
+__device__ __forceinline__ bool fragment_enc(const Proj &P, const Trans &T, float x, float y,
+                                             float z, uint32_t &px, uint32_t &py, uint64_t &q)
+{
+    if constexpr (ZK == 0)
+        return fragment<PW>(P, T, x, y, z, px, py, q);
+    else
+        return fragment_zk<ZK>(P, T, x, y, z, px, py, q);
+}
+
 // Workgroup -> chunk of points.  Workgroups are dealt round-robin to the 8
 // XCDs; with the remap, XCD k works through the k-th eighth of the chunks,
 // so spatially coherent (e.g. Morton-ordered) ranges share one L2.
@@ -676,7 +719,7 @@ __device__ __forceinline__ Box wave_box_live_min(const uint32_t (&px)[PPT],
 // raster_chunk with BIN, but every wave gathers its own 64 * PPT fragments
 // in its own 8 KiB slice (w_tile) and flushes it, so no workgroup barrier
 // is needed.  Same result bits as raster_chunk.
-template <int PPT, bool PW>
+template <int PPT, bool PW, int ZK = 0>
 __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__restrict__ fb,
                                                   const float (&x)[PPT], const float (&y)[PPT],
                                                   const float (&z)[PPT], const uint32_t (&c)[PPT],
@@ -690,7 +733,7 @@ __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__res
     for (int j = 0; j < PPT; ++j) {
         uint64_t q = 0;
         uint32_t a = 0, b = 0;
-        live[j] = fragment<PW>(P, T, x[j], y[j], z[j], a, b, q) & in[j];
+        live[j] = fragment_enc<PW, ZK>(P, T, x[j], y[j], z[j], a, b, q) & in[j];
         px[j] = a;
         py[j] = b;
         key[j] = (q << 24) | ((uint64_t)c[j] & kRgbMask);

@@ -45,6 +45,28 @@ __global__ void __launch_bounds__(512) k_raster_min(Pts p, Proj P, uint64_t *__r
         raster_chunk<PPT, EARLY, BIN == kBinBlock, PW>(P, fb, x, y, z, c, in, s_tile, s_box);
 }
 
+// Depth pass for the float depth encodings (RZ_DEPTH_GL24, RZ_DEPTH_F32REV)
+// at one pixel per point: the per-wave tile kernel with the encoding's key.
+template <bool VEC, int ZK>
+__global__ void __launch_bounds__(512) k_raster_min_zk(Pts p, Proj P, uint64_t *__restrict__ fb,
+                                                       int64_t nchunks)
+{
+    constexpr int PPT = 16;
+    extern __shared__ uint64_t s_waves[];
+    const int64_t chunk = blockIdx.x;
+    if (chunk >= nchunks)
+        return;
+    float x[PPT], y[PPT], z[PPT];
+    uint32_t c[PPT];
+    bool in[PPT];
+    load_points_nan<PPT, VEC>(p, chunk * (int64_t)blockDim.x * PPT, x, y, z, c);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j)
+        in[j] = true;
+    raster_chunk_wave<PPT, false, ZK>(P, fb, x, y, z, c, in,
+                                      s_waves + (threadIdx.x >> 6) * kWaveTileWords);
+}
+
 // Accumulation pass of section 2.2 for one view.
 template <int PPT, bool VEC, bool XCD, int BIN, bool PW>
 __global__ void __launch_bounds__(512) k_hq_accum(Pts p, Proj P, uint32_t eps_num,
@@ -248,6 +270,20 @@ hipError_t hq_accum_dispatch(const Pts &p, const Proj &P, uint32_t num, uint32_t
                              : hq_accum_vec<PPT, false>(p, P, num, den, fb, acc, t, s);
 }
 
+template <int ZK>
+hipError_t raster_min_zk(const Pts &p, const Proj &P, uint64_t *fb, const Tune &t, hipStream_t s)
+{
+    const int64_t nchunks = blocks_for(p.n, (int64_t)t.block * 16);
+    const size_t lds = wave_lds(kBinWave, t.block);
+    if (planes_aligned(p))
+        hipLaunchKernelGGL((k_raster_min_zk<true, ZK>), dim3((uint32_t)nchunks), dim3(t.block),
+                           lds, s, p, P, fb, nchunks);
+    else
+        hipLaunchKernelGGL((k_raster_min_zk<false, ZK>), dim3((uint32_t)nchunks), dim3(t.block),
+                           lds, s, p, P, fb, nchunks);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_raster_min(const Pts &p, const Proj &P, uint64_t *fb, const Tune &t,
@@ -255,6 +291,14 @@ hipError_t launch_raster_min(const Pts &p, const Proj &P, uint64_t *fb, const Tu
 {
     if (p.n == 0)
         return hipSuccess;
+    if (P.zkind != 0) {
+        // float depth encodings: the per-wave tile kernel at the default
+        // shape, the general point kernel for every other launch shape
+        if (t.bin != kBinWave || t.ppt != 16 || t.xcd_remap)
+            return launch_raster_points(p, P, 1, fb, s);
+        return P.zkind == RZ_DEPTH_GL24 ? raster_min_zk<RZ_DEPTH_GL24>(p, P, fb, t, s)
+                                        : raster_min_zk<RZ_DEPTH_F32REV>(p, P, fb, t, s);
+    }
     switch (t.ppt) {
     case 4: return raster_min_dispatch<4>(p, P, fb, t, s);
     case 8: return raster_min_dispatch<8>(p, P, fb, t, s);

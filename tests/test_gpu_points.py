@@ -105,6 +105,27 @@ def test_atomicmin_call_takes_float_encodings(rz, oracle):
         assert np.array_equal(rz.to_u32(img), want)
 
 
+def test_float_depth_every_launch_shape(rz, oracle):
+    """One-pixel float encodings take the depth pass's tile kernel at the
+    default launch shape and the general point kernel at any other; both
+    give the oracle's keys."""
+    import torch
+    cloud, view = gen.config1(n=150_000)
+    pts = rz.Points.from_cloud(cloud)
+    try:
+        for shape in ((64, 16, 1, 0, 2), (256, 8, 1, 0, 2), (64, 16, 1, 0, 1), (128, 16, 1, 1, 2)):
+            rz.set_launch(*shape)
+            for kind in (GL24, F32REV):
+                fb, _ = rz.new_framebuffer(view, 0)
+                rz.rasterize_atomicmin(pts, view, (kind, 0.0), fb=fb, keep_keys=True)
+                torch.cuda.synchronize()
+                want = oracle.raster_min(cloud.x, cloud.y, cloud.z, cloud.rgb, view.vp, view.near,
+                                         view.far, view.width, view.height, kind)
+                assert np.array_equal(rz.to_u64(fb), want), (shape, kind)
+    finally:
+        rz.reset_launch()
+
+
 def test_one_millimetre_at_one_kilometre(rz, oracle):
     """The precision case of the oracle pins on the GPU: the 40-bit map and
     the reversed float depth show the nearer surface everywhere, the 24-bit
