@@ -23,6 +23,9 @@ using namespace dev;
 constexpr int kGenBlock = 256;
 constexpr int kGenPpt = 4;   // one 16-byte group of points per thread
 constexpr size_t kLds = (kGenBlock / 64) * kWaveTileWords * sizeof(uint64_t);
+// splat pass: per wave, the sums tile and the nearest depths of its pixels
+constexpr uint32_t kWaveWordsHq = kWaveTileWords + kWaveTileHq;
+constexpr size_t kLdsHq = (kGenBlock / 64) * kWaveWordsHq * sizeof(uint64_t);
 
 // Covered pixels [lo, hi) along one axis for a point of size k at pixel c.
 __device__ __forceinline__ void cover(uint32_t c, int32_t k, int32_t size, int32_t &lo,
@@ -82,6 +85,15 @@ __global__ void __launch_bounds__(kGenBlock) k_raster_points(Pts p, Proj P, int3
         px[j] = a;
         py[j] = b;
         key[j] = (q << 24) | ((uint64_t)c[j] & kRgbMask);
+    }
+    // consecutive points of a thread with one centre pixel cover the same
+    // square: keep only their smaller key (k^2 atomics saved per merge)
+#pragma unroll
+    for (int j = 1; j < kGenPpt; ++j) {
+        const bool same = live[j] && live[j - 1] && px[j] == px[j - 1] && py[j] == py[j - 1];
+        const uint64_t lo = key[j] < key[j - 1] ? key[j] : key[j - 1];
+        key[j] = same ? lo : key[j];
+        live[j - 1] = live[j - 1] && !same;
     }
     const Cover cv = wave_cover(wave_box<kGenPpt>(px, py, live), k, P.width, P.height,
                                 kWaveTileMin);
@@ -149,7 +161,8 @@ __global__ void __launch_bounds__(kGenBlock) k_hq_points(Pts p, Proj P, int32_t 
                                                          uint64_t *__restrict__ acc)
 {
     extern __shared__ uint64_t s_waves[];
-    uint64_t *w_tile = s_waves + (threadIdx.x >> 6) * kWaveTileWords;
+    uint64_t *w_tile = s_waves + (threadIdx.x >> 6) * kWaveWordsHq;   // sums
+    uint64_t *w_qmin = w_tile + kWaveTileWords;                      // nearest depths
     const int64_t base = (int64_t)blockIdx.x * kGenBlock * kGenPpt;
     float x[kGenPpt], y[kGenPpt], z[kGenPpt];
     uint32_t c[kGenPpt];
@@ -171,11 +184,59 @@ __global__ void __launch_bounds__(kGenBlock) k_hq_points(Pts p, Proj P, int32_t 
                                 kWaveTileHq);
     const uint32_t lane = threadIdx.x & 63u;
     if (cv.tiled) {
+        // the nearest depth of every pixel of the rectangle, read once with
+        // coalesced row loads, then looked up in LDS per covered pixel
         const uint32_t area = cv.bw * cv.bh;
-        for (uint32_t i = lane; i < 2 * area; i += 64)
-            w_tile[i] = 0ull;
+        const float inv_bw = 1.0f / (float)cv.bw;
+        for (uint32_t i = lane; i < area; i += 64) {
+            uint32_t r, col;
+            tile_rc(i, cv.bw, inv_bw, r, col);
+            w_qmin[i] = fb[__umul24((uint32_t)cv.y0 + r, (uint32_t)P.width) + cv.x0 + col] >> 24;
+            w_tile[2 * i] = 0ull;
+            w_tile[2 * i + 1] = 0ull;
+        }
         wave_sync();
+#pragma unroll
+        for (int j = 0; j < kGenPpt; ++j) {
+            if (!live[j])
+                continue;
+            const uint32_t col = c[j];
+            const uint64_t w0 = (uint64_t)(col & 0xFFu) | ((uint64_t)((col >> 8) & 0xFFu) << 32);
+            const uint64_t w1 = (uint64_t)((col >> 16) & 0xFFu) | (1ull << 32);
+            int32_t x0, x1, y0, y1;
+            cover(px[j], k, P.width, x0, x1);
+            cover(py[j], k, P.height, y0, y1);
+            for (int32_t yy = y0; yy < y1; ++yy) {
+                const uint32_t row = __umul24((uint32_t)(yy - cv.y0), cv.bw) - (uint32_t)cv.x0;
+                for (int32_t xx = x0; xx < x1; ++xx) {
+                    const uint32_t t = row + (uint32_t)xx;
+                    if (!in_window_live<PW>(P, eps_num, eps_den, q[j], w_qmin[t], true))
+                        continue;
+                    __hip_atomic_fetch_add(&w_tile[2 * t], w0, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_fetch_add(&w_tile[2 * t + 1], w1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
+        }
+        wave_sync();
+        for (uint32_t i = lane; i < area; i += 64) {
+            const uint64_t a1 = w_tile[2 * i + 1];
+            if (a1 != 0ull) {
+                uint32_t r, col;
+                tile_rc(i, cv.bw, inv_bw, r, col);
+                uint64_t *dst =
+                    acc + 2 * (uint64_t)(__umul24((uint32_t)cv.y0 + r, (uint32_t)P.width) +
+                                         cv.x0 + col);
+                __hip_atomic_fetch_add(dst, w_tile[2 * i], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(dst + 1, a1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        wave_sync();
+        return;
     }
+    // the squares spread too far for the tile: global reads and atomics
 #pragma unroll
     for (int j = 0; j < kGenPpt; ++j) {
         if (!live[j])
@@ -188,40 +249,15 @@ __global__ void __launch_bounds__(kGenBlock) k_hq_points(Pts p, Proj P, int32_t 
         cover(py[j], k, P.height, y0, y1);
         for (int32_t yy = y0; yy < y1; ++yy) {
             for (int32_t xx = x0; xx < x1; ++xx) {
-                const int64_t pp = (int64_t)yy * P.width + xx;
+                const uint64_t pp = __umul24((uint32_t)yy, (uint32_t)P.width) + (uint32_t)xx;
                 if (!in_window<PW>(P, eps_num, eps_den, q[j], fb[pp] >> 24))
                     continue;
-                uint64_t *t = cv.tiled ? &w_tile[2 * ((uint32_t)(yy - cv.y0) * cv.bw +
-                                                      (uint32_t)(xx - cv.x0))]
-                                       : acc + 2 * pp;
-                if (cv.tiled) {
-                    __hip_atomic_fetch_add(t, w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    __hip_atomic_fetch_add(t + 1, w1, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                } else {
-                    __hip_atomic_fetch_add(t, w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_fetch_add(t + 1, w1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-            }
-        }
-    }
-    if (cv.tiled) {
-        wave_sync();
-        const uint32_t area = cv.bw * cv.bh;
-        const float inv_bw = 1.0f / (float)cv.bw;
-        for (uint32_t i = lane; i < area; i += 64) {
-            const uint64_t a1 = w_tile[2 * i + 1];
-            if (a1 != 0ull) {
-                uint32_t r, col;
-                tile_rc(i, cv.bw, inv_bw, r, col);
-                uint64_t *dst =
-                    acc + 2 * ((int64_t)(cv.y0 + (int32_t)r) * P.width + cv.x0 + col);
-                __hip_atomic_fetch_add(dst, w_tile[2 * i], __ATOMIC_RELAXED,
+                __hip_atomic_fetch_add(acc + 2 * pp, w0, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_add(dst + 1, a1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(acc + 2 * pp + 1, w1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        wave_sync();
     }
 }
 
@@ -253,16 +289,16 @@ hipError_t launch_hq_points(const Pts &p, const Proj &P, int32_t k, uint32_t eps
     const dim3 grid((uint32_t)((p.n + kGenBlock * kGenPpt - 1) / (kGenBlock * kGenPpt)));
     const bool v = aligned16(p), pw = P.nr != 0;
     if (v && pw)
-        hipLaunchKernelGGL((k_hq_points<true, true>), grid, dim3(kGenBlock), kLds, s, p, P, k,
+        hipLaunchKernelGGL((k_hq_points<true, true>), grid, dim3(kGenBlock), kLdsHq, s, p, P, k,
                            eps_num, eps_den, fb, acc);
     else if (v)
-        hipLaunchKernelGGL((k_hq_points<true, false>), grid, dim3(kGenBlock), kLds, s, p, P, k,
+        hipLaunchKernelGGL((k_hq_points<true, false>), grid, dim3(kGenBlock), kLdsHq, s, p, P, k,
                            eps_num, eps_den, fb, acc);
     else if (pw)
-        hipLaunchKernelGGL((k_hq_points<false, true>), grid, dim3(kGenBlock), kLds, s, p, P, k,
+        hipLaunchKernelGGL((k_hq_points<false, true>), grid, dim3(kGenBlock), kLdsHq, s, p, P, k,
                            eps_num, eps_den, fb, acc);
     else
-        hipLaunchKernelGGL((k_hq_points<false, false>), grid, dim3(kGenBlock), kLds, s, p, P, k,
+        hipLaunchKernelGGL((k_hq_points<false, false>), grid, dim3(kGenBlock), kLdsHq, s, p, P, k,
                            eps_num, eps_den, fb, acc);
     return hipGetLastError();
 }
