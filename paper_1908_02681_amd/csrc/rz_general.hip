@@ -23,9 +23,14 @@ using namespace dev;
 constexpr int kGenBlock = 256;
 constexpr int kGenPpt = 4;   // one 16-byte group of points per thread
 constexpr size_t kLds = (kGenBlock / 64) * kWaveTileWords * sizeof(uint64_t);
-// splat pass: per wave, the sums tile and the nearest depths of its pixels
-constexpr uint32_t kWaveWordsHq = kWaveTileWords + kWaveTileHq;
-constexpr size_t kLdsHq = (kGenBlock / 64) * kWaveWordsHq * sizeof(uint64_t);
+// Splat pass: per wave, one packed sum word and the nearest depth of each
+// pixel of its tile.  A wave holds 64 * kGenPpt = 256 points, and a point
+// adds to a pixel at most once, so a pixel's count stays <= 256 and its
+// channel sums <= 255 * 256 < 2^17: R | G << 17 | B << 34 | count << 51
+// never carries between fields.
+constexpr uint64_t kOneR = 1ull, kOneG = 1ull << 17, kOneB = 1ull << 34, kOneC = 1ull << 51;
+static_assert(64 * kGenPpt * 255 < (1 << 17) && 64 * kGenPpt < (1 << 13), "packed sums");
+constexpr size_t kLdsHq = kLds;   // kWaveTileHq sum words + kWaveTileHq depths per wave
 
 // Covered pixels [lo, hi) along one axis for a point of size k at pixel c.
 __device__ __forceinline__ void cover(uint32_t c, int32_t k, int32_t size, int32_t &lo,
@@ -161,8 +166,8 @@ __global__ void __launch_bounds__(kGenBlock) k_hq_points(Pts p, Proj P, int32_t 
                                                          uint64_t *__restrict__ acc)
 {
     extern __shared__ uint64_t s_waves[];
-    uint64_t *w_tile = s_waves + (threadIdx.x >> 6) * kWaveWordsHq;   // sums
-    uint64_t *w_qmin = w_tile + kWaveTileWords;                      // nearest depths
+    uint64_t *w_tile = s_waves + (threadIdx.x >> 6) * kWaveTileWords;   // packed sums
+    uint64_t *w_qmin = w_tile + kWaveTileHq;                           // nearest depths
     const int64_t base = (int64_t)blockIdx.x * kGenBlock * kGenPpt;
     float x[kGenPpt], y[kGenPpt], z[kGenPpt];
     uint32_t c[kGenPpt];
@@ -192,8 +197,7 @@ __global__ void __launch_bounds__(kGenBlock) k_hq_points(Pts p, Proj P, int32_t 
             uint32_t r, col;
             tile_rc(i, cv.bw, inv_bw, r, col);
             w_qmin[i] = fb[__umul24((uint32_t)cv.y0 + r, (uint32_t)P.width) + cv.x0 + col] >> 24;
-            w_tile[2 * i] = 0ull;
-            w_tile[2 * i + 1] = 0ull;
+            w_tile[i] = 0ull;
         }
         wave_sync();
 #pragma unroll
@@ -201,8 +205,8 @@ __global__ void __launch_bounds__(kGenBlock) k_hq_points(Pts p, Proj P, int32_t 
             if (!live[j])
                 continue;
             const uint32_t col = c[j];
-            const uint64_t w0 = (uint64_t)(col & 0xFFu) | ((uint64_t)((col >> 8) & 0xFFu) << 32);
-            const uint64_t w1 = (uint64_t)((col >> 16) & 0xFFu) | (1ull << 32);
+            const uint64_t w = (col & 0xFFu) * kOneR + ((col >> 8) & 0xFFu) * kOneG +
+                               ((col >> 16) & 0xFFu) * kOneB + kOneC;
             int32_t x0, x1, y0, y1;
             cover(px[j], k, P.width, x0, x1);
             cover(py[j], k, P.height, y0, y1);
@@ -212,24 +216,23 @@ __global__ void __launch_bounds__(kGenBlock) k_hq_points(Pts p, Proj P, int32_t 
                     const uint32_t t = row + (uint32_t)xx;
                     if (!in_window_live<PW>(P, eps_num, eps_den, q[j], w_qmin[t], true))
                         continue;
-                    __hip_atomic_fetch_add(&w_tile[2 * t], w0, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                    __hip_atomic_fetch_add(&w_tile[2 * t + 1], w1, __ATOMIC_RELAXED,
+                    __hip_atomic_fetch_add(&w_tile[t], w, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             }
         }
         wave_sync();
         for (uint32_t i = lane; i < area; i += 64) {
-            const uint64_t a1 = w_tile[2 * i + 1];
-            if (a1 != 0ull) {
+            const uint64_t sw = w_tile[i];
+            if (sw != 0ull) {   // unpack into the accumulator's two words
+                const uint64_t a0 = (sw & 0x1FFFFull) | (((sw >> 17) & 0x1FFFFull) << 32);
+                const uint64_t a1 = ((sw >> 34) & 0x1FFFFull) | ((sw >> 51) << 32);
                 uint32_t r, col;
                 tile_rc(i, cv.bw, inv_bw, r, col);
                 uint64_t *dst =
                     acc + 2 * (uint64_t)(__umul24((uint32_t)cv.y0 + r, (uint32_t)P.width) +
                                          cv.x0 + col);
-                __hip_atomic_fetch_add(dst, w_tile[2 * i], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(dst, a0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_fetch_add(dst + 1, a1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
