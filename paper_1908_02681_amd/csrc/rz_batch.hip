@@ -518,16 +518,21 @@ int rz_batch_autotune(rz_batch *b, void *stream, int32_t reps, rz_batch_opts *ch
     const bool had_graph = b->exec != nullptr;
     drop_graph(b);
     struct Cand {
-        int32_t k, block, ppt, bin;
+        int32_t k, block, ppt, bin, xcd;
     };
     std::vector<Cand> cands;
     const int32_t ks[] = {1, 2, 4, 8};
-    const int32_t shapes[][2] = {{256, 4}, {256, 8}, {512, 8}, {256, 16}};
-    for (int32_t bin : {2, 1})
-        for (int32_t k : ks)
-            for (auto &sh : shapes)
-                cands.push_back({k, sh[0], sh[1], bin});
-    cands.push_back({4, 256, 16, 0});
+    // the one-view defaults (64 x 16 for the depth pass, 128 x 8 for the
+    // splat pass) first, then wider workgroups
+    const int32_t shapes[][2] = {{64, 16}, {128, 8}, {256, 4}, {256, 8}, {512, 8}, {256, 16}};
+    for (int32_t k : ks)
+        for (auto &sh : shapes)
+            for (int32_t xcd : {0, 1})
+                cands.push_back({k, sh[0], sh[1], 2, xcd});
+    for (int32_t k : ks)
+        for (auto &sh : shapes)
+            cands.push_back({k, sh[0], sh[1], 1, 1});
+    cands.push_back({4, 256, 16, 0, 1});
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
@@ -546,7 +551,7 @@ int rz_batch_autotune(rz_batch *b, void *stream, int32_t reps, rz_batch_opts *ch
         b->tune.ppt = c.ppt;
         b->tune.bin = c.bin;
         b->tune.early_out = 1;
-        b->tune.xcd_remap = 1;
+        b->tune.xcd_remap = c.xcd;
         // correctness: one run, then the checksum of every image
         e = enqueue(b, s);
         if (e == hipSuccess)

@@ -7,7 +7,10 @@
 // gathers its fragments in a private 8 KiB LDS tile when the rectangle they
 // cover fits (it does for spatially ordered clouds), and flushes it with one
 // coalesced global atomic per touched pixel; otherwise every fragment takes
-// an early-out read and a global atomic.
+// an early-out read and a global atomic.  The depth pass first keeps only
+// the smallest key of a thread's consecutive points with one centre pixel;
+// the splat pass reads the rectangle's nearest depths into LDS once and
+// adds one packed sum word per accepted covered pixel.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
