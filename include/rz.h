@@ -377,7 +377,9 @@ int rz_batch_run(rz_batch *b, void *stream);
 /* Times the batch under candidate launch shapes and group sizes (reps runs
    each, median), keeps the fastest whose images hash to the same value as
    the first candidate's, and re-captures if the batch had a graph.  Runs
-   synchronously on `stream`.  chosen may be NULL. */
+   synchronously on `stream`.  chosen may be NULL.  Candidates include the
+   one-view calls' pair of shapes, one for the depth passes and another for
+   the accumulate passes; opts.launch then reports the depth passes' shape. */
 int rz_batch_autotune(rz_batch *b, void *stream, int32_t reps, rz_batch_opts *chosen,
                       float *best_ms);
 /* Current options of the batch. */

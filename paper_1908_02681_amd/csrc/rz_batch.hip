@@ -295,7 +295,8 @@ struct rz_batch {
     MvResolve *d_resolve = nullptr;       // all views
     unsigned long long *d_sum = nullptr;  // autotuner checksum
     rz_batch_opts opts;
-    Tune tune;
+    Tune tune;      // depth passes (opts.launch)
+    Tune tune_hq;   // accumulate passes: opts.launch, or the autotuner's pick
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -311,8 +312,8 @@ hipError_t enqueue(rz_batch *b, hipStream_t s)
         e = mv_launch(false, b->any_pw, b->pts, b->d_raster + g, std::min(K, b->nviews - g),
                       b->tune, s);
     for (int32_t g = 0; g < b->nhq && e == hipSuccess; g += K)
-        e = mv_launch(true, b->hq_pw, b->pts, b->d_accum + g, std::min(K, b->nhq - g), b->tune,
-                      s);
+        e = mv_launch(true, b->hq_pw, b->pts, b->d_accum + g, std::min(K, b->nhq - g),
+                      b->tune_hq, s);
     if (e == hipSuccess && b->resolve_blocks > 0) {
         hipLaunchKernelGGL(k_mv_resolve, dim3((uint32_t)b->resolve_blocks), dim3(256), 0, s,
                            b->d_resolve, b->nviews, b->opts.status);
@@ -447,6 +448,7 @@ int rz_batch_plan(const rz_points *pts, const rz_batch_view *views, int32_t nvie
     b->resolve_blocks = blocks;
     b->opts = o;
     b->tune = tune_of(o.launch);
+    b->tune_hq = b->tune;
     const size_t s1 = raster.size() * sizeof(MvView);
     const size_t s2 = accum.size() * sizeof(MvView);
     const size_t s3 = res.size() * sizeof(MvResolve);
@@ -518,21 +520,24 @@ int rz_batch_autotune(rz_batch *b, void *stream, int32_t reps, rz_batch_opts *ch
     const bool had_graph = b->exec != nullptr;
     drop_graph(b);
     struct Cand {
-        int32_t k, block, ppt, bin, xcd;
+        int32_t k, block, ppt, bin, xcd, hq_block, hq_ppt;   // hq_*: accumulate passes
     };
     std::vector<Cand> cands;
     const int32_t ks[] = {1, 2, 4, 8};
-    // the one-view defaults (64 x 16 for the depth pass, 128 x 8 for the
-    // splat pass) first, then wider workgroups
+    // the one-view defaults (64 x 16 for the depth passes with 128 x 8 for
+    // the accumulate passes) first, then one shape for both
+    for (int32_t k : ks)
+        for (int32_t xcd : {0, 1})
+            cands.push_back({k, 64, 16, 2, xcd, 128, 8});
     const int32_t shapes[][2] = {{64, 16}, {128, 8}, {256, 4}, {256, 8}, {512, 8}, {256, 16}};
     for (int32_t k : ks)
         for (auto &sh : shapes)
             for (int32_t xcd : {0, 1})
-                cands.push_back({k, sh[0], sh[1], 2, xcd});
+                cands.push_back({k, sh[0], sh[1], 2, xcd, sh[0], sh[1]});
     for (int32_t k : ks)
         for (auto &sh : shapes)
-            cands.push_back({k, sh[0], sh[1], 1, 1});
-    cands.push_back({4, 256, 16, 0, 1});
+            cands.push_back({k, sh[0], sh[1], 1, 1, sh[0], sh[1]});
+    cands.push_back({4, 256, 16, 0, 1, 256, 16});
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
@@ -542,7 +547,7 @@ int rz_batch_autotune(rz_batch *b, void *stream, int32_t reps, rz_batch_opts *ch
     bool have_ref = false;
     float best = 1e30f;
     rz_batch_opts best_opts = b->opts;
-    Tune best_tune = b->tune;
+    Tune best_tune = b->tune, best_tune_hq = b->tune_hq;
     const rz_batch_opts saved = b->opts;
     for (size_t ci = 0; ci < cands.size() && e == hipSuccess; ++ci) {
         const Cand &c = cands[ci];
@@ -552,6 +557,9 @@ int rz_batch_autotune(rz_batch *b, void *stream, int32_t reps, rz_batch_opts *ch
         b->tune.bin = c.bin;
         b->tune.early_out = 1;
         b->tune.xcd_remap = c.xcd;
+        b->tune_hq = b->tune;
+        b->tune_hq.block = c.hq_block;
+        b->tune_hq.ppt = c.hq_ppt;
         // correctness: one run, then the checksum of every image
         e = enqueue(b, s);
         if (e == hipSuccess)
@@ -596,6 +604,7 @@ int rz_batch_autotune(rz_batch *b, void *stream, int32_t reps, rz_batch_opts *ch
             best_opts = b->opts;
             best_opts.launch = launch_of(b->tune);
             best_tune = b->tune;
+            best_tune_hq = b->tune_hq;
         }
     }
     if (e0)
@@ -605,11 +614,13 @@ int rz_batch_autotune(rz_batch *b, void *stream, int32_t reps, rz_batch_opts *ch
     if (e != hipSuccess) {
         b->opts = saved;
         b->tune = tune_of(saved.launch);
+        b->tune_hq = b->tune;
         return hip_fail(e);
     }
     b->opts = best_opts;
     b->opts.use_graph = had_graph ? 1 : 0;
     b->tune = best_tune;
+    b->tune_hq = best_tune_hq;
     if (had_graph) {
         int rc = capture(b);
         if (rc)
