@@ -206,6 +206,113 @@ def _random_scene(seed, n, W, H, kind=LINEAR, scale=0.0):
     return v, pts[:, 0].copy(), pts[:, 1].copy(), pts[:, 2].copy(), rgb
 
 
+def _round_ieee(v: F, p: int, emin: int) -> F:
+    """v rounded to the nearest binary floating-point number with p significand
+    bits and least normal exponent emin, ties to even (IEEE 754, section 4.3.1);
+    no overflow in these inputs."""
+    if v == 0:
+        return F(0)
+    sign, a = (-1, -v) if v < 0 else (1, v)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if F(2) ** e > a:
+        e -= 1
+    ulp = F(2) ** (max(e, emin) - p + 1)
+    m = a / ulp
+    k = m.numerator // m.denominator
+    r = m - k
+    if r > F(1, 2) or (r == F(1, 2) and k % 2 == 1):
+        k += 1
+    return sign * k * ulp
+
+
+def _r32(v):
+    return _round_ieee(v, 24, -126)
+
+
+def _r64(v):
+    return _round_ieee(v, 53, -1022)
+
+
+def _rounded_fragment(m, v, W, H, near, far, o, s, X, Y, Z, fused):
+    """Pixel and 40-bit depth with every operation rounded as a reading states:
+    fused=True is the reading the oracle implements (each fused multiply-add of
+    a matrix row rounded once, one rounded reciprocal of w, a fused viewport);
+    fused=False is the unfused order with two divisions and (ndc + 1)·size/2."""
+    def row(r, mat, rnd):
+        if fused:
+            a = rnd(mat[4 * r] * X + mat[4 * r + 3])
+            a = rnd(mat[4 * r + 1] * Y + a)
+            return rnd(mat[4 * r + 2] * Z + a)
+        a = rnd(rnd(mat[4 * r] * X) + rnd(mat[4 * r + 1] * Y))
+        a = rnd(a + rnd(mat[4 * r + 2] * Z))
+        return rnd(a + mat[4 * r + 3])
+
+    cx, cy, cw = row(0, m, _r32), row(1, m, _r32), row(3, m, _r32)
+    if not cw > 0:
+        return -1, None
+    hw, hh = F(W, 2), F(H, 2)
+    if fused:
+        iw = _r32(1 / cw)
+        nx, ny = _r32(cx * iw), _r32(cy * iw)
+        fx, fy = _r32(nx * hw + hw), _r32(ny * hh + hh)
+    else:
+        nx, ny = _r32(cx / cw), _r32(cy / cw)
+        fx, fy = _r32(_r32(nx + 1) * hw), _r32(_r32(ny + 1) * hh)
+    if not (0 <= fx < W and 0 <= fy < H):
+        return -1, None
+    d = row(3, v, _r64)
+    if not (near <= d < far):
+        return -1, None
+    t = _r64(_r64(d - o) * s)
+    q = min(t.numerator // t.denominator, (1 << 40) - 2)
+    return (fy.numerator // fy.denominator) * W + fx.numerator // fx.denominator, q
+
+
+@pytest.mark.parametrize("offset", [0.0, 3.0e5])
+def test_projection_rounding_follows_the_fused_reading(oracle, offset):
+    """The section 1 projection runs in FP32 and the depth in FP64, but the
+    paper fixes no operation order.  Against the IEEE definition of each
+    rounded step, evaluated in exact rationals, the oracle takes the fused
+    order bit for bit; on the same points the unfused order moves some pixels
+    or depths, so the comparison tells the two readings apart.  The second
+    scene sits 3·10^5 units from the origin (georeferenced coordinates), where
+    the terms of the depth row cancel and its rounding decides the 40-bit q."""
+    W, H = 15000, 12000          # half sizes that are not powers of two
+    v, x, y, z, rgb = _random_scene(11, 1500, W, H)
+    # and 500 points unprojected from within 10^-4 pixel of a pixel corner,
+    # where the rounding of the divide and the viewport decides the floor
+    rng = np.random.default_rng(13)
+    corner = rng.integers(1, [W, H], size=(500, 2)) + rng.uniform(-1e-4, 1e-4, (500, 2))
+    ndc = np.column_stack([2 * corner / [W, H] - 1, rng.uniform(-0.9, 0.9, 500), np.ones(500)])
+    world = np.linalg.solve(np.asarray(v.vp, np.float64).reshape(4, 4), ndc.T).T
+    world = (world[:, :3] / world[:, 3:]).astype(np.float32)
+    x, y, z = (np.concatenate([a, world[:, k]]) for k, a in enumerate((x, y, z)))
+    if offset:
+        off = np.array([offset, 0.5 * offset, -0.25 * offset])
+        rng = np.random.default_rng(12)
+        v = gen.make_view(rng.uniform(-3, 3, 3) + np.array([0, 0, 6.0]) + off,
+                          rng.uniform(-0.5, 0.5, 3) + off, (0.2, 1.0, 0.1), 55.0, W, H, 0.3, 12.0)
+        x, y, z = ((a + np.float32(b)).astype(np.float32) for a, b in zip((x, y, z), off))
+    o, s, z0 = oracle.depth_constants(v.vp, v.near, v.far, W, H)
+    vp = np.asarray(v.vp, np.float64).reshape(16)
+    m = [F(float(np.float32(a))) for a in vp]
+    vv = [F(float(a)) for a in vp]
+    near, far, fo, fs = F(float(v.near)), F(float(v.far)), F(o), F(s)
+    pix, q = oracle.fragments(x, y, z, v.vp, v.near, v.far, W, H)
+    differ = frags = 0
+    for i in range(x.shape[0]):
+        X, Y, Z = F(float(x[i])), F(float(y[i])), F(float(z[i]))
+        ep, eq = _rounded_fragment(m, vv, W, H, near, far, fo, fs, X, Y, Z, True)
+        assert int(pix[i]) == ep, i
+        if ep >= 0:
+            frags += 1
+            assert int(q[i]) == eq, i
+        up, uq = _rounded_fragment(m, vv, W, H, near, far, fo, fs, X, Y, Z, False)
+        differ += (up, uq) != (ep, eq)
+    assert frags > 300
+    assert differ > 0
+
+
 @pytest.mark.parametrize("seed,kind,scale", [(1, LINEAR, 0.0), (2, LINEAR, 0.0), (3, SCALE, 1000.0),
                                              (4, SCALE, 2.0 ** 30)])
 def test_fragments_match_exact_projection(oracle, seed, kind, scale):

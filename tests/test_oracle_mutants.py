@@ -19,6 +19,12 @@ MUTANTS = {
     "ndc scales by the wrong reciprocal": ("ny = cy * iw;", "ny = cy / cx;"),
     "reciprocal of the wrong row": ("iw = 1.0f / cw;", "iw = 1.0f / cx;"),
     "window edge inclusive": ("fx < c->fw", "fx <= c->fw"),
+    "clip row unfused": ("cx = fmaf(m[0], x, m[3]);\n    cx = fmaf(m[1], y, cx);\n    cx = fmaf(m[2], z, cx);",
+                         "cx = ((m[0] * x + m[1] * y) + m[2] * z) + m[3];"),
+    "depth row unfused": ("d = fma(v[13], (double)y, d);\n    d = fma(v[14], (double)z, d);",
+                          "d = (d + v[13] * (double)y) + v[14] * (double)z;"),
+    "division instead of the reciprocal": ("nx = cx * iw;", "nx = cx / cw;"),
+    "viewport unfused": ("fx = fmaf(nx, c->hw, c->hw);", "fx = (nx + 1.0f) * c->hw;"),
     "depth from row 2": ("d = fma(v[12], (double)x, v[15]);", "d = fma(v[8], (double)x, v[15]);"),
     "depth offset dropped": ("d = fma(v[12], (double)x, v[15]);", "d = v[12] * (double)x;"),
     "depth in single precision": ("d = fma(v[14], (double)z, d);",
@@ -92,6 +98,7 @@ PINS = [
     (T.test_optical_axis_hits_centre_pixel, {}),
     (T.test_resolve_clears_framebuffer, {}),
     (T.test_fragments_match_exact_projection, {"seed": 1, "kind": 0, "scale": 0.0}),
+    *[(T.test_projection_rounding_follows_the_fused_reading, {"offset": f}) for f in (0.0, 3.0e5)],
     (T.test_framebuffer_matches_brute_force, {"seed": 5}),
     (T.test_eps_window_relative_to_linear_depth, {}),
     (T.test_piecewise_paper_example, {}),
