@@ -65,8 +65,9 @@ def workload(name):
     return cloud, view, desc
 
 
-def cpu_baseline(cloud, view, eps, budget_s=20.0):
-    """The oracle, single-threaded, on the same workload (whole frames)."""
+def cpu_baseline(cloud, view, eps, min_s=10.0, budget_s=20.0):
+    """The oracle, single-threaded, on the same workload (whole frames):
+    at least three frames and min_s seconds of work, at most budget_s."""
     from oracle import oracle
     oracle.build()
     n = cloud.n
@@ -81,7 +82,8 @@ def cpu_baseline(cloud, view, eps, budget_s=20.0):
                          view.width, view.height, eps=eps)
         t2 = time.perf_counter()
         times.append((t1 - t0, t2 - t1))
-        if time.perf_counter() - t_start > budget_s or len(times) >= 3:
+        spent = time.perf_counter() - t_start
+        if spent > budget_s or (len(times) >= 3 and spent >= min_s):
             break
     t_min = float(np.median([a for a, _ in times]))
     t_hq = float(np.median([b for _, b in times]))
