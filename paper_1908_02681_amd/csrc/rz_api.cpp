@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
+
 #include <hip/hip_runtime.h>
 
 #include "rz.h"
@@ -20,11 +22,23 @@ int hip_fail(hipError_t e)
     return RZ_EHIP;
 }
 
+// Launch shapes, process wide: every call takes a copy under the lock, so a
+// concurrent rz_set_launch never tears the shape a call launches with.
+static std::mutex g_tune_mu;
 static Tune g_tune;              // launch shape of the depth pass
 static Tune g_tune_hq = kHqTune;  // and of the splat accumulate pass
 
-const Tune &current_tune() { return g_tune; }
-const Tune &current_tune_hq() { return g_tune_hq; }
+Tune current_tune()
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    return g_tune;
+}
+
+Tune current_tune_hq()
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    return g_tune_hq;
+}
 
 constexpr double kQRange = 1099511627775.0;   // 2^40 - 1
 constexpr int64_t kMaxPoints = 4294966784ll;  // 2^32 - 2^9
@@ -189,7 +203,7 @@ int rasterize_atomicmin(const rz_points *pts, const rz_view *view, const rz_dept
         return RZ_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const Pts p{pts->x, pts->y, pts->z, pts->rgb, pts->n};
-    hipError_t e = launch_raster_min(p, P, fb, g_tune, s);   // every encoding
+    hipError_t e = launch_raster_min(p, P, fb, current_tune(), s);   // every encoding
     if (e != hipSuccess)
         return hip_fail(e);
     if (!(flags & RZ_KEEP_KEYS)) {
@@ -217,9 +231,9 @@ int rasterize_hq_splat(const rz_points *pts, const rz_view *view, const rz_depth
         return RZ_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const Pts p{pts->x, pts->y, pts->z, pts->rgb, pts->n};
-    hipError_t e = launch_raster_min(p, P, fb, g_tune, s);
+    hipError_t e = launch_raster_min(p, P, fb, current_tune(), s);
     if (e == hipSuccess)
-        e = launch_hq_accum(p, P, num, den, fb, acc, g_tune_hq, s);
+        e = launch_hq_accum(p, P, num, den, fb, acc, current_tune_hq(), s);
     if (e == hipSuccess && !(flags & RZ_KEEP_KEYS))
         e = launch_resolve_hq(fb, acc, (int64_t)P.width * P.height, background, img, status, s);
     return e == hipSuccess ? RZ_OK : hip_fail(e);
@@ -240,7 +254,7 @@ int rz_hq_accumulate(const rz_points *pts, const rz_view *view, const rz_depth_m
     if (!fb || !acc)
         return RZ_EINVAL;
     const Pts p{pts->x, pts->y, pts->z, pts->rgb, pts->n};
-    hipError_t e = launch_hq_accum(p, P, num, den, fb, acc, g_tune_hq, (hipStream_t)stream);
+    hipError_t e = launch_hq_accum(p, P, num, den, fb, acc, current_tune_hq(), (hipStream_t)stream);
     return e == hipSuccess ? RZ_OK : hip_fail(e);
 }
 
@@ -267,10 +281,10 @@ int rasterize_points(const rz_points *pts, const rz_view *view, const rz_depth_m
     // encodings are depth-only: check_hq rejects them with splatting)
     const bool general = point_size > 1;
     hipError_t e = general ? launch_raster_points(p, P, point_size, fb, s)
-                           : launch_raster_min(p, P, fb, g_tune, s);
+                           : launch_raster_min(p, P, fb, current_tune(), s);
     if (e == hipSuccess && hq)
         e = general ? launch_hq_points(p, P, point_size, num, den, fb, acc, s)
-                    : launch_hq_accum(p, P, num, den, fb, acc, g_tune_hq, s);
+                    : launch_hq_accum(p, P, num, den, fb, acc, current_tune_hq(), s);
     const int64_t npix = (int64_t)P.width * P.height;
     if (e == hipSuccess && !(flags & RZ_KEEP_KEYS))
         e = hq ? launch_resolve_hq(fb, acc, npix, background, img, status, s)
@@ -306,6 +320,7 @@ int rz_resolve_hq(uint64_t *fb, uint64_t *acc, int64_t npix, uint32_t background
 int rz_set_launch(const rz_launch *l)
 {
     if (!l) {   // back to the library defaults
+        std::lock_guard<std::mutex> lock(g_tune_mu);
         g_tune = Tune();
         g_tune_hq = kHqTune;
         return RZ_OK;
@@ -316,6 +331,7 @@ int rz_set_launch(const rz_launch *l)
         return RZ_EINVAL;
     if ((l->early_out & ~1) || (l->xcd_remap & ~1) || l->bin < 0 || l->bin > 2)
         return RZ_EINVAL;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune.block = l->block;
     g_tune.ppt = l->ppt;
     g_tune.early_out = l->early_out;
@@ -329,11 +345,12 @@ int rz_get_launch(rz_launch *l)
 {
     if (!l)
         return RZ_EINVAL;
-    l->block = g_tune.block;
-    l->ppt = g_tune.ppt;
-    l->early_out = g_tune.early_out;
-    l->xcd_remap = g_tune.xcd_remap;
-    l->bin = g_tune.bin;
+    const Tune t = current_tune();
+    l->block = t.block;
+    l->ppt = t.ppt;
+    l->early_out = t.early_out;
+    l->xcd_remap = t.xcd_remap;
+    l->bin = t.bin;
     return RZ_OK;
 }
 

@@ -28,7 +28,7 @@ int check_points(const rz_points *p);
 int make_proj(const rz_view *v, const rz_depth_map *dm, Proj *P);
 int check_hq(const rz_hq_params *hq, const Proj &P, uint32_t *num, uint32_t *den);
 int hip_fail(hipError_t e);
-const Tune &current_tune();
+Tune current_tune();
 
 namespace {
 

@@ -35,8 +35,8 @@ int check_points(const rz_points *p);
 int make_proj(const rz_view *v, const rz_depth_map *dm, Proj *P);
 int check_hq(const rz_hq_params *hq, const Proj &P, uint32_t *num, uint32_t *den);
 int hip_fail(hipError_t e);
-const Tune &current_tune();
-const Tune &current_tune_hq();
+Tune current_tune();
+Tune current_tune_hq();
 
 namespace {
 
@@ -180,7 +180,7 @@ int launch(rz_server *s, Req *r)
     uint64_t *acc = r->acc_bytes ? (uint64_t *)(s->dmem + r->off + r->fb_bytes) : nullptr;
     uint32_t *status = (uint32_t *)(s->dmem + r->off + r->fb_bytes + r->acc_bytes);
     const Pts &p = s->clouds[r->r.cloud];
-    const Tune &t = current_tune();
+    const Tune t = current_tune();
     hipError_t e = launch_clear(fb, acc, (int64_t)r->npix, r->r.background, st);
     if (e == hipSuccess)
         e = hipMemsetAsync(status, 0, sizeof(uint32_t), st);

@@ -263,3 +263,34 @@ def test_batch_plan_validation(rz):
     for fn in ("rz_batch_run", "rz_batch_capture", "rz_batch_destroy"):
         args = (None, None) if fn == "rz_batch_run" else (None,)
         assert getattr(lib, fn)(*args) == rz.RZ_EINVAL
+
+
+def test_launch_shape_is_never_torn(rz):
+    """rz_set_launch and rz_get_launch from several threads at once (ctypes
+    drops the GIL around each call): every read returns one of the shapes
+    written, never a mix of two."""
+    import threading
+    shapes = [(256, 4, 0, 1, 0), (64, 16, 1, 0, 2), (512, 8, 1, 1, 1)]
+    allowed = {s for s in shapes}
+    bad = []
+
+    def writer(shape):
+        for _ in range(3000):
+            rz.set_launch(*shape)
+
+    def reader():
+        for _ in range(3000):
+            g = rz.get_launch()
+            t = (g["block"], g["ppt"], g["early_out"], g["xcd_remap"], g["bin"])
+            if t not in allowed:
+                bad.append(t)
+
+    rz.set_launch(*shapes[0])
+    threads = [threading.Thread(target=writer, args=(s,)) for s in shapes]
+    threads += [threading.Thread(target=reader) for _ in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    rz.reset_launch()
+    assert not bad, bad[:3]
