@@ -222,6 +222,21 @@ def test_tile_fallback_and_sparse_screens(rz, oracle, bin_):
         rz.reset_launch()
 
 
+@pytest.mark.parametrize("size", [(1, 1), (1, 7), (7, 1), (3, 2)])
+def test_tiny_screens(rz, oracle, size):
+    """Screens of one pixel, one column and one row: every wave's fragments
+    pile onto a few pixels, in tiles one pixel wide or high; under every
+    merge mode (direct atomics, workgroup tiles, wave tiles)."""
+    cloud, _ = gen.config1(n=20_000)
+    view = gen.make_view((0.5, 0.5, 2.5), (0.5, 0.5, 0.5), (0, 1, 0), 60.0, *size, 0.01, 10.0)
+    try:
+        for bin_ in (2, 1, 0):
+            rz.set_launch(bin=bin_)
+            check_scene(rz, oracle, cloud, view, bg=0x0A0B0C, label=f"tiny {size} bin={bin_}")
+    finally:
+        rz.reset_launch()
+
+
 def test_unaligned_planes_take_the_scalar_path(rz, oracle):
     import torch
     cloud = gen.terrain(50_001, 4, extent=50.0, amplitude=5.0, wavelength=20.0)

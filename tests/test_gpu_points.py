@@ -66,6 +66,14 @@ def test_point_sizes_spheres(rz, oracle, k):
     check(rz, oracle, cloud, view, k=k, bg=0x102030, label="spheres")
 
 
+@pytest.mark.parametrize("size,k", [((1, 1), 3), ((3, 2), 5), ((1, 7), 4), ((7, 1), 2)])
+def test_points_larger_than_the_screen(rz, oracle, size, k):
+    """k x k squares clipped on every side by a screen of a few pixels."""
+    cloud, _ = gen.config1(n=20_000)
+    view = gen.make_view((0.5, 0.5, 2.5), (0.5, 0.5, 0.5), (0, 1, 0), 60.0, *size, 0.01, 10.0)
+    check(rz, oracle, cloud, view, k=k, bg=0x0A0B0C, label=f"tiny {size}")
+
+
 @pytest.mark.parametrize("k", [2, 5])
 def test_point_sizes_terrain(rz, oracle, k):
     cloud = gen.terrain(500_000, 51, extent=100.0, amplitude=10.0, wavelength=40.0)
