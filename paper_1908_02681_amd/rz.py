@@ -213,6 +213,26 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _fits(what, t, nbytes):
+    """The library writes nbytes from t's address: t must be a contiguous
+    device tensor holding at least that many bytes."""
+    if t is None:
+        return
+    if not t.is_contiguous() or t.numel() * t.element_size() < nbytes:
+        raise RzError(RZ_EINVAL, f"{what}: needs a contiguous device tensor of at least "
+                      f"{nbytes} bytes, got {t.numel() * t.element_size()} "
+                      f"({'contiguous' if t.is_contiguous() else 'not contiguous'})")
+
+
+def _fits_view(npix, fb=None, acc=None, img=None, status=None):
+    """Framebuffer (8 B), splat sums (16 B) and image (4 B) per pixel, and a
+    4-byte status word."""
+    _fits("fb", fb, 8 * npix)
+    _fits("acc", acc, 16 * npix)
+    _fits("img", img, 4 * npix)
+    _fits("status", status, 4)
+
+
 def _stream(stream):
     torch = _torch()
     if stream is None:
@@ -296,6 +316,7 @@ def new_framebuffer(view, background=0, hq=False, stream=None):
 
 def clear(fb, acc, npix, background=0, stream=None):
     _require_gpu(fb, acc)
+    _fits_view(int(npix), fb, acc)
     _check(load().rz_clear(_ptr(fb), _ptr(acc), int(npix), int(background) & 0xFFFFFFFF,
                            _stream(stream)), "rz_clear")
 
@@ -305,6 +326,7 @@ def resolve_min(fb, npix, background=0, img=None, stream=None):
     _require_gpu(fb, img)
     if img is None:
         img = torch.empty(int(npix), dtype=torch.int32, device="cuda")
+    _fits_view(int(npix), fb, img=img)
     _check(load().rz_resolve_min(_ptr(fb), int(npix), int(background) & 0xFFFFFFFF, _ptr(img),
                                  _stream(stream)), "rz_resolve_min")
     return img
@@ -315,6 +337,7 @@ def resolve_hq(fb, acc, npix, background=0, img=None, status=None, stream=None):
     _require_gpu(fb, acc, img, status)
     if img is None:
         img = torch.empty(int(npix), dtype=torch.int32, device="cuda")
+    _fits_view(int(npix), fb, acc, img, status)
     _check(load().rz_resolve_hq(_ptr(fb), _ptr(acc), int(npix), int(background) & 0xFFFFFFFF,
                                 _ptr(img), _ptr(status), _stream(stream)), "rz_resolve_hq")
     return img
@@ -330,6 +353,7 @@ def rasterize_atomicmin(points: Points, view, depth=None, background=0, fb=None,
         fb, _ = new_framebuffer(view, background, stream=stream)
     if img is None and not keep_keys:
         img = torch.empty(_npix(view), dtype=torch.int32, device="cuda")
+    _fits_view(_npix(view), fb, img=img)
     ps, vs = points.struct(), view_struct(view)
     ds = depth if isinstance(depth, rz_depth_map) else depth_struct(*(depth or (DEPTH_LINEAR, 0.0)))
     rc = load().rasterize_atomicmin(ctypes.byref(ps), ctypes.byref(vs), ctypes.byref(ds),
@@ -351,6 +375,7 @@ def rasterize_hq_splat(points: Points, view, depth=None, eps=(1, 100), backgroun
         img = torch.empty(_npix(view), dtype=torch.int32, device="cuda")
     if status is None:
         status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _fits_view(_npix(view), fb, acc, img, status)
     ps, vs = points.struct(), view_struct(view)
     ds = depth if isinstance(depth, rz_depth_map) else depth_struct(*(depth or (DEPTH_LINEAR, 0.0)))
     hq = rz_hq_params(int(eps[0]), int(eps[1]))
@@ -365,6 +390,7 @@ def rasterize_hq_splat(points: Points, view, depth=None, eps=(1, 100), backgroun
 def hq_accumulate(points: Points, view, fb, acc, depth=None, eps=(1, 100), stream=None):
     """Second splatting pass alone; fb holds the finished depth pass."""
     _require_gpu(points.x, fb, acc)
+    _fits_view(_npix(view), fb, acc)
     ps, vs = points.struct(), view_struct(view)
     ds = depth if isinstance(depth, rz_depth_map) else depth_struct(*(depth or (DEPTH_LINEAR, 0.0)))
     hq = rz_hq_params(int(eps[0]), int(eps[1]))
@@ -388,6 +414,8 @@ def rasterize_points(points: Points, view, depth=None, hq=False, eps=(1, 100), p
         img = torch.empty(_npix(view), dtype=torch.int32, device="cuda")
     if hq and status is None:
         status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _fits_view(_npix(view), fb, acc if hq else None, None if keep_keys else img,
+               status if hq else None)
     ps, vs = points.struct(), view_struct(view)
     ds = depth if isinstance(depth, rz_depth_map) else depth_struct(*(depth or (DEPTH_LINEAR, 0.0)))
     hp = ctypes.byref(rz_hq_params(int(eps[0]), int(eps[1]))) if hq else None
@@ -432,6 +460,9 @@ def rasterize_sorted(points: Points, view, depth=None, hq=False, eps=(1, 100), b
         status = torch.zeros(1, dtype=torch.int32, device="cuda")
     if workspace is None:
         workspace = new_workspace(points.n, view.width, view.height)
+    _fits_view(_npix(view), fb, acc if hq else None, None if keep_keys else img,
+               status if hq else None)
+    _fits("workspace", workspace, 0)
     ps, vs = points.struct(), view_struct(view)
     ds = depth if isinstance(depth, rz_depth_map) else depth_struct(*(depth or (DEPTH_LINEAR, 0.0)))
     hp = ctypes.byref(rz_hq_params(int(eps[0]), int(eps[1]))) if hq else None
@@ -449,6 +480,8 @@ def merge_min(dst, src, npix=None, stream=None):
     """Sort-last composition of depth passes: dst = min(dst, src) per pixel."""
     _require_gpu(dst, src)
     n = dst.numel() if npix is None else int(npix)
+    _fits("dst", dst, 8 * n)
+    _fits("src", src, 8 * n)
     _check(load().rz_merge_min(_ptr(dst), _ptr(src), n, _stream(stream)), "rz_merge_min")
     return dst
 
@@ -457,6 +490,8 @@ def merge_sum(dst, src, npix=None, stream=None):
     """Sort-last composition of packed splat sums (2 words per pixel)."""
     _require_gpu(dst, src)
     n = dst.numel() // 2 if npix is None else int(npix)
+    _fits("dst", dst, 16 * n)
+    _fits("src", src, 16 * n)
     _check(load().rz_merge_sum(_ptr(dst), _ptr(src), n, _stream(stream)), "rz_merge_sum")
     return dst
 
@@ -566,6 +601,7 @@ class Batch:
             opts.launch = rz_launch(*launch) if not isinstance(launch, dict) else rz_launch(
                 **{k: launch[k] for k, _ in rz_launch._fields_})
         opts.use_graph = 1 if use_graph else 0
+        _fits("status", status, 4)
         opts.status = status.data_ptr() if status is not None else None
         self._ps = points.struct()
         self._arr = arr
@@ -640,6 +676,7 @@ class Server:
 
     def submit(self, cloud, view, mode, img=None, depth=None, eps=(1, 100), background=0,
                inject_failure=False) -> int:
+        _fits("img", img, 4 * _npix(view))
         ds = depth if isinstance(depth, rz_depth_map) else depth_struct(*(depth or (DEPTH_LINEAR, 0.0)))
         r = rz_request(int(cloud), int(mode), view_struct(view), ds,
                        rz_hq_params(int(eps[0]), int(eps[1])), int(background) & 0xFFFFFFFF,

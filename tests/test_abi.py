@@ -294,3 +294,19 @@ def test_launch_shape_is_never_torn(rz):
         t.join()
     rz.reset_launch()
     assert not bad, bad[:3]
+
+
+def test_binding_checks_buffer_sizes(rz):
+    """The binding refuses a buffer too small or not contiguous for what the
+    library will write into it (the C ABI takes bare pointers)."""
+    import torch
+    npix = 6
+    rz._fits_view(npix, torch.empty(npix, dtype=torch.int64), torch.empty(2 * npix, dtype=torch.int64),
+                  torch.empty(npix, dtype=torch.int32), torch.empty(1, dtype=torch.int32))
+    for kw in ({"fb": torch.empty(npix - 1, dtype=torch.int64)},
+               {"acc": torch.empty(2 * npix - 1, dtype=torch.int64)},
+               {"img": torch.empty(npix, dtype=torch.int16)},
+               {"status": torch.empty(0, dtype=torch.int32)},
+               {"fb": torch.empty(2 * npix, dtype=torch.int64)[::2]}):
+        with pytest.raises(rz.RzError):
+            rz._fits_view(npix, **kw)

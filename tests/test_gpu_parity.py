@@ -237,6 +237,35 @@ def test_tiny_screens(rz, oracle, size):
         rz.reset_launch()
 
 
+def test_binding_refuses_small_buffers(rz):
+    """Each call refuses an fb, acc or img shorter than the view before
+    anything is enqueued.  The short buffers are slices of full-size ones, so
+    nothing could be written outside an allocation either way."""
+    import torch
+    cloud, view = gen.config1(n=1000)
+    view = gen.View(view.vp, view.near, view.far, 64, 32)
+    pts = rz.Points.from_cloud(cloud)
+    fb, acc = rz.new_framebuffer(view, hq=True)
+    img = torch.empty(64 * 32, dtype=torch.int32, device="cuda")
+    short_fb, short_acc, short_img = fb[:-1], acc[:-1], img[:-1]
+    calls = [
+        lambda: rz.rasterize_atomicmin(pts, view, fb=short_fb, img=img),
+        lambda: rz.rasterize_atomicmin(pts, view, fb=fb, img=short_img),
+        lambda: rz.rasterize_hq_splat(pts, view, fb=fb, acc=short_acc, img=img),
+        lambda: rz.rasterize_points(pts, view, hq=True, point_size=3, fb=fb, acc=short_acc, img=img),
+        lambda: rz.rasterize_sorted(pts, view, fb=short_fb, img=img),
+        lambda: rz.resolve_min(short_fb, 64 * 32, img=img),
+        lambda: rz.clear(fb, short_acc, 64 * 32),
+        lambda: rz.merge_min(fb, short_fb, 64 * 32),
+    ]
+    for i, call in enumerate(calls):
+        with pytest.raises(rz.RzError):
+            call()
+    torch.cuda.synchronize()
+    # nothing ran: the buffers are still cleared
+    assert (rz.to_u64(fb) == np.uint64(0xFFFFFFFFFF000000)).all() and (rz.to_u64(acc) == 0).all()
+
+
 def test_unaligned_planes_take_the_scalar_path(rz, oracle):
     import torch
     cloud = gen.terrain(50_001, 4, extent=50.0, amplitude=5.0, wavelength=20.0)
