@@ -87,13 +87,21 @@ def cpu_baseline(cloud, view, eps, min_s=10.0, budget_s=20.0):
             break
     t_min = float(np.median([a for a, _ in times]))
     t_hq = float(np.median([b for _, b in times]))
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next(line.split(":", 1)[1].strip() for line in f
+                         if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {
         "value": round(2 * n / (t_min + t_hq) / 1e9, 6),
         "unit": "Gpoints/s",
         "cores": 1,
         "kind": "oracle",
         "sample": f"{len(times)} full frames (atomicMin + HQ) of the same {n}-point workload; "
-                  f"median atomicMin {t_min:.3f} s, HQ {t_hq:.3f} s",
+                  f"median atomicMin {t_min:.3f} s, HQ {t_hq:.3f} s; one thread on {model} "
+                  f"({os.cpu_count()} host cores)",
     }
 
 
