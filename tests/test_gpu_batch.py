@@ -176,3 +176,57 @@ def test_batch_mixed_depth_maps(rz, oracle, scene):
                                           v.far, v.width, v.height, dm[0], dm[1], bg=bg)
         assert np.array_equal(got, want)
     b.close()
+
+
+def test_batch_full_size(rz, oracle):
+    """The batched multi-view workload at its full size (100M Morton-ordered
+    terrain points resident, 64 orbit views at 256x256 to 1920x1080, modes
+    drawn 50/50), in the default and in the autotuned launch shapes: every
+    view's image equals its one-view call bit for bit, and the two smallest
+    views (one per method) equal the oracle's whole images."""
+    import torch
+    sizes = [(256, 256), (640, 480), (1280, 720), (1920, 1080)]
+    say("[batch-full] generating 100M terrain points")
+    cloud = gen.terrain(100_000_000, gen.CONFIG_SEEDS[4])
+    views = gen.orbit_views(64, gen.CONFIG_SEEDS[4], sizes)
+    modes = np.random.default_rng([gen.CONFIG_SEEDS[4], 7]).integers(0, 2, 64).tolist()
+    # the smallest view of each method, checked against the oracle
+    picks = {}
+    for i in sorted(range(64), key=lambda i: views[i].width * views[i].height):
+        picks.setdefault(modes[i], i)
+    want = {}
+    for m, i in picks.items():
+        v = views[i]
+        say(f"[batch-full] oracle view {i} {v.width}x{v.height} mode {m}")
+        if m == 0:
+            _, want[i] = oracle.render_atomicmin(cloud.x, cloud.y, cloud.z, cloud.rgb, v.vp,
+                                                 v.near, v.far, v.width, v.height)
+        else:
+            _, _, want[i] = oracle.render_hq(cloud.x, cloud.y, cloud.z, cloud.rgb, v.vp, v.near,
+                                             v.far, v.width, v.height)
+    pts = rz.Points.from_cloud(cloud)
+    del cloud
+    say("[batch-full] one-view calls")
+    plain = []
+    for v, m in zip(views, modes):
+        img = (rz.rasterize_atomicmin(pts, v)[1] if m == 0 else rz.rasterize_hq_splat(pts, v)[2])
+        plain.append(img)
+    torch.cuda.synchronize()
+    for i in want:
+        assert np.array_equal(rz.to_u32(plain[i]), want[i]), f"one-view call, view {i}"
+    b = rz.Batch(pts, views, modes, use_graph=True)
+    try:
+        for label in ("default", "autotuned"):
+            if label == "autotuned":
+                say("[batch-full] autotune")
+                b.autotune(reps=1)
+            say(f"[batch-full] batch run, {label} shapes")
+            b.run()
+            torch.cuda.synchronize()
+            for i, (got, ref) in enumerate(zip(b.imgs, plain)):
+                assert torch.equal(got, ref), f"{label}: view {i} differs from its one-view call"
+            for i in want:
+                assert np.array_equal(rz.to_u32(b.imgs[i]), want[i]), f"{label}: view {i}"
+    finally:
+        b.close()
+    say("[batch-full] done")
