@@ -393,8 +393,9 @@ def main():
                          "(a plain copy kernel of known size for scaling HBM counters)")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the sharded "
-              "path is not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the sort-last "
+              "composition across GPUs is designed, with its merge kernels timed on one GPU, "
+              "but not run across GPUs", file=sys.stderr)
         raise SystemExit(2)
 
     import torch
