@@ -8,6 +8,7 @@ from __future__ import annotations
 import argparse
 import concurrent.futures as cf
 import glob
+import hashlib
 import os
 import subprocess
 import sys
@@ -50,7 +51,10 @@ def _compile(src, force):
     if not force and os.path.exists(obj) and os.path.getmtime(obj) >= newest:
         return obj
     tmp = obj + f".tmp{os.getpid()}"
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", tmp]
+    # a fixed compilation-unit id per source (the default one hashes the
+    # output path, which here holds the process id): reproducible libraries
+    cuid = hashlib.sha1(os.path.basename(src).encode()).hexdigest()[:16]
+    cmd = [HIPCC, *FLAGS, f"-cuid={cuid}", "-c", src, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(line for line in r.stderr.splitlines()
                     if "packed-fp32-ops" not in line)
