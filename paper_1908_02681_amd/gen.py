@@ -18,6 +18,8 @@ plane holding R | G << 8 | B << 16 (top byte zero).
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -26,6 +28,7 @@ __all__ = [
     "Cloud", "View", "look_at", "perspective", "make_view", "spheres",
     "terrain", "terrain_height", "buildings", "concat", "shuffle",
     "orbit_views", "config1", "config2", "config3", "CONFIG_SEEDS",
+    "SERVE_SIZES", "SERVE_CLOUDS", "serve_cloud", "request_trace",
 ]
 
 # Seeds of the five benchmark workloads (1M spheres, 50M terrain, 300M
@@ -103,6 +106,30 @@ def make_view(eye, target, up, fovy, width, height, near, far, **meta) -> View:
 
 
 # --------------------------------------------------------------------------
+# element-wise work in chunks on a thread pool (numpy releases the GIL in
+# its array loops); every chunk computes exactly what one whole-array
+# expression would, so the result does not depend on the thread count
+# --------------------------------------------------------------------------
+
+_CHUNK = 1 << 22
+
+
+def _threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _chunked(n: int, fn):
+    """fn(a, b) for consecutive ranges covering [0, n), on a thread pool."""
+    ranges = [(a, min(n, a + _CHUNK)) for a in range(0, n, _CHUNK)]
+    if len(ranges) <= 1:
+        for a, b in ranges:
+            fn(a, b)
+        return
+    with ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(lambda r: fn(*r), ranges))
+
+
+# --------------------------------------------------------------------------
 # integer hash used for lattice noise (Wellons' "lowbias32" mixer)
 # --------------------------------------------------------------------------
 
@@ -154,6 +181,18 @@ def terrain_height(px, py, seed: int, extent=1000.0, amplitude=50.0,
     return z * (amplitude / total)
 
 
+def _chunked_rows(g: int, fn):
+    """fn(a, b) over row ranges of a g x g grid, about _CHUNK cells each."""
+    per = max(1, _CHUNK // max(1, g))
+    ranges = [(a, min(g, a + per)) for a in range(0, g, per)]
+    if len(ranges) <= 1:
+        for a, b in ranges:
+            fn(a, b)
+        return
+    with ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(lambda r: fn(*r), ranges))
+
+
 def _height_grid(g: int, h: float, seed: int, extent, amplitude, wavelength,
                  octaves, persistence) -> np.ndarray:
     """Value noise at the g x g cell centres ((i + 0.5) h, (j + 0.5) h), as a
@@ -173,8 +212,11 @@ def _height_grid(g: int, h: float, seed: int, extent, amplitude, wavelength,
         rows = (lat[:, iu] * (1 - t)[None, :] + lat[:, iu + 1] * t[None, :]).astype(np.float32)
         w1 = (amp * t).astype(np.float32)[:, None]
         w0 = (amp * (1 - t)).astype(np.float32)[:, None]
-        z += rows[iu] * w0
-        z += rows[iu + 1] * w1
+
+        def add_rows(a, b, rows=rows, iu=iu, w0=w0, w1=w1):
+            z[a:b] += rows[iu[a:b]] * w0[a:b]
+            z[a:b] += rows[iu[a:b] + 1] * w1[a:b]
+        _chunked_rows(g, add_rows)
         total += amp
         amp *= persistence
     z *= np.float32(amplitude / total)
@@ -199,20 +241,41 @@ def _compact1by1(v: np.ndarray) -> np.ndarray:
     return t[v & np.uint32(0xFFFF)] | (t[v >> np.uint32(16)] << np.uint32(8))
 
 
+_BLOCK_BITS = 8   # Z order in blocks of 256 x 256 cells
+
+
+def _block_pattern():
+    """Z order inside one 256 x 256 block: the cell (i, j) of every code."""
+    code = np.arange(1 << (2 * _BLOCK_BITS), dtype=np.uint32)
+    return (_compact1by1(code).astype(np.int32),
+            _compact1by1(code >> np.uint32(1)).astype(np.int32))
+
+
 def _morton_cells(g: int, n: int):
-    """The first n cells of a g x g grid in Z (Morton) order, as (i, j)."""
+    """The first n cells of a g x g grid in Z (Morton) order, as (i, j).
+
+    A Z code splits into the code of a 256 x 256 block (high bits) and the
+    code inside the block (low bits), so the order is: blocks in Z order of
+    their block coordinates, each block's cells in the fixed in-block Z
+    order, cells outside the grid dropped."""
     k = max(1, int(math.ceil(math.log2(g))))
     if k > 16:
         raise ValueError("grid side above 65536")
-    total = 1 << (2 * k)
+    side = 1 << _BLOCK_BITS
+    nb = (g + side - 1) // side                      # blocks per axis
+    bcode = np.arange(1 << (2 * max(0, k - _BLOCK_BITS)), dtype=np.uint32)
+    bi, bj = _compact1by1(bcode), _compact1by1(bcode >> np.uint32(1))
+    keep = (bi < nb) & (bj < nb)
+    bi, bj = bi[keep].astype(np.int64), bj[keep].astype(np.int64)
+    pi, pj = _block_pattern()
     out_i, out_j, have = [], [], 0
-    step = 1 << 24
-    for start in range(0, total, step):
-        code = np.arange(start, min(total, start + step), dtype=np.uint32)
-        i = _compact1by1(code)
-        j = _compact1by1(code >> np.uint32(1))
-        keep = (i < g) & (j < g)
-        i, j = i[keep].astype(np.int64), j[keep].astype(np.int64)
+    step = max(1, (1 << 26) // pi.size)              # blocks per piece
+    for b0 in range(0, bi.size, step):
+        i = (bi[b0:b0 + step, None] * side + pi[None, :]).ravel()
+        j = (bj[b0:b0 + step, None] * side + pj[None, :]).ravel()
+        inside = (i < g) & (j < g)
+        if not inside.all():
+            i, j = i[inside], j[inside]
         out_i.append(i)
         out_j.append(j)
         have += i.size
@@ -241,27 +304,39 @@ def terrain(n: int, seed: int, extent=1000.0, amplitude=50.0, wavelength=200.0,
     rng = np.random.default_rng([seed, 0x7E77A1])
     g = max(1, int(math.ceil(math.sqrt(n))))
     h = extent / g
-    zg = _height_grid(g, h, seed, extent, amplitude, wavelength, octaves, persistence)
-    ci, cj = _morton_cells(g, n)
+
+    def draws():
+        # the random draws, in their fixed order (one stream), made on a
+        # thread of their own while the grid and the cell order are computed
+        j = [rng.standard_normal(n, dtype=np.float32) for _ in range(3)]
+        return j, [rng.integers(-12, 13, size=n, dtype=np.int16) for _ in range(3)]
+    with ThreadPoolExecutor(1) as ex:
+        pending = ex.submit(draws)
+        zg = _height_grid(g, h, seed, extent, amplitude, wavelength, octaves, persistence)
+        ci, cj = _morton_cells(g, n)
+        (jx, jy, jz), noise = pending.result()
     sig = np.float32(jitter * h)
-    x = ((ci.astype(np.float32) + np.float32(0.5)) * np.float32(h)
-         + rng.standard_normal(n, dtype=np.float32) * sig)
-    y = ((cj.astype(np.float32) + np.float32(0.5)) * np.float32(h)
-         + rng.standard_normal(n, dtype=np.float32) * sig)
-    zc = zg[cj, ci]
-    del zg
-    z = zc + rng.standard_normal(n, dtype=np.float32) * sig
+    x = np.empty(n, np.float32)
+    y = np.empty(n, np.float32)
+    z = np.empty(n, np.float32)
+    rgb = np.empty(n, np.uint32)
     lo, hi = -amplitude, amplitude
-    tn = np.clip((zc.astype(np.float64) - lo) / (hi - lo), 0.0, 1.0)
-    del zc
-    chans = []
-    for ch in range(3):
-        base = np.interp(tn, _RAMP_T, _RAMP_C[:, ch])
-        noise = rng.integers(-12, 13, size=n, dtype=np.int16)
-        chans.append(np.clip(np.rint(base) + noise, 0, 255).astype(np.uint8))
-    del tn
-    c = Cloud(x.astype(np.float32, copy=False), y.astype(np.float32, copy=False),
-              z.astype(np.float32, copy=False), _pack_rgb(*chans), f"terrain{n}")
+    hf = np.float32(h)
+
+    def fill(a, b):
+        x[a:b] = (ci[a:b].astype(np.float32) + np.float32(0.5)) * hf + jx[a:b] * sig
+        y[a:b] = (cj[a:b].astype(np.float32) + np.float32(0.5)) * hf + jy[a:b] * sig
+        zc = zg[cj[a:b], ci[a:b]]
+        z[a:b] = zc + jz[a:b] * sig
+        tn = np.clip((zc.astype(np.float64) - lo) / (hi - lo), 0.0, 1.0)
+        chans = []
+        for ch in range(3):
+            base = np.interp(tn, _RAMP_T, _RAMP_C[:, ch])
+            chans.append(np.clip(np.rint(base) + noise[ch][a:b], 0, 255).astype(np.uint8))
+        rgb[a:b] = _pack_rgb(*chans)
+    _chunked(n, fill)
+    del zg, jx, jy, jz, noise, ci, cj
+    c = Cloud(x, y, z, rgb, f"terrain{n}")
     if order == "shuffled":
         c = shuffle(c, seed)
     return c
@@ -319,14 +394,16 @@ def buildings(count: int, per: int, seed: int, extent=1000.0, rmin=10.0, rmax=40
     r = rng.uniform(rmin, rmax, count)
     ground = terrain_height(cx, cy, seed if terrain_seed is None else terrain_seed,
                             extent=extent, **terrain_kw)
-    parts = []
-    for b in range(count):
+
+    def one(b):   # each sphere from its own seed: built on a thread pool
         s = spheres(per, seed * 1000 + b, count=1, rmin=1.0, rmax=1.0, box=0.0)
         x = (s.x.astype(np.float64) * r[b] + cx[b]).astype(np.float32)
         y = (s.y.astype(np.float64) * r[b] + cy[b]).astype(np.float32)
         z = (s.z.astype(np.float64) * r[b] + ground[b] + 0.5 * r[b]).astype(np.float32)
         o = _morton3_order(x, y, z)
-        parts.append(Cloud(x[o], y[o], z[o], s.rgb[o]))
+        return Cloud(x[o], y[o], z[o], s.rgb[o])
+    with ThreadPoolExecutor(_threads()) as ex:
+        parts = list(ex.map(one, range(count)))
     return concat(parts, f"buildings{count}x{per}")
 
 
@@ -393,3 +470,43 @@ def config3(seed: int = CONFIG_SEEDS[3], n_terrain: int = 250_000_000,
     if order == "shuffled":
         c = shuffle(c, seed)
     return c, [terrain_view(2560, 1440), terrain_view(640, 360)]
+
+
+# --------------------------------------------------------------------------
+# serving workload: resident clouds and request traces
+# --------------------------------------------------------------------------
+
+SERVE_SIZES = [(256, 256), (640, 480), (1280, 720), (1920, 1080), (2560, 1440)]
+SERVE_CLOUDS = [1_000_000, 5_000_000, 20_000_000, 50_000_000, 100_000_000, 150_000_000,
+                200_000_000, 300_000_000]
+
+
+def serve_cloud(i: int, n: int) -> Cloud:
+    """Cloud i of the serving workload: the sphere generator for the first
+    (1M points), the stress generator (terrain plus dense spheres) for a
+    300M-point cloud, terrain otherwise."""
+    if i == 0:
+        return config1(n=n)[0]
+    if n == 300_000_000:
+        return config3()[0]
+    return terrain(n, CONFIG_SEEDS[5] * 10 + i)
+
+
+def request_trace(count: int, rate: float, seed: int, nclouds: int, sizes=SERVE_SIZES):
+    """Poisson arrivals at `rate` per second: a list of (arrival time in s,
+    cloud index, view, mode).  Each request picks a cloud, a resolution, a
+    method (0 atomicMin, 1 splatting) and a random orbit camera uniformly;
+    cloud 0 (the spheres in the unit cube) gets a close orbit of its own."""
+    rng = np.random.default_rng([seed, int(rate)])
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, count))
+    out = []
+    for i in range(count):
+        c = int(rng.integers(0, nclouds))
+        w, h = sizes[int(rng.integers(0, len(sizes)))]
+        if c == 0:
+            v = orbit_views(1, int(rng.integers(1 << 30)), [(w, h)], extent=1.0, rmin=1.5,
+                            rmax=3.0, elev=(-60.0, 60.0), near=0.01, far=10.0)[0]
+        else:
+            v = orbit_views(1, int(rng.integers(1 << 30)), [(w, h)])[0]
+        out.append((float(arrivals[i]), c, v, int(rng.integers(0, 2))))
+    return out
