@@ -58,7 +58,9 @@ extern "C" {
                                 or the eps test could overflow 64 bits    */
 #define RZ_EHIP (-3)         /* a HIP runtime call failed; see
                                 rz_last_hip_error()                       */
-#define RZ_EOVERFLOW (-4)    /* a splat count exceeded its exact range    */
+#define RZ_EOVERFLOW (-4)    /* a splat count exceeded its exact range (the
+                                error of a served request; the asynchronous
+                                calls report it through their status word) */
 #define RZ_EBUDGET (-5)      /* request does not fit the memory budget    */
 #define RZ_ESTATE (-6)       /* object used in the wrong state            */
 
@@ -68,7 +70,9 @@ extern "C" {
 #define RZ_KEEP_KEYS 1u
 
 /* bit set in *status by the splat resolve when a pixel's count exceeded the
-   exactly representable range (see rasterize_hq_splat) */
+   exactly representable range (see rasterize_hq_splat).  Every call that
+   resolves splat sums requires a status word, so that such a result can
+   never pass unnoticed. */
 #define RZ_STATUS_HQ_OVERFLOW 1u
 
 /* ---- depth maps (section 2.1) ----------------------------------------- */
@@ -172,10 +176,14 @@ int rasterize_atomicmin(const rz_points *pts, const rz_view *view,
  *   img      device, width*height uint32: per channel
  *            (2 * sum + count) / (2 * count) (rounded half up), or the
  *            background where count = 0.
- *   status   device uint32 or NULL.  The resolve ORs RZ_STATUS_HQ_OVERFLOW
- *            into it if any pixel's count left the exact range (that pixel's
- *            colour is then unspecified).  It cannot happen when n <= 16843009.
- * Errors: RZ_EINVAL, RZ_EDEPTHRANGE, RZ_EHIP.
+ *   status   device uint32, required unless RZ_KEEP_KEYS (then unused and
+ *            may be NULL).  The resolve ORs RZ_STATUS_HQ_OVERFLOW into it if
+ *            any pixel's count left the exact range (that pixel's colour is
+ *            then unspecified); the caller zeroes it and reads it after the
+ *            stream has reached the call.  It cannot happen when
+ *            n <= 16843009.
+ * Errors: RZ_EINVAL (also status NULL without RZ_KEEP_KEYS),
+ * RZ_EDEPTHRANGE, RZ_EHIP.
  */
 int rasterize_hq_splat(const rz_points *pts, const rz_view *view,
                        const rz_depth_map *depth, const rz_hq_params *hq,
@@ -201,7 +209,7 @@ int rasterize_hq_splat(const rz_points *pts, const rz_view *view,
  *   Limits: ceil(width / 256) * ceil(height / 256) <= 256 (e.g. 4096x4096
  *   or 7680x2160), else RZ_EINVAL; rz_sorted_workspace_bytes returns -1 for
  *   such a screen or a negative size.  Other arguments and errors as for
- *   the one-view calls.
+ *   the one-view calls (status required with hq unless RZ_KEEP_KEYS).
  */
 int64_t rz_sorted_workspace_bytes(int64_t n, int32_t width, int32_t height);
 int rasterize_sorted(const rz_points *pts, const rz_view *view,
@@ -221,8 +229,9 @@ int rasterize_sorted(const rz_points *pts, const rz_view *view,
  *   hq       NULL: depth pass + resolve as rasterize_atomicmin; else the three
  *            passes of rasterize_hq_splat (depth maps 0-2 only).
  *   Other arguments as for rasterize_atomicmin / rasterize_hq_splat (acc and
- *   status are used only with hq).  point_size 1 with an integer depth map
- *   runs the same kernels as those calls.
+ *   status are used only with hq; with hq and without RZ_KEEP_KEYS, status
+ *   is required).  point_size 1 with an integer depth map runs the same
+ *   kernels as those calls.
  * Errors: RZ_EINVAL (also point_size out of range, hq with a float depth
  * encoding), RZ_EDEPTHRANGE, RZ_EHIP.
  */
@@ -238,7 +247,7 @@ int rasterize_points(const rz_points *pts, const rz_view *view,
  *   p < npix, and acc[0 .. 2*npix) = 0 when acc is not NULL.
  * rz_resolve_min: img[p] = fb[p] & 0xffffff, then fb[p] = cleared value.
  * rz_resolve_hq: img from acc as in rasterize_hq_splat, then fb and acc
- *   cleared; status as above (may be NULL).
+ *   cleared; status as above (required).
  * All pointers device; npix >= 0.
  */
 int rz_clear(uint64_t *fb, uint64_t *acc, int64_t npix, uint32_t background,
@@ -330,6 +339,16 @@ int rz_merge_sum(uint64_t *dst, const uint64_t *src, int64_t npix, void *stream)
 #define RZ_CHECK_ESTIMATE_ONLY 1u
 int rz_check_reciprocal(uint32_t first_bits, int64_t count, uint64_t *mismatches, uint32_t flags,
                         void *stream);
+/*
+ * The same reciprocal as the kernels' perspective divide (section 2.1),
+ * applied elementwise: out[i] = 1 / w[i] as the point kernels compute it,
+ * for a host to compare with its own IEEE quotients (the self-check above
+ * compares on the device, against the device's division).  For w <= 0 and
+ * NaN the value is whatever the estimate gives (the kernels cull those
+ * points).  w and out are device arrays of n floats; n >= 0.  Errors:
+ * RZ_EINVAL (n < 0, NULL arrays with n > 0), RZ_EHIP.
+ */
+int rz_reciprocal(const float *w, float *out, int64_t n, void *stream);
 
 /* ---- batched multi-view rendering ------------------------------------ */
 /*
@@ -358,8 +377,10 @@ typedef struct rz_batch_opts {
     int32_t views_per_group;  /* K in 1..8; 0 = 4                              */
     rz_launch launch;         /* launch shape; block == 0 = library default   */
     int32_t use_graph;        /* 1: runs replay one captured hipGraph          */
-    uint32_t *status;         /* device or NULL: RZ_STATUS_HQ_OVERFLOW, as for
-                                 rasterize_hq_splat                            */
+    uint32_t *status;         /* device: RZ_STATUS_HQ_OVERFLOW, as for
+                                 rasterize_hq_splat; required when a view is
+                                 RZ_MODE_HQ (else RZ_EINVAL), may be NULL
+                                 otherwise                                     */
 } rz_batch_opts;
 
 typedef struct rz_batch rz_batch;   /* opaque; owns a small device table and,
@@ -431,11 +452,22 @@ typedef struct rz_request {
     uint32_t flags;          /* 0 or RZ_REQ_INJECT_FAILURE                     */
     uint32_t *img;           /* device, width*height, caller-owned; written by
                                 the time the request is RZ_REQ_DONE            */
+    void *after;             /* hipStream_t or NULL.  Not NULL: the request's
+                                device work starts only after the work the
+                                caller had queued on this stream when it
+                                submitted (an event recorded at submission),
+                                e.g. the fill of img or the upload of the
+                                cloud.  NULL: the caller must have finished
+                                such work (e.g. synchronised) before
+                                submitting.                                    */
 } rz_request;
 
 typedef struct rz_request_status {
     int32_t state;           /* RZ_REQ_*                                      */
-    int32_t error;           /* RZ_OK, or the RZ_E* code of a failed request  */
+    int32_t error;           /* RZ_OK, or the RZ_E* code of a failed request:
+                                RZ_EHIP (launch failed) or RZ_EOVERFLOW (a
+                                splat count left the exact range; the image
+                                was written but some colours are unspecified) */
     uint32_t hq_status;      /* RZ_STATUS_HQ_OVERFLOW bits (RZ_MODE_HQ)        */
     uint32_t stream;         /* stream index the request ran on               */
     double t_submit_us;      /* host steady clock, microseconds since the
@@ -472,8 +504,11 @@ int rz_server_poll(rz_server *s, uint64_t ticket, rz_request_status *st);
    RZ_ESTATE). */
 int rz_server_drain(rz_server *s, double timeout_s);
 int rz_server_get_stats(rz_server *s, rz_server_stats *st);
-/* Drains, stops the scheduler, frees the streams and the budget. */
-int rz_server_destroy(rz_server *s);
+/* Waits up to timeout_s seconds for every submitted request to finish, then
+   stops the scheduler and frees the streams and the budget.  If requests are
+   still queued or running at the timeout it returns RZ_ESTATE and leaves the
+   server running (call again later, or drain first). */
+int rz_server_destroy(rz_server *s, double timeout_s);
 
 /* Name of an RZ_* return code (static string). */
 const char *rz_error_string(int code);

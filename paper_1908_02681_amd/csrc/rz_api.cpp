@@ -227,7 +227,8 @@ int rasterize_hq_splat(const rz_points *pts, const rz_view *view, const rz_depth
     uint32_t num, den;
     if ((rc = check_hq(hq, P, &num, &den)))
         return rc;
-    if (!fb || !acc || (flags & ~RZ_KEEP_KEYS) || (!(flags & RZ_KEEP_KEYS) && !img))
+    if (!fb || !acc || (flags & ~RZ_KEEP_KEYS) ||
+        (!(flags & RZ_KEEP_KEYS) && (!img || !status)))
         return RZ_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const Pts p{pts->x, pts->y, pts->z, pts->rgb, pts->n};
@@ -273,7 +274,7 @@ int rasterize_points(const rz_points *pts, const rz_view *view, const rz_depth_m
     if (hq && (rc = check_hq(hq, P, &num, &den)))
         return rc;
     if (point_size < 1 || point_size > kMaxPointSize || !fb || (hq && !acc) ||
-        (flags & ~RZ_KEEP_KEYS) || (!(flags & RZ_KEEP_KEYS) && !img))
+        (flags & ~RZ_KEEP_KEYS) || (!(flags & RZ_KEEP_KEYS) && (!img || (hq && !status))))
         return RZ_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const Pts p{pts->x, pts->y, pts->z, pts->rgb, pts->n};
@@ -311,7 +312,7 @@ int rz_resolve_min(uint64_t *fb, int64_t npix, uint32_t background, uint32_t *im
 int rz_resolve_hq(uint64_t *fb, uint64_t *acc, int64_t npix, uint32_t background, uint32_t *img,
                   uint32_t *status, void *stream)
 {
-    if (npix < 0 || (npix > 0 && (!fb || !acc || !img)))
+    if (npix < 0 || !status || (npix > 0 && (!fb || !acc || !img)))
         return RZ_EINVAL;
     hipError_t e = launch_resolve_hq(fb, acc, npix, background, img, status, (hipStream_t)stream);
     return e == hipSuccess ? RZ_OK : hip_fail(e);

@@ -435,6 +435,8 @@ int rz_batch_plan(const rz_points *pts, const rz_batch_view *views, int32_t nvie
         blocks += (r.npix + kResolvePix - 1) / kResolvePix;
     }
 
+    if (!accum.empty() && !o.status)   // splat sums are resolved: overflow must be seen
+        return RZ_EINVAL;
     rz_batch *b = new (std::nothrow) rz_batch();
     if (!b)
         return RZ_EINVAL;

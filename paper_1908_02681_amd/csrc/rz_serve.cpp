@@ -5,17 +5,27 @@
 // the head is admitted as soon as its framebuffer memory fits the budget
 // pool and an in-flight slot is free, then its kernels (clear, depth pass,
 // splat accumulate, resolve: the same launchers as the one-view calls) are
-// enqueued on the least loaded of several HIP streams, followed by an
-// asynchronous copy of its splat status into a pinned host slot and an
-// event.  The scheduler polls the events, stamps completion, and returns the
-// memory and the slot, which admits the next requests while others still
-// run.  A dry-run mode replaces the device by a host timer so that
-// admission, budgeting and failure isolation can be tested without a GPU.
+// enqueued on the least loaded of several HIP streams, after a wait for the
+// event recorded at submission on the caller's stream (if it named one), and
+// followed by an asynchronous copy of its splat status into a pinned host
+// slot and a host function that marks the request finished and wakes the
+// scheduler.  The scheduler sleeps until a submission or a completion wakes
+// it, stamps completion, and returns the memory and the slot, which admits
+// the next requests while others still run.  A dry-run mode replaces the
+// device by a host timer so that admission, budgeting and failure isolation
+// can be tested without a GPU.
+//
+// Locks: `mu` guards the queue, the in-flight list, the pool and the
+// tickets, and is held while the scheduler enqueues device work.  `wake_mu`
+// guards only the wake-up counter; it is never held across a HIP call, so
+// the host functions, which run on a HIP runtime thread and take only
+// `wake_mu`, can never wait on a thread that waits on the runtime.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -95,6 +105,7 @@ struct Pool {
 };
 
 struct Req {
+    rz_server *srv = nullptr;
     uint64_t ticket = 0;
     rz_request r;
     Proj P;
@@ -107,7 +118,8 @@ struct Req {
     int32_t slot = -1;         // pinned status slot
     uint32_t hq_status = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
-    hipEvent_t ev = nullptr;
+    hipEvent_t after = nullptr;            // recorded on the caller's stream at submit
+    std::atomic<bool> gpu_done{false};     // set by the host function after the work
 };
 
 }  // namespace
@@ -125,10 +137,12 @@ struct rz_server {
     Pool pool;
     std::vector<hipStream_t> streams;
     std::vector<int32_t> load;
-    std::vector<hipEvent_t> events;
+    std::vector<hipEvent_t> events;       // pool of ordering events
     std::mutex mu;
-    std::condition_variable cv;           // work for the scheduler
-    std::condition_variable idle_cv;      // everything finished
+    std::condition_variable idle_cv;      // everything finished (with mu)
+    std::mutex wake_mu;                   // only the counter below
+    std::condition_variable wake_cv;      // submission, completion or stop
+    uint64_t wake_seq = 0;
     std::deque<Req *> queue;
     std::vector<Req *> inflight;
     std::unordered_map<uint64_t, Req *> tickets;
@@ -143,6 +157,12 @@ struct rz_server {
     {
         return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0)
             .count();
+    }
+    void wake()
+    {
+        std::lock_guard<std::mutex> lk(wake_mu);
+        ++wake_seq;
+        wake_cv.notify_one();   // under the lock: see on_device_done
     }
 };
 
@@ -159,17 +179,38 @@ void finish(rz_server *s, Req *r, int32_t state, int32_t error)
         s->free_slots.push_back(r->slot);
         r->slot = -1;
     }
-    if (r->ev) {
-        s->events.push_back(r->ev);
-        r->ev = nullptr;
+    if (r->after) {
+        s->events.push_back(r->after);
+        r->after = nullptr;
     }
     if (r->stream >= 0)
         s->load[r->stream]--;
     s->pool.release(r->off, r->bytes);
+    // a splat count beyond the exact range of the packed sums leaves some
+    // pixels' colours unspecified: the request fails visibly
+    if (state == RZ_REQ_DONE && r->r.mode == RZ_MODE_HQ &&
+        (r->hq_status & RZ_STATUS_HQ_OVERFLOW)) {
+        r->state = state = RZ_REQ_FAILED;
+        r->error = RZ_EOVERFLOW;
+    }
     if (state == RZ_REQ_DONE)
         s->completed++;
     else
         s->failed++;
+}
+
+// Host function enqueued after a request's device work: runs on a HIP
+// runtime thread once that work has completed.  It takes only wake_mu and
+// notifies under it, so once rz_server_destroy holds wake_mu after the last
+// request finished, no host function touches the server any more.
+void on_device_done(void *p)
+{
+    Req *r = static_cast<Req *>(p);
+    rz_server *s = r->srv;
+    std::lock_guard<std::mutex> lk(s->wake_mu);
+    r->gpu_done.store(true, std::memory_order_release);
+    ++s->wake_seq;
+    s->wake_cv.notify_one();
 }
 
 // Enqueues the request's kernels; returns an RZ_* code.
@@ -181,7 +222,11 @@ int launch(rz_server *s, Req *r)
     uint32_t *status = (uint32_t *)(s->dmem + r->off + r->fb_bytes + r->acc_bytes);
     const Pts &p = s->clouds[r->r.cloud];
     const Tune t = current_tune();
-    hipError_t e = launch_clear(fb, acc, (int64_t)r->npix, r->r.background, st);
+    hipError_t e = hipSuccess;
+    if (r->after)
+        e = hipStreamWaitEvent(st, r->after, 0);
+    if (e == hipSuccess)
+        e = launch_clear(fb, acc, (int64_t)r->npix, r->r.background, st);
     if (e == hipSuccess)
         e = hipMemsetAsync(status, 0, sizeof(uint32_t), st);
     if (e == hipSuccess)
@@ -198,20 +243,9 @@ int launch(rz_server *s, Req *r)
     if (e == hipSuccess)
         e = hipMemcpyAsync(&s->host_status[r->slot], status, sizeof(uint32_t),
                            hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) {
-        if (s->events.empty()) {
-            hipEvent_t ev;
-            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-            if (e == hipSuccess)
-                s->events.push_back(ev);
-        }
-        if (e == hipSuccess) {
-            r->ev = s->events.back();
-            s->events.pop_back();
-            e = hipEventRecord(r->ev, st);
-        }
-    }
-    return e == hipSuccess ? RZ_OK : RZ_EHIP;
+    if (e == hipSuccess)
+        e = hipLaunchHostFunc(st, on_device_done, r);
+    return e == hipSuccess ? RZ_OK : hip_fail(e);
 }
 
 void admit(rz_server *s, Req *r)
@@ -246,51 +280,64 @@ void scheduler(rz_server *s)
 {
     if (!s->o.dry_run)
         (void)hipSetDevice(s->device);
-    std::unique_lock<std::mutex> lk(s->mu);
+    uint64_t seen = 0;
     for (;;) {
-        // completions
-        for (size_t i = 0; i < s->inflight.size();) {
-            Req *r = s->inflight[i];
-            int32_t state = -1, err = RZ_OK;
-            if (s->o.dry_run) {
-                if (s->now_us() >= r->t_admit + s->o.dry_run_us)
-                    state = RZ_REQ_DONE;
-            } else {
-                const hipError_t q = hipEventQuery(r->ev);
-                if (q == hipSuccess) {
-                    state = RZ_REQ_DONE;
-                } else if (q != hipErrorNotReady) {
-                    state = RZ_REQ_FAILED;
-                    err = RZ_EHIP;
+        double next_deadline = -1.0;   // dry run: when the next request ends
+        bool stop = false;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            // completions
+            for (size_t i = 0; i < s->inflight.size();) {
+                Req *r = s->inflight[i];
+                bool done;
+                if (s->o.dry_run) {
+                    const double end = r->t_admit + s->o.dry_run_us;
+                    done = s->now_us() >= end;
+                    if (!done && (next_deadline < 0 || end < next_deadline))
+                        next_deadline = end;
+                } else {
+                    done = r->gpu_done.load(std::memory_order_acquire);
+                }
+                if (done) {
+                    s->inflight[i] = s->inflight.back();
+                    s->inflight.pop_back();
+                    finish(s, r, RZ_REQ_DONE, RZ_OK);
+                } else {
+                    ++i;
                 }
             }
-            if (state >= 0) {
-                s->inflight[i] = s->inflight.back();
-                s->inflight.pop_back();
-                finish(s, r, state, err);
-            } else {
-                ++i;
+            // admissions, in arrival order
+            while (!s->queue.empty() && (int32_t)s->inflight.size() < s->o.max_inflight &&
+                   !s->free_slots.empty()) {
+                Req *r = s->queue.front();
+                if (!s->pool.alloc(r->bytes, &r->off))
+                    break;
+                s->queue.pop_front();
+                admit(s, r);
+                if (s->o.dry_run && r->state == RZ_REQ_RUNNING) {
+                    const double end = r->t_admit + s->o.dry_run_us;
+                    if (next_deadline < 0 || end < next_deadline)
+                        next_deadline = end;
+                }
+            }
+            if (s->inflight.empty() && s->queue.empty()) {
+                s->idle_cv.notify_all();
+                stop = s->stop;
             }
         }
-        // admissions, in arrival order
-        while (!s->queue.empty() && (int32_t)s->inflight.size() < s->o.max_inflight &&
-               !s->free_slots.empty()) {
-            Req *r = s->queue.front();
-            if (!s->pool.alloc(r->bytes, &r->off))
-                break;
-            s->queue.pop_front();
-            admit(s, r);
-        }
-        if (s->inflight.empty() && s->queue.empty()) {
-            s->idle_cv.notify_all();
-            if (s->stop)
-                break;
-            s->cv.wait(lk, [s] { return s->stop || !s->queue.empty(); });
+        if (stop)
+            break;
+        // sleep until a submission, a completion or a dry-run deadline
+        std::unique_lock<std::mutex> wl(s->wake_mu);
+        if (next_deadline >= 0) {
+            const auto until =
+                s->t0 + std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                            std::chrono::duration<double, std::micro>(next_deadline));
+            s->wake_cv.wait_until(wl, until, [&] { return s->wake_seq != seen; });
         } else {
-            lk.unlock();
-            std::this_thread::yield();
-            lk.lock();
+            s->wake_cv.wait(wl, [&] { return s->wake_seq != seen; });
         }
+        seen = s->wake_seq;
     }
 }
 
@@ -413,11 +460,34 @@ int rz_server_submit(rz_server *s, const rz_request *req, uint64_t *ticket)
     Req *r = new (std::nothrow) Req();
     if (!r)
         return RZ_EINVAL;
+    r->srv = s;
     std::unique_lock<std::mutex> lk(s->mu);
     int rc = validate(s, req, r);
     if (rc) {
         delete r;
         return rc;
+    }
+    if (req->after && !s->o.dry_run) {
+        // order the request after the caller's work queued so far on its
+        // stream (e.g. the fill of its image, or the upload of its cloud)
+        hipError_t e = hipSuccess;
+        if (s->events.empty()) {
+            hipEvent_t ev;
+            e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess)
+                s->events.push_back(ev);
+        }
+        if (e == hipSuccess) {
+            r->after = s->events.back();
+            s->events.pop_back();
+            e = hipEventRecord(r->after, (hipStream_t)req->after);
+        }
+        if (e != hipSuccess) {
+            if (r->after)
+                s->events.push_back(r->after);
+            delete r;
+            return hip_fail(e);
+        }
     }
     r->ticket = s->next_ticket++;
     r->t_submit = s->now_us();
@@ -426,7 +496,7 @@ int rz_server_submit(rz_server *s, const rz_request *req, uint64_t *ticket)
     s->submitted++;
     *ticket = r->ticket;
     lk.unlock();
-    s->cv.notify_one();
+    s->wake();
     return RZ_OK;
 }
 
@@ -481,17 +551,27 @@ int rz_server_get_stats(rz_server *s, rz_server_stats *st)
     return RZ_OK;
 }
 
-int rz_server_destroy(rz_server *s)
+int rz_server_destroy(rz_server *s, double timeout_s)
 {
-    if (!s)
+    if (!s || !(timeout_s >= 0.0))
         return RZ_EINVAL;
     {
         std::unique_lock<std::mutex> lk(s->mu);
-        s->idle_cv.wait(lk, [s] { return s->queue.empty() && s->inflight.empty(); });
+        const bool idle = s->idle_cv.wait_for(
+            lk, std::chrono::duration<double>(timeout_s),
+            [s] { return s->queue.empty() && s->inflight.empty(); });
+        if (!idle)
+            return RZ_ESTATE;   // still working: the server stays usable
         s->stop = true;
     }
-    s->cv.notify_all();
+    s->wake();
     s->th.join();
+    // every request has finished, so every host function has set its flag;
+    // wait for the streams (and their host functions) to end, then take
+    // wake_mu once: no host function is inside its critical section after
+    for (hipStream_t st : s->streams)
+        (void)hipStreamSynchronize(st);
+    { std::lock_guard<std::mutex> lk(s->wake_mu); }
     for (auto &kv : s->tickets)
         delete kv.second;
     release_device(s);

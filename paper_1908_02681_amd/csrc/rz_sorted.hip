@@ -650,7 +650,8 @@ int rasterize_sorted(const rz_points *pts, const rz_view *view, const rz_depth_m
     uint32_t num = 1, den = 100;
     if (hq && (rc = check_hq(hq, P, &num, &den)))
         return rc;
-    if (!fb || (hq && !acc) || (flags & ~RZ_KEEP_KEYS) || (!(flags & RZ_KEEP_KEYS) && !img))
+    if (!fb || (hq && !acc) || (flags & ~RZ_KEEP_KEYS) ||
+        (!(flags & RZ_KEEP_KEYS) && (!img || (hq && !status))))
         return RZ_EINVAL;
     const Layout L = layout(pts->n, P.width, P.height);
     if (L.ncoarse > kMaxCoarse)

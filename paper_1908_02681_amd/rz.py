@@ -91,7 +91,7 @@ class rz_server_opts(ctypes.Structure):
 class rz_request(ctypes.Structure):
     _fields_ = [("cloud", c_int32), ("mode", c_int32), ("view", rz_view), ("depth", rz_depth_map),
                 ("hq", rz_hq_params), ("background", c_uint32), ("flags", c_uint32),
-                ("img", c_void_p)]
+                ("img", c_void_p), ("after", c_void_p)]
 
 
 class rz_request_status(ctypes.Structure):
@@ -124,6 +124,7 @@ SIGNATURES = {
     "rz_merge_min": ([c_void_p, c_void_p, c_int64, c_void_p], ctypes.c_int),
     "rz_merge_sum": ([c_void_p, c_void_p, c_int64, c_void_p], ctypes.c_int),
     "rz_check_reciprocal": ([c_uint32, c_int64, c_void_p, c_uint32, c_void_p], ctypes.c_int),
+    "rz_reciprocal": ([c_void_p, c_void_p, c_int64, c_void_p], ctypes.c_int),
     "rz_clear": ([c_void_p, c_void_p, c_int64, c_uint32, c_void_p], ctypes.c_int),
     "rz_hq_accumulate": ([P(rz_points), P(rz_view), P(rz_depth_map), P(rz_hq_params), c_void_p,
                           c_void_p, c_void_p], ctypes.c_int),
@@ -149,7 +150,7 @@ SIGNATURES = {
     "rz_server_poll": ([c_void_p, ctypes.c_uint64, P(rz_request_status)], ctypes.c_int),
     "rz_server_drain": ([c_void_p, c_double], ctypes.c_int),
     "rz_server_get_stats": ([c_void_p, P(rz_server_stats)], ctypes.c_int),
-    "rz_server_destroy": ([c_void_p], ctypes.c_int),
+    "rz_server_destroy": ([c_void_p, c_double], ctypes.c_int),
 }
 
 RZ_REQ_QUEUED, RZ_REQ_RUNNING, RZ_REQ_DONE, RZ_REQ_FAILED = 0, 1, 2, 3
@@ -333,10 +334,14 @@ def resolve_min(fb, npix, background=0, img=None, stream=None):
 
 
 def resolve_hq(fb, acc, npix, background=0, img=None, status=None, stream=None):
+    """Third splatting pass.  status (one int32, zero) receives the overflow
+    bit; one is allocated when None."""
     torch = _torch()
     _require_gpu(fb, acc, img, status)
     if img is None:
         img = torch.empty(int(npix), dtype=torch.int32, device="cuda")
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device="cuda")
     _fits_view(int(npix), fb, acc, img, status)
     _check(load().rz_resolve_hq(_ptr(fb), _ptr(acc), int(npix), int(background) & 0xFFFFFFFF,
                                 _ptr(img), _ptr(status), _stream(stream)), "rz_resolve_hq")
@@ -508,6 +513,19 @@ def check_reciprocal(first_bits=0, count=1 << 32, estimate_only=False, stream=No
     return out
 
 
+def reciprocal(w, out=None, stream=None):
+    """The kernels' 1 / w applied to a float32 device tensor."""
+    torch = _torch()
+    _require_gpu(w, out)
+    if w.dtype != torch.float32 or not w.is_contiguous():
+        raise RzError(RZ_EINVAL, "w must be a contiguous float32 device tensor")
+    if out is None:
+        out = torch.empty_like(w)
+    _fits("out", out, 4 * w.numel())
+    _check(load().rz_reciprocal(_ptr(w), _ptr(out), w.numel(), _stream(stream)), "rz_reciprocal")
+    return out
+
+
 def set_launch(block=64, ppt=16, early_out=1, xcd_remap=0, bin=2):
     """Launch shape of both point passes of the one-view calls."""
     _check(load().rz_set_launch(ctypes.byref(rz_launch(block, ppt, early_out, xcd_remap, bin))),
@@ -594,6 +612,8 @@ class Batch:
             arr[i] = rz_batch_view(view_struct(v), ds, m, rz_hq_params(int(eps[0]), int(eps[1])),
                                    bgs[i] & 0xFFFFFFFF, fb.data_ptr(),
                                    acc.data_ptr() if acc is not None else None, img.data_ptr())
+        if status is None and RZ_MODE_HQ in self.modes:
+            status = torch.zeros(1, dtype=torch.int32, device="cuda")   # overflow bit
         self.status = status
         opts = rz_batch_opts()
         opts.views_per_group = int(views_per_group)
@@ -675,13 +695,22 @@ class Server:
         return cid.value
 
     def submit(self, cloud, view, mode, img=None, depth=None, eps=(1, 100), background=0,
-               inject_failure=False) -> int:
+               inject_failure=False, after="current") -> int:
+        """Queue one request.  after: the stream whose queued work (e.g. the
+        fill of img) the request waits for; "current" = torch's current
+        stream, None = no wait (the caller has synchronised)."""
         _fits("img", img, 4 * _npix(view))
         ds = depth if isinstance(depth, rz_depth_map) else depth_struct(*(depth or (DEPTH_LINEAR, 0.0)))
+        if self.dry_run or after is None:
+            after_p = None
+        elif isinstance(after, str):
+            after_p = _stream(None).value
+        else:
+            after_p = after.cuda_stream
         r = rz_request(int(cloud), int(mode), view_struct(view), ds,
                        rz_hq_params(int(eps[0]), int(eps[1])), int(background) & 0xFFFFFFFF,
                        RZ_REQ_INJECT_FAILURE if inject_failure else 0,
-                       img.data_ptr() if img is not None else None)
+                       img.data_ptr() if img is not None else None, after_p)
         t = ctypes.c_uint64()
         _check(load().rz_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)),
                "rz_server_submit")
@@ -700,9 +729,12 @@ class Server:
         _check(load().rz_server_get_stats(self._h, ctypes.byref(st)), "rz_server_get_stats")
         return {f: getattr(st, f) for f, _ in rz_server_stats._fields_ if f != "pad"}
 
-    def close(self):
+    def close(self, timeout_s=600.0):
+        """Waits up to timeout_s for the submitted requests, then frees the
+        server; RzError(RZ_ESTATE) if requests are still running then (the
+        server stays open)."""
         if getattr(self, "_h", None) and self._h.value:
-            _check(load().rz_server_destroy(self._h), "rz_server_destroy")
+            _check(load().rz_server_destroy(self._h, float(timeout_s)), "rz_server_destroy")
             self._h = c_void_p()
 
     def __del__(self):

@@ -125,6 +125,39 @@ def test_argument_validation(rz):
                              None) == E.RZ_EINVAL
 
 
+def test_splat_resolve_requires_a_status_word(rz):
+    """Every call that resolves splat sums refuses a NULL status word (the
+    only place an overflowed count is reported, section 2.2's sums being
+    packed); with RZ_KEEP_KEYS nothing is resolved and NULL is accepted as
+    far as validation goes (it fails later only on the fake pointers, which
+    these calls never reach)."""
+    lib = rz.load()
+    ps, vs, ds = rz.rz_points(1, 1, 1, 1, 10), rz.view_struct(_View()), rz.depth_struct()
+    hq = rz.rz_hq_params(1, 100)
+    one = ctypes.c_void_p(16)
+    b = ctypes.byref
+    assert lib.rasterize_hq_splat(b(ps), b(vs), b(ds), b(hq), 0, one, one, one, None, 0,
+                                  None) == rz.RZ_EINVAL
+    assert lib.rasterize_points(b(ps), b(vs), b(ds), b(hq), 2, 0, one, one, one, None, 0,
+                                None) == rz.RZ_EINVAL
+    assert lib.rasterize_sorted(b(ps), b(vs), b(ds), b(hq), 0, one, one, one, None, one,
+                                1 << 40, 0, None) == rz.RZ_EINVAL
+    assert lib.rz_resolve_hq(one, one, 4, 0, one, None, None) == rz.RZ_EINVAL
+    assert lib.rz_resolve_hq(one, one, 0, 0, one, None, None) == rz.RZ_EINVAL
+    # the depth-only forms need no status word (they fail here on the
+    # missing image instead, which shows they got past the status check)
+    assert lib.rasterize_points(b(ps), b(vs), b(ds), None, 2, 0, one, None, None, None, 0,
+                                None) == rz.RZ_EINVAL
+    # a batch with a splatting view needs opts.status
+    views = (rz.rz_batch_view * 2)(
+        rz.rz_batch_view(vs, ds, rz.RZ_MODE_ATOMICMIN, hq, 0, 16, None, 48),
+        rz.rz_batch_view(vs, ds, rz.RZ_MODE_HQ, hq, 0, 80, 96, 112))
+    opts = rz.rz_batch_opts()
+    h = ctypes.c_void_p()
+    assert lib.rz_batch_plan(b(ps), views, 2, b(opts), b(h)) == rz.RZ_EINVAL
+    assert not h.value
+
+
 def test_sorted_path_validation(rz):
     """Workspace sizes and the checks made before any launch."""
     lib = rz.load()
@@ -208,6 +241,14 @@ def test_reciprocal_check_validation(rz):
     assert lib.rz_check_reciprocal(0, 16, P(256 + 4), 0, None) == E       # not 8-byte aligned
     assert lib.rz_check_reciprocal(0, 16, P(256), 2, None) == E            # unknown flag
     assert lib.rz_check_reciprocal(0, 0, P(256), rz.RZ_CHECK_ESTIMATE_ONLY, None) == rz.RZ_OK
+
+
+def test_reciprocal_values_validation(rz):
+    lib = rz.load()
+    assert lib.rz_reciprocal(None, None, -1, None) == rz.RZ_EINVAL
+    assert lib.rz_reciprocal(None, ctypes.c_void_p(16), 4, None) == rz.RZ_EINVAL
+    assert lib.rz_reciprocal(ctypes.c_void_p(16), None, 4, None) == rz.RZ_EINVAL
+    assert lib.rz_reciprocal(None, None, 0, None) == rz.RZ_OK
 
 
 def test_launch_shape_validation(rz):

@@ -152,3 +152,32 @@ def test_many_requests_from_threads(rz):
     st = _wait(s, out, timeout=60)
     assert len(set(out)) == 200 and all(x["state"] == rz.RZ_REQ_DONE for x in st)
     s.close()
+
+
+def test_destroy_times_out_while_requests_run(rz):
+    """rz_server_destroy waits at most its timeout: with a request still
+    running it returns RZ_ESTATE and leaves the server usable."""
+    s, cid = _server(rz, 64 << 20, 400_000)
+    t = s.submit(cid, _View(64, 48), 0)
+    t0 = time.perf_counter()
+    with pytest.raises(rz.RzError) as e:
+        s.close(timeout_s=0.05)
+    assert e.value.code == rz.RZ_ESTATE
+    assert time.perf_counter() - t0 < 0.3
+    st = _wait(s, [t])[0]
+    assert st["state"] == rz.RZ_REQ_DONE
+    s.close(timeout_s=5.0)
+
+
+def test_scheduler_sleeps_while_waiting(rz):
+    """The scheduler blocks between events instead of spinning: a second of
+    running requests costs the process far less than a second of CPU time."""
+    s, cid = _server(rz, 64 << 20, 250_000, streams=1, inflight=1)
+    ts = [s.submit(cid, _View(64, 48), 0) for _ in range(4)]
+    c0, w0 = time.process_time(), time.perf_counter()
+    st = _wait(s, ts)
+    cpu, wall = time.process_time() - c0, time.perf_counter() - w0
+    assert all(x["state"] == rz.RZ_REQ_DONE for x in st)
+    assert wall > 0.9
+    assert cpu < 0.25 * wall, (cpu, wall)
+    s.close()
