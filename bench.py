@@ -178,28 +178,9 @@ def bench_batch(a):
     print(json.dumps(out), flush=True)
 
 
-SERVE_SIZES = [(256, 256), (640, 480), (1280, 720), (1920, 1080), (2560, 1440)]
-SERVE_CLOUDS = [1_000_000, 5_000_000, 20_000_000, 50_000_000, 100_000_000, 150_000_000,
-                200_000_000, 300_000_000]
-
-
 def serve_trace(n, rate, seed, nclouds):
-    """Poisson arrivals; each request picks a cloud, a resolution, a method
-    and a random orbit camera uniformly."""
     from paper_1908_02681_amd import gen
-    rng = np.random.default_rng([seed, int(rate)])
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, n))
-    out = []
-    for i in range(n):
-        c = int(rng.integers(0, nclouds))
-        w, h = SERVE_SIZES[int(rng.integers(0, len(SERVE_SIZES)))]
-        if c == 0:
-            v = gen.orbit_views(1, int(rng.integers(1 << 30)), [(w, h)], extent=1.0, rmin=1.5,
-                                rmax=3.0, elev=(-60.0, 60.0), near=0.01, far=10.0)[0]
-        else:
-            v = gen.orbit_views(1, int(rng.integers(1 << 30)), [(w, h)])[0]
-        out.append((float(arrivals[i]), c, v, int(rng.integers(0, 2))))
-    return out
+    return gen.request_trace(n, rate, seed, nclouds)
 
 
 def pct(a, q):
@@ -212,22 +193,22 @@ def bench_serve(a):
     import torch
     from paper_1908_02681_amd import gen, rz
 
-    clouds = SERVE_CLOUDS[:a.serve_clouds]
+    clouds = gen.SERVE_CLOUDS[:a.serve_clouds]
     pts, npts = [], []
     for i, n in enumerate(clouds):
         log(f"[serve] generating cloud {i}: {n} points")
-        c = gen.config1(n=n)[0] if i == 0 else gen.terrain(n, gen.CONFIG_SEEDS[5] * 10 + i)
+        c = gen.serve_cloud(i, n)
         pts.append(rz.Points.from_cloud(c))
-        npts.append(n)
+        npts.append(c.n)
         del c
     torch.cuda.synchronize()
     log(f"[serve] {sum(npts) / 1e6:.0f}M points resident")
     # one reusable output image ring per resolution (requests in flight never share)
     ring = a.serve_ring
     imgs = {sz: [torch.empty(sz[0] * sz[1], dtype=torch.int32, device="cuda") for _ in range(ring)]
-            for sz in SERVE_SIZES}
+            for sz in gen.SERVE_SIZES}
     # plain loop buffers: one fb/acc per resolution
-    fbs = {sz: rz.new_framebuffer(gen.View(np.eye(4), 1, 2, *sz), 0, hq=True) for sz in SERVE_SIZES}
+    fbs = {sz: rz.new_framebuffer(gen.View(np.eye(4), 1, 2, *sz), 0, hq=True) for sz in gen.SERVE_SIZES}
     st_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
 
     def plain_one(c, v, m, img):
@@ -254,7 +235,7 @@ def bench_serve(a):
         srv = rz.Server(a.serve_budget, streams=a.serve_streams)
         ids = [srv.add_cloud(p) for p in pts]
         pending, status = {}, {}
-        slot_owner = {sz: [None] * ring for sz in SERVE_SIZES}
+        slot_owner = {sz: [None] * ring for sz in gen.SERVE_SIZES}
 
         def reap(block=False):
             for t in list(pending):
@@ -349,7 +330,7 @@ def bench_serve(a):
         "dtype": "f32+f64->u64", "data": "synthetic",
         "config": {"workload": f"serving: {len(pts)} resident clouds "
                                f"({', '.join(f'{n // 1_000_000}M' for n in npts)} points), Poisson "
-                               f"arrivals, resolutions {SERVE_SIZES}, methods 50/50, "
+                               f"arrivals, resolutions {gen.SERVE_SIZES}, methods 50/50, "
                                f"framebuffer budget {a.serve_budget >> 20} MiB, "
                                f"{a.serve_streams} streams",
                    "requests_per_rate": a.serve_requests, "plain_capacity_req_s": round(cap, 1)},

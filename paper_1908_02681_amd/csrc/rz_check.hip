@@ -36,6 +36,16 @@ __global__ void __launch_bounds__(kCheckBlock) k_check_recip(uint32_t first, int
         atomicAdd(mismatches, bad);
 }
 
+// The same device function over caller-given values, results to memory, so
+// that a host can compare them with its own IEEE quotients.
+__global__ void __launch_bounds__(kCheckBlock) k_recip_values(const float *__restrict__ w,
+                                                              float *__restrict__ out, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * kCheckBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kCheckBlock + threadIdx.x; i < n; i += stride)
+        out[i] = dev::recip_rn(w[i]);
+}
+
 }  // namespace
 }  // namespace rz
 
@@ -59,6 +69,20 @@ extern "C" int rz_check_reciprocal(uint32_t first_bits, int64_t count, uint64_t 
     else
         hipLaunchKernelGGL(k_check_recip<true>, dim3((uint32_t)blocks), dim3(kCheckBlock), 0,
                            (hipStream_t)stream, first_bits, count, out);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RZ_OK : hip_fail(e);
+}
+
+extern "C" int rz_reciprocal(const float *w, float *out, int64_t n, void *stream)
+{
+    if (n < 0 || (n > 0 && (!w || !out)))
+        return RZ_EINVAL;
+    if (n == 0)
+        return RZ_OK;
+    int64_t blocks = (n + kCheckBlock - 1) / kCheckBlock;
+    blocks = blocks < kCheckMaxBlocks ? blocks : kCheckMaxBlocks;
+    hipLaunchKernelGGL(k_recip_values, dim3((uint32_t)blocks), dim3(kCheckBlock), 0,
+                       (hipStream_t)stream, w, out, n);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RZ_OK : hip_fail(e);
 }

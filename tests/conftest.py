@@ -18,3 +18,11 @@ def oracle():
     from oracle import oracle as o
     o.build()
     return o
+
+
+@pytest.fixture(scope="session")
+def stress_cloud():
+    """The 300M-point stress cloud (Morton order) and its two cameras,
+    generated once per test session."""
+    from paper_1908_02681_amd import gen
+    return gen.config3()

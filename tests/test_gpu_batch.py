@@ -182,20 +182,21 @@ def test_batch_full_size(rz, oracle):
     """The batched multi-view workload at its full size (100M Morton-ordered
     terrain points resident, 64 orbit views at 256x256 to 1920x1080, modes
     drawn 50/50), in the default and in the autotuned launch shapes: every
-    view's image equals its one-view call bit for bit, and the two smallest
-    views (one per method) equal the oracle's whole images."""
+    view's image equals its one-view call bit for bit, and one view of every
+    (method, resolution) pair equals the oracle's whole image."""
     import torch
     sizes = [(256, 256), (640, 480), (1280, 720), (1920, 1080)]
     say("[batch-full] generating 100M terrain points")
     cloud = gen.terrain(100_000_000, gen.CONFIG_SEEDS[4])
     views = gen.orbit_views(64, gen.CONFIG_SEEDS[4], sizes)
     modes = np.random.default_rng([gen.CONFIG_SEEDS[4], 7]).integers(0, 2, 64).tolist()
-    # the smallest view of each method, checked against the oracle
+    # the first view of each (method, resolution), checked against the oracle
     picks = {}
-    for i in sorted(range(64), key=lambda i: views[i].width * views[i].height):
-        picks.setdefault(modes[i], i)
+    for i in range(64):
+        picks.setdefault((modes[i], views[i].width), i)
+    assert len(picks) == 2 * len(sizes)
     want = {}
-    for m, i in picks.items():
+    for (m, _), i in sorted(picks.items()):
         v = views[i]
         say(f"[batch-full] oracle view {i} {v.width}x{v.height} mode {m}")
         if m == 0:

@@ -467,3 +467,91 @@ def test_hq_count_limit(rz, oracle):
             assert st == 0
             assert rz.to_u32(img)[3] == 0xFFFFFF
         del pts
+
+
+def _sparse_sums_equal(rz, acc, want_sums):
+    """The packed device sums against the oracle's exact sums, read back only
+    at the pixels the oracle accepted fragments in; every other pixel of acc
+    must hold zero (its count word is zero exactly when nothing was added)."""
+    import torch
+    nz = np.flatnonzero(want_sums[:, 3])
+    pairs = acc.view(-1, 2)
+    got = rz.unpack_acc(pairs[torch.from_numpy(nz).to("cuda")].reshape(-1))
+    others = int((pairs[:, 1] != 0).sum().item()) - nz.size
+    return np.array_equal(got, want_sums[nz]) and others == 0
+
+
+@pytest.mark.parametrize("offset", [0.0, 3.0e5])
+def test_rounding_edge_sets(rz, oracle, offset):
+    """The point sets on which the fused and the unfused projection readings
+    disagree (500 points within 10^-4 pixel of a pixel corner of a
+    15000 x 12000 screen; the same scene 3·10^5 units from the origin, where
+    the depth row's terms cancel): keys and splat sums of the depth pass,
+    the splat pass and the point-size kernels equal the oracle's, whose
+    rounding is pinned step by step against the IEEE definition."""
+    import torch
+    from tests.edge_scenes import rounding_edge_scene
+    v, x, y, z, rgb = rounding_edge_scene(offset)
+    W, H = v.width, v.height
+    pts = rz.Points.from_numpy(x, y, z, rgb)
+    args = (x, y, z, rgb, v.vp, v.near, v.far, W, H)
+    pix, _ = oracle.fragments(x, y, z, v.vp, v.near, v.far, W, H)
+    assert (pix >= 0).sum() > 300
+    say(f"[edge] offset {offset}: atomicMin")
+    want_k, _ = oracle.render_atomicmin(*args)
+    fb, _ = rz.new_framebuffer(v, 0)
+    rz.rasterize_atomicmin(pts, v, fb=fb, keep_keys=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(rz.to_u64(fb), want_k), "depth pass keys"
+    say(f"[edge] offset {offset}: splatting")
+    hk, hs, _ = oracle.render_hq(*args)
+    assert np.array_equal(hk, want_k)
+    fb, acc = rz.new_framebuffer(v, 0, hq=True)
+    rz.rasterize_hq_splat(pts, v, fb=fb, acc=acc, keep_keys=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(rz.to_u64(fb), hk), "splat depth pass keys"
+    assert _sparse_sums_equal(rz, acc, hs), "splat sums"
+    del hs
+    for k in (1, 2):
+        say(f"[edge] offset {offset}: point size {k}")
+        pk, _ = oracle.render_atomicmin(*args, point_size=k)
+        fb, acc = rz.new_framebuffer(v, 0, hq=True)
+        rz.rasterize_points(pts, v, point_size=k, fb=fb, keep_keys=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(rz.to_u64(fb), pk), f"point size {k} keys"
+        _, phs, _ = oracle.render_hq(*args, point_size=k)
+        rz.clear(fb, None, W * H)
+        rz.rasterize_points(pts, v, hq=True, point_size=k, fb=fb, acc=acc, keep_keys=True)
+        torch.cuda.synchronize()
+        assert _sparse_sums_equal(rz, acc, phs), f"point size {k} sums"
+        del fb, acc, phs
+        torch.cuda.empty_cache()
+
+
+def test_reciprocal_matches_host_quotient(rz):
+    """The kernels' 1 / w copied back and compared with the host's own IEEE
+    single-precision quotient (numpy on the CPU, which does not flush
+    denormals): 4096 random significands in every binade from the
+    denormals to 2^127, plus the patterns at the ends of the estimate's
+    range (2^-126, 2^126) and at the extremes.  Unlike the device self-check
+    above, this does not rely on the device's own division."""
+    import torch
+    say("[parity] reciprocal against the host quotient")
+    rng = np.random.default_rng(21)
+    exps = np.arange(0, 255, dtype=np.uint32)
+    bits = (exps[:, None] << np.uint32(23)) | rng.integers(0, 1 << 23, size=(255, 4096),
+                                                           dtype=np.uint32)
+    edges = np.array([1, 2, 0x007FFFFF, 0x00800000, 0x00800001, 0x3F7FFFFF, 0x3F800000,
+                      0x3F800001, 0x7E7FFFFF, 0x7E800000, 0x7E800001, 0x7F7FFFFF, 0x7F800000],
+                     np.uint32)
+    bits = np.concatenate([bits.ravel(), edges])
+    bits = bits[bits != 0]
+    w = bits.view(np.float32)
+    with np.errstate(divide="ignore", over="ignore", under="ignore"):
+        want = (np.float32(1.0) / w).view(np.uint32)
+    got = rz.reciprocal(torch.from_numpy(w.copy()).to("cuda"))
+    torch.cuda.synchronize()
+    got = rz.to_u32(got)
+    bad = np.flatnonzero(got != want)
+    assert bad.size == 0, [(hex(int(bits[i])), hex(int(got[i])), hex(int(want[i])))
+                           for i in bad[:8]]

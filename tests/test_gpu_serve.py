@@ -117,3 +117,69 @@ def test_failed_request_is_isolated(rz, world, alone):
         else:
             assert x["state"] == rz.RZ_REQ_DONE and np.array_equal(got, want)
     assert stats["failed"] == len(fail)
+
+
+def test_served_splat_overflow_is_an_error(rz):
+    """A pixel with more splat fragments than the packed sums hold exactly
+    (16,843,010 white points in one pixel; section 2.2's sums) fails its
+    request with RZ_EOVERFLOW instead of returning unspecified colours as
+    done; one fragment fewer is served normally."""
+    import torch
+    view = gen.View(np.array([[1.0, 0, 0, 0], [0, 1.0, 0, 0], [0, 0, 0, 0], [0, 0, -1.0, 0]]),
+                    1.0, 100.0, 2, 2)
+    s = rz.Server(64 << 20, streams=2)
+    try:
+        for n, over in ((16_843_009, False), (16_843_010, True)):
+            say(f"[serve] count limit n={n}")
+            pts = rz.Points(torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"),
+                            torch.full((n,), -10.0, device="cuda"),
+                            torch.full((n,), 0xFFFFFF, dtype=torch.int32, device="cuda"))
+            cid = s.add_cloud(pts)
+            img = torch.zeros(4, dtype=torch.int32, device="cuda")
+            t = s.submit(cid, view, rz.RZ_MODE_HQ, img=img)
+            s.drain(60)
+            st = s.poll(t)
+            if over:
+                assert st["state"] == rz.RZ_REQ_FAILED and st["error"] == rz.RZ_EOVERFLOW
+                assert st["hq_status"] & rz.RZ_STATUS_HQ_OVERFLOW
+            else:
+                assert st["state"] == rz.RZ_REQ_DONE and st["error"] == rz.RZ_OK
+                assert rz.to_u32(img)[3] == 0xFFFFFF
+            # the atomicMin method has no sums to overflow
+            t = s.submit(cid, view, rz.RZ_MODE_ATOMICMIN, img=img)
+            s.drain(60)
+            assert s.poll(t)["state"] == rz.RZ_REQ_DONE
+            del pts
+    finally:
+        s.close()
+
+
+def test_requests_wait_for_the_callers_stream(rz, world, alone):
+    """A request submitted right after its inputs were produced on another
+    stream (a fresh copy of the cloud's planes and the fill of the output
+    image, queued behind a long fill) waits for that stream's work: its image
+    equals the one-view call's."""
+    import torch
+    clouds, pts, reqs = world
+    side = torch.cuda.Stream()
+    big = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    s = rz.Server(256 << 20, streams=4)
+    try:
+        outs = []
+        for i in (1, 2, 5):
+            c, v, m, bg = reqs[i]
+            torch.cuda.synchronize()
+            with torch.cuda.stream(side):
+                big.fill_(i)                       # keeps the side stream busy first
+                copy = rz.Points(*(t.clone() for t in (pts[c].x, pts[c].y, pts[c].z, pts[c].rgb)))
+                img = torch.full((v.width * v.height,), -1, dtype=torch.int32, device="cuda")
+            cid = s.add_cloud(copy)
+            t = s.submit(cid, v, m, img=img, background=bg, after=side)
+            outs.append((i, t, img, copy))
+        s.drain(60)
+        for i, t, img, _ in outs:
+            assert s.poll(t)["state"] == rz.RZ_REQ_DONE
+            assert np.array_equal(rz.to_u32(img), alone[i]), f"request {i}"
+    finally:
+        s.close()
+        del big

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 from paper_1908_02681_amd import gen
+from tests.edge_scenes import EDGE_H, EDGE_W, random_scene, rounding_edge_scene
 from tests.exact import ExactCamera, brute_force_min, fragments as exact_fragments
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -194,16 +195,7 @@ def test_behind_camera_and_outside_range_culled(oracle):
 # --------------------------------------------------------------------------
 
 def _random_scene(seed, n, W, H, kind=LINEAR, scale=0.0):
-    rng = np.random.default_rng(seed)
-    v = gen.make_view(rng.uniform(-3, 3, 3) + np.array([0, 0, 6.0]), rng.uniform(-0.5, 0.5, 3),
-                      (0.2, 1.0, 0.1), 55.0, W, H, 0.3, 12.0)
-    pts = rng.uniform(-4, 4, size=(n, 3)).astype(np.float32)
-    # a dense cluster so that pixels receive many candidates
-    pts[: n // 2] = (rng.normal(0, 0.4, size=(n // 2, 3))).astype(np.float32)
-    rgb = rng.integers(0, 1 << 24, size=n, dtype=np.uint32)
-    # a few exact depth ties with different colours
-    pts[n // 2: n // 2 + 20] = pts[n // 2 + 20: n // 2 + 40]
-    return v, pts[:, 0].copy(), pts[:, 1].copy(), pts[:, 2].copy(), rgb
+    return random_scene(seed, n, W, H)
 
 
 def _round_ieee(v: F, p: int, emin: int) -> F:
@@ -277,22 +269,8 @@ def test_projection_rounding_follows_the_fused_reading(oracle, offset):
     or depths, so the comparison tells the two readings apart.  The second
     scene sits 3·10^5 units from the origin (georeferenced coordinates), where
     the terms of the depth row cancel and its rounding decides the 40-bit q."""
-    W, H = 15000, 12000          # half sizes that are not powers of two
-    v, x, y, z, rgb = _random_scene(11, 1500, W, H)
-    # and 500 points unprojected from within 10^-4 pixel of a pixel corner,
-    # where the rounding of the divide and the viewport decides the floor
-    rng = np.random.default_rng(13)
-    corner = rng.integers(1, [W, H], size=(500, 2)) + rng.uniform(-1e-4, 1e-4, (500, 2))
-    ndc = np.column_stack([2 * corner / [W, H] - 1, rng.uniform(-0.9, 0.9, 500), np.ones(500)])
-    world = np.linalg.solve(np.asarray(v.vp, np.float64).reshape(4, 4), ndc.T).T
-    world = (world[:, :3] / world[:, 3:]).astype(np.float32)
-    x, y, z = (np.concatenate([a, world[:, k]]) for k, a in enumerate((x, y, z)))
-    if offset:
-        off = np.array([offset, 0.5 * offset, -0.25 * offset])
-        rng = np.random.default_rng(12)
-        v = gen.make_view(rng.uniform(-3, 3, 3) + np.array([0, 0, 6.0]) + off,
-                          rng.uniform(-0.5, 0.5, 3) + off, (0.2, 1.0, 0.1), 55.0, W, H, 0.3, 12.0)
-        x, y, z = ((a + np.float32(b)).astype(np.float32) for a, b in zip((x, y, z), off))
+    W, H = EDGE_W, EDGE_H
+    v, x, y, z, rgb = rounding_edge_scene(offset)
     o, s, z0 = oracle.depth_constants(v.vp, v.near, v.far, W, H)
     vp = np.asarray(v.vp, np.float64).reshape(16)
     m = [F(float(np.float32(a))) for a in vp]
