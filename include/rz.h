@@ -219,6 +219,31 @@ int rasterize_sorted(const rz_points *pts, const rz_view *view,
                      int64_t workspace_bytes, uint32_t flags, void *stream);
 
 /*
+ * rasterize_sorted without a workspace argument, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * hosts that forbid allocation): the workspace is a static device array of
+ * RZ_NOALLOC_SCRATCH_BYTES per device, held by the library until the process
+ * ends; the call itself allocates nothing (the array's device address is
+ * looked up once per device, on the first call there).  The caller still
+ * passes fb, acc, img and status as for rasterize_sorted, and gets the same
+ * results bit for bit.
+ *   Limit: rz_sorted_workspace_bytes(pts->n, width, height) <=
+ *   RZ_NOALLOC_SCRATCH_BYTES (at 1920x1080 about 3 million points), else
+ *   RZ_EBUDGET before anything is enqueued.
+ *   Every call on one device shares that device's array and leaves it
+ *   holding its own intermediate data: calls that overlap on one device
+ *   (on two streams, or from two threads without ordering) race and give
+ *   undefined results.  Calls on one stream, or ordered by the caller, are
+ *   safe.
+ * Errors: those of rasterize_sorted, RZ_EBUDGET, RZ_EHIP (symbol lookup).
+ */
+#define RZ_NOALLOC_SCRATCH_BYTES (64u << 20)
+int rasterize_sorted_noalloc(const rz_points *pts, const rz_view *view,
+                             const rz_depth_map *depth, const rz_hq_params *hq,
+                             uint32_t background, uint64_t *fb, uint64_t *acc, uint32_t *img,
+                             uint32_t *status, uint32_t flags, void *stream);
+
+/*
  * Points larger than one pixel (the paper relates cost to the number of
  * fragments, section 3), and the depth encodings RZ_DEPTH_GL24 / _F32REV.
  * A point of size k (1 <= k <= 16) is culled by its centre as usual and then

@@ -30,6 +30,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "rz.h"
 #include "rz_device.h"
 #include "rz_internal.h"
@@ -696,4 +698,72 @@ int rasterize_sorted(const rz_points *pts, const rz_view *view, const rz_depth_m
     return e == hipSuccess ? RZ_OK : hip_fail(e);
 }
 
+
 }  // extern "C"
+
+// ---- allocation-free variant -----------------------------------------
+//
+// The workspace of rasterize_sorted_noalloc is a file-scope device array.
+// In host code its name is only a stand-in for the symbol, so its device
+// address is looked up once per device (with that device current) and kept;
+// kernels and every host-side use take that address, never the name.
+namespace rz {
+namespace {
+
+static __device__ __align__(256) unsigned char scratch[RZ_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch` (first call per device: the symbol
+// lookup, under a lock).  Returns hipSuccess and sets *out.
+hipError_t scratch_for_current_device(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        if (!ptr || ((uintptr_t)ptr & 255u))
+            return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+}  // namespace rz
+
+extern "C" int rasterize_sorted_noalloc(const rz_points *pts, const rz_view *view,
+                                        const rz_depth_map *depth, const rz_hq_params *hq,
+                                        uint32_t background, uint64_t *fb, uint64_t *acc,
+                                        uint32_t *img, uint32_t *status, uint32_t flags,
+                                        void *stream)
+{
+    // the size checks of rasterize_sorted first, so that a call too large
+    // for the scratch is refused before the symbol lookup
+    if (!view || !pts)
+        return RZ_EINVAL;
+    const int64_t need = rz_sorted_workspace_bytes(pts->n, view->width, view->height);
+    if (need < 0 || pts->n < 0)
+        return RZ_EINVAL;
+    if (need > (int64_t)RZ_NOALLOC_SCRATCH_BYTES)
+        return RZ_EBUDGET;
+    void *ws = nullptr;
+    if (pts->n > 0) {
+        const hipError_t e = rz::scratch_for_current_device(&ws);
+        if (e != hipSuccess)
+            return rz::hip_fail(e);
+    }
+    return rasterize_sorted(pts, view, depth, hq, background, fb, acc, img, status, ws,
+                            (int64_t)RZ_NOALLOC_SCRATCH_BYTES, flags, stream);
+}

@@ -26,6 +26,7 @@ RZ_ESTATE = -6
 RZ_KEEP_KEYS = 1
 RZ_STATUS_HQ_OVERFLOW = 1
 RZ_CHECK_ESTIMATE_ONLY = 1
+RZ_NOALLOC_SCRATCH_BYTES = 64 << 20
 DEPTH_LINEAR = 0
 DEPTH_SCALE = 1
 DEPTH_PIECEWISE = 2
@@ -118,6 +119,9 @@ SIGNATURES = {
     "rasterize_sorted": ([P(rz_points), P(rz_view), P(rz_depth_map), P(rz_hq_params), c_uint32,
                           c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_uint32,
                           c_void_p], ctypes.c_int),
+    "rasterize_sorted_noalloc": ([P(rz_points), P(rz_view), P(rz_depth_map), P(rz_hq_params),
+                                  c_uint32, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32,
+                                  c_void_p], ctypes.c_int),
     "rasterize_points": ([P(rz_points), P(rz_view), P(rz_depth_map), P(rz_hq_params), c_int32,
                           c_uint32, c_void_p, c_void_p, c_void_p, c_void_p, c_uint32, c_void_p],
                          ctypes.c_int),
@@ -478,6 +482,28 @@ def rasterize_sorted(points: Points, view, depth=None, hq=False, eps=(1, 100), b
                                  workspace.numel() * workspace.element_size(),
                                  RZ_KEEP_KEYS if keep_keys else 0, _stream(stream))
     _check(rc, "rasterize_sorted")
+    return fb, (acc if hq else None), (None if keep_keys else img), (status if hq else None)
+
+
+def rasterize_sorted_noalloc(points: Points, view, fb, img, depth=None, hq=False, eps=(1, 100),
+                             background=0, acc=None, status=None, keep_keys=False, stream=None):
+    """rasterize_sorted with the library's static device scratch in place of
+    a workspace: the C call allocates nothing.  The caller passes every
+    buffer (fb cleared; with hq also acc zeroed and a zeroed status word).
+    Calls that overlap on one device race on the shared scratch."""
+    _require_gpu(points.x, fb, acc, img, status)
+    _fits_view(_npix(view), fb, acc if hq else None, None if keep_keys else img,
+               status if hq else None)
+    ps, vs = points.struct(), view_struct(view)
+    ds = depth if isinstance(depth, rz_depth_map) else depth_struct(*(depth or (DEPTH_LINEAR, 0.0)))
+    hp = ctypes.byref(rz_hq_params(int(eps[0]), int(eps[1]))) if hq else None
+    rc = load().rasterize_sorted_noalloc(ctypes.byref(ps), ctypes.byref(vs), ctypes.byref(ds), hp,
+                                         int(background) & 0xFFFFFFFF, _ptr(fb),
+                                         _ptr(acc) if hq else None,
+                                         None if keep_keys else _ptr(img),
+                                         _ptr(status) if hq else None,
+                                         RZ_KEEP_KEYS if keep_keys else 0, _stream(stream))
+    _check(rc, "rasterize_sorted_noalloc")
     return fb, (acc if hq else None), (None if keep_keys else img), (status if hq else None)
 
 

@@ -243,6 +243,25 @@ def test_reciprocal_check_validation(rz):
     assert lib.rz_check_reciprocal(0, 0, P(256), rz.RZ_CHECK_ESTIMATE_ONLY, None) == rz.RZ_OK
 
 
+def test_noalloc_sorted_validation(rz):
+    """The allocation-free sorted call refuses, before any device call, a
+    cloud whose workspace would not fit its static scratch, and bad sizes."""
+    lib = rz.load()
+    b = ctypes.byref
+    vs, ds = rz.view_struct(_View(w=1920, h=1080)), rz.depth_struct()
+    one = ctypes.c_void_p(16)
+    big = rz.rz_points(16, 16, 16, 16, 10_000_000)
+    assert rz.sorted_workspace_bytes(big.n, 1920, 1080) > rz.RZ_NOALLOC_SCRATCH_BYTES
+    assert lib.rasterize_sorted_noalloc(b(big), b(vs), b(ds), None, 0, one, None, one, None, 0,
+                                        None) == rz.RZ_EBUDGET
+    assert lib.rasterize_sorted_noalloc(None, b(vs), b(ds), None, 0, one, None, one, None, 0,
+                                        None) == rz.RZ_EINVAL
+    huge = rz.view_struct(_View(w=20000, h=20000))    # too many screen buckets
+    small = rz.rz_points(16, 16, 16, 16, 10)
+    assert lib.rasterize_sorted_noalloc(b(small), b(huge), b(ds), None, 0, one, None, one, None,
+                                        0, None) == rz.RZ_EINVAL
+
+
 def test_reciprocal_values_validation(rz):
     lib = rz.load()
     assert lib.rz_reciprocal(None, None, -1, None) == rz.RZ_EINVAL
