@@ -252,12 +252,15 @@ __device__ __forceinline__ double depth_of(const Proj &P, float x, float y, floa
 // of the depth when no lane of the wave is on screen.
 // tq: q as a double for the linear and scale maps (meaningless for the
 // piecewise map).
+// vis: the point is on screen (w > 0, inside the framebuffer), whatever its
+// depth.
 template <bool PW>
 __device__ __forceinline__ bool fragment(const Proj &P, const Trans &T, float x, float y, float z,
-                                         uint32_t &px, uint32_t &py, uint64_t &q, double &tq)
+                                         uint32_t &px, uint32_t &py, uint64_t &q, double &tq,
+                                         bool &vis)
 {
     float cw, iw;
-    const bool vis = project(P, T, x, y, z, px, py, cw, iw);
+    vis = project(P, T, x, y, z, px, py, cw, iw);
     q = 0;
     tq = 0.0;
     if (!wave_any(vis))
@@ -271,6 +274,14 @@ __device__ __forceinline__ bool fragment(const Proj &P, const Trans &T, float x,
         q = piecewise_q(P, in_range ? d : P.near_);
     }
     return vis && in_range;
+}
+
+template <bool PW>
+__device__ __forceinline__ bool fragment(const Proj &P, const Trans &T, float x, float y, float z,
+                                         uint32_t &px, uint32_t &py, uint64_t &q, double &tq)
+{
+    bool vis;
+    return fragment<PW>(P, T, x, y, z, px, py, q, tq, vis);
 }
 
 template <bool PW>

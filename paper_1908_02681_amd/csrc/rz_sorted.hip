@@ -1,32 +1,31 @@
 // Screen-sorted rendering (declared in include/rz.h): the same depth pass
 // (section 2.1) and splat accumulation (section 2.2) for clouds in no
 // particular order, where one global atomic per fragment would hit random
-// framebuffer lines.  The fragments are first sorted by 32x32 screen tile in
-// two scatter levels, every write of the sort part of a run:
-//   A   k_sort_count   per workgroup range of points: fragments per tile
-//                      (LDS histogram, added to the totals) and per coarse
-//                      bucket (256x256 px)
-//   B   k_sort_prefix  per coarse bucket: each workgroup's offset (prefix
-//                      over workgroups)
-//       k_sort_scan    bucket starts and the work lists of C2, D and E
-//   C1  k_sort_coarse  the fragments again; each workgroup appends to its
-//                      own run of every coarse bucket through LDS cursors:
-//                      key + pixel in bucket
-//   C2  k_sort_fine    per chunk of 8192 entries of a coarse bucket: ranked
-//                      by tile in LDS, one global atomic per tile reserves
-//                      the chunk's run in the tile bucket: key + pixel in
-//                      tile
-//   D   k_sort_raster  per chunk of a tile bucket: LDS minimum, then one
-//                      coalesced global atomic per touched pixel
-//   E   k_sort_accum   per chunk of a tile bucket: eps window against the
-//                      finished depth pass, LDS sums, one flush per pixel
-// Only C2 places entries with global atomics, one per (chunk, tile).  Tiles
-// are numbered coarse bucket first ("slots"): slot = coarse * 64 + 8 * (tile
-// row in bucket) + (tile column in bucket), so a coarse bucket is the
-// contiguous union of its 64 tile buckets; inside a coarse bucket the runs
-// of A's workgroups follow in workgroup order.  Every reduction is a minimum or an
-// integer sum, so the result is the oracle's bit for bit whatever order the
-// fragments land in.
+// framebuffer lines.  The fragments are sorted once, by bucket (a 64x64
+// screen tile), and each bucket is then reduced in LDS:
+//   A  k_sort_count    per workgroup range of points: on-screen points per
+//                      bucket, from the single-precision projection alone
+//                      (LDS histogram); one row of counts per workgroup
+//   B  k_sort_prefix   per bucket: each workgroup's offset (prefix over
+//                      workgroups) and the bucket's total
+//      k_sort_scan     bucket starts and the chunk work list of D and E
+//   C  k_sort_scatter  the same ranges again, with the whole fragment (depth
+//                      in double precision).  Per step of 4096 points the
+//                      workgroup sorts its entries by bucket in LDS (a
+//                      counting sort), then writes each bucket's run at its
+//                      own cursor in that bucket: consecutive lanes write
+//                      consecutive entries.  Entry = key (u64) + pixel in
+//                      the tile (u16).  (8192 points per step)
+//   D  k_sort_raster   per chunk of a bucket: LDS minimum over the tile, then
+//                      one coalesced early-out atomic per touched pixel
+//   E  k_sort_accum    per chunk: the tile's nearest depths staged in LDS,
+//                      the eps window, LDS sums, one flush per pixel
+// A point that is on screen but outside [near, far) still takes its place
+// (A counts it without the double-precision depth), with the key ~0: it
+// never lowers a minimum, D never flushes a tile entry that only it
+// reached, and E skips it.  Every reduction is a minimum or an integer sum,
+// so the result is the oracle's bit for bit whatever order the fragments
+// land in.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -47,162 +46,143 @@ namespace {
 
 using namespace dev;
 
-constexpr int kTileShift = 5;                 // 32 x 32 pixel tiles
-constexpr int kTilePix = 1 << (2 * kTileShift);
-constexpr int kCoarseShift = 3;               // 8 x 8 tiles per coarse bucket
-constexpr int kSlotsPerCoarse = 1 << (2 * kCoarseShift);
-constexpr int kMaxCoarse = 256;
-constexpr int kMaxSlots = kMaxCoarse * kSlotsPerCoarse;   // pass A histogram: 64 KiB
-constexpr int kGroups = 512;                  // workgroups of passes A and C1 (<= 1024)
-constexpr int kSortBlock = 1024;
-constexpr int kSortPpt = 8;                   // 8192 points per workgroup step
-constexpr int kStep = kSortBlock * kSortPpt;
-constexpr uint32_t kChunk = 8192;             // bucket entries per work item (C2, D, E)
-constexpr int kUnroll = 4;                    // bucket entries in flight per thread (D, E)
+constexpr int kTileShift = 6;                 // buckets are 64 x 64 pixel tiles
+constexpr int kTileSide = 1 << kTileShift;
+constexpr int kTilePix = kTileSide * kTileSide;
+constexpr int kMaxBuckets = 4096;             // A's histogram and C's offsets: 16 KiB
+constexpr int kGroups = 512;                  // workgroups of passes A and C (<= 1024)
+constexpr int kCountBlock = 1024;             // pass A: 8192 points per step
+constexpr int kCountPpt = 8;
+constexpr int kCountStep = kCountBlock * kCountPpt;
+constexpr int kScBlock = 1024;                // pass C: 8192 points per step
+constexpr int kScPpt = 8;
+constexpr int kScStep = kScBlock * kScPpt;
+constexpr int kScBuckets = kMaxBuckets / kScBlock;   // buckets per thread in C's scan
+constexpr int kRasterBlock = 256;
+constexpr int kAccumBlock = 1024;
+constexpr int kUnroll = 8;                    // bucket entries in flight per thread (D, E)
 constexpr int kPrefixCols = 32;               // pass B: columns per workgroup
 constexpr int kPrefixSegs = 32;               // pass B: workgroup segments per column
+constexpr int kScanThreads = 1024;
+static_assert(kCountStep % kScStep == 0, "A's ranges are whole steps of C");
+static_assert(kMaxBuckets % kScBlock == 0 && kMaxBuckets % kScanThreads == 0, "scan shapes");
+static_assert(kMaxBuckets <= 4096 && kTilePix <= 4096, "bucket and pixel fit 12 bits each");
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 struct Layout {
-    int32_t ntx = 0, nty = 0, ccols = 0, crows = 0, ncoarse = 0, nslots = 0, groups = 0;
+    int32_t ntx = 0, nty = 0, nb = 0, groups = 0;
     int64_t per_wg = 0;
-    int64_t cchunks_max = 0, fchunks_max = 0;   // bounds on the work lists
-    size_t ccounts = 0, total = 0, ctotal = 0, fstart = 0, fchunk = 0;
-    size_t fcursor = 0, cchunk = 0;
-    size_t xkeys = 0, xlpc = 0, ykeys = 0, ylps = 0, bytes = 0;
+    uint32_t chunk = 0;          // bucket entries per work item of D and E
+    int64_t chunks_max = 0;      // bound on the work items
+    size_t ccounts = 0, btotal = 0, bstart = 0, bchunk = 0, keys = 0, lps = 0, bytes = 0;
 };
 
 Layout layout(int64_t n, int32_t w, int32_t h)
 {
     Layout L;
-    L.ntx = (w + (1 << kTileShift) - 1) >> kTileShift;
-    L.nty = (h + (1 << kTileShift) - 1) >> kTileShift;
-    L.ccols = (L.ntx + (1 << kCoarseShift) - 1) >> kCoarseShift;
-    L.crows = (L.nty + (1 << kCoarseShift) - 1) >> kCoarseShift;
-    L.ncoarse = L.ccols * L.crows;
-    L.nslots = L.ncoarse * kSlotsPerCoarse;
+    L.ntx = (w + kTileSide - 1) >> kTileShift;
+    L.nty = (h + kTileSide - 1) >> kTileShift;
+    L.nb = L.ntx * L.nty;
     if (n > 0) {
         const int64_t want = (n + kGroups - 1) / kGroups;
-        L.per_wg = (want + kStep - 1) / kStep * kStep;
+        L.per_wg = (want + kCountStep - 1) / kCountStep * kCountStep;
         L.groups = (int32_t)((n + L.per_wg - 1) / L.per_wg);
     }
-    // sum over buckets of ceil(count / kChunk) <= n / kChunk + buckets
-    L.cchunks_max = (n + kChunk - 1) / kChunk + L.ncoarse;
-    L.fchunks_max = (n + kChunk - 1) / kChunk + L.nslots;
+    // about 512 work items, at least 131072 entries each: a chunk's flush of
+    // up to 4096 pixels (two global atomics each in the splat pass) stays
+    // small beside its entries
+    const int64_t c = ((n + 511) / 512 + 1023) / 1024 * 1024;
+    L.chunk = (uint32_t)(c > 131072 ? c : 131072);
+    // sum over buckets of ceil(count / chunk) <= n / chunk + buckets
+    L.chunks_max = (n + L.chunk - 1) / L.chunk + L.nb;
     size_t o = 0;
     auto take = [&o](size_t bytes) {
         const size_t at = o;
         o = align256(o + bytes);
         return at;
     };
-    L.ccounts = take((size_t)L.groups * L.ncoarse * 4);
-    L.total = take((size_t)L.nslots * 4);
-    L.ctotal = take((size_t)L.ncoarse * 4);
-    L.fstart = take(((size_t)L.nslots + 1) * 4);
-    L.fchunk = take(((size_t)L.nslots + 1) * 4);
-    L.fcursor = take((size_t)L.nslots * 4);
-    L.cchunk = take(((size_t)L.ncoarse + 1) * 4);
-    L.xkeys = take((size_t)n * 8);
-    L.xlpc = take((size_t)n * 2);
-    L.ykeys = take((size_t)n * 8);
-    L.ylps = take((size_t)n * 2);
+    L.ccounts = take((size_t)L.groups * L.nb * 4);
+    L.btotal = take((size_t)L.nb * 4);
+    L.bstart = take(((size_t)L.nb + 1) * 4);
+    L.bchunk = take(((size_t)L.nb + 1) * 4);
+    L.keys = take((size_t)n * 8);
+    L.lps = take((size_t)n * 2);
     L.bytes = o;
     return L;
 }
 
-// Slot of the tile holding pixel (px, py).
-__device__ __forceinline__ uint32_t slot_of(uint32_t px, uint32_t py, int32_t ccols)
+// Bucket and pixel-in-tile of an on-screen pixel, packed: bucket << 12 | pixel.
+__device__ __forceinline__ uint32_t bucket_pixel(uint32_t px, uint32_t py, int32_t ntx)
 {
-    const uint32_t tx = px >> kTileShift, ty = py >> kTileShift;
-    const uint32_t c = (ty >> kCoarseShift) * (uint32_t)ccols + (tx >> kCoarseShift);
-    return (c << (2 * kCoarseShift)) | ((ty & 7u) << kCoarseShift) | (tx & 7u);
+    const uint32_t b = __umul24(py >> kTileShift, (uint32_t)ntx) + (px >> kTileShift);
+    return (b << 12) | ((py & (kTileSide - 1)) << kTileShift) | (px & (kTileSide - 1));
 }
 
-// First pixel of the tile of a slot.
-__device__ __forceinline__ void slot_origin(uint32_t slot, int32_t ccols, uint32_t &x0,
-                                            uint32_t &y0)
-{
-    const uint32_t c = slot >> (2 * kCoarseShift), f = slot & (kSlotsPerCoarse - 1);
-    const uint32_t tx = (c % (uint32_t)ccols) * 8u + (f & 7u);
-    const uint32_t ty = (c / (uint32_t)ccols) * 8u + (f >> kCoarseShift);
-    x0 = tx << kTileShift;
-    y0 = ty << kTileShift;
-}
-
-// Adds this lane's entry to the LDS counter hist[bin] and returns the
-// counter before it (the entry's rank among the workgroup's entries of that
-// bin).  A wave whose live lanes share one bin makes a single atomic.  Every
-// lane of the wave must call it.
-__device__ __forceinline__ uint32_t lds_rank(uint32_t *hist, uint32_t bin, bool live)
+// Adds one to hist[bin] for every live lane; a wave whose live lanes share
+// one bin makes a single atomic.  Every lane of the wave must call it.
+__device__ __forceinline__ void lds_count(uint32_t *hist, uint32_t bin, bool live)
 {
     const uint64_t m = __ballot(live);
     if (m == 0)
-        return 0u;
-    const uint32_t below =
-        __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        return;
     const int leader = __builtin_ctzll(m);
     const uint32_t b0 = __shfl(bin, leader);
     if (__all(!live || bin == b0)) {
-        uint32_t base = 0;
-        if (live && below == 0)
-            base = atomicAdd(&hist[b0], (uint32_t)__popcll(m));
-        return __shfl(base, leader) + below;
+        if ((int)(threadIdx.x & 63u) == leader)
+            atomicAdd(&hist[b0], (uint32_t)__popcll(m));
+        return;
     }
-    return live ? atomicAdd(&hist[bin], 1u) : 0u;
+    if (live)
+        atomicAdd(&hist[bin], 1u);
 }
 
-// Pass A: fragments per tile (added to total[], zero on entry) and per
-// coarse bucket in this workgroup's contiguous range of points
-// (ccounts[g][coarse]).
-template <bool VEC, bool PW>
-__global__ void __launch_bounds__(kSortBlock) k_sort_count(Pts p, Proj P, uint32_t *total,
-                                                           uint32_t *ccounts, int32_t ccols,
-                                                           int32_t nslots, int32_t ncoarse,
-                                                           int64_t per_wg)
+// Inclusive prefix sum over the 64 lanes of a wave (all lanes active).
+__device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v)
 {
-    extern __shared__ uint32_t hist[];
-    for (int32_t i = threadIdx.x; i < nslots; i += blockDim.x)
+    const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t t = (uint32_t)__shfl_up((int)v, d);
+        v += lane >= (uint32_t)d ? t : 0u;
+    }
+    return v;
+}
+
+// Pass A: on-screen points per bucket in this workgroup's contiguous range
+// of points, written as row blockIdx.x of ccounts ([groups][nb]).
+template <bool VEC>
+__global__ void __launch_bounds__(kCountBlock) k_sort_count(Pts p, Proj P, uint32_t *ccounts,
+                                                            int32_t ntx, int32_t nb,
+                                                            int64_t per_wg)
+{
+    __shared__ uint32_t hist[kMaxBuckets];
+    for (int32_t i = threadIdx.x; i < nb; i += blockDim.x)
         hist[i] = 0u;
     __syncthreads();
     const int64_t lo = (int64_t)blockIdx.x * per_wg;
     Pts q = p;
     q.n = lo + per_wg < p.n ? lo + per_wg : p.n;
-    for (int64_t base = lo; base < q.n; base += kStep) {
-        float x[kSortPpt], y[kSortPpt], z[kSortPpt];
-        uint32_t c[kSortPpt];
-        bool in[kSortPpt];
-        load_points<kSortPpt, VEC>(q, base, x, y, z, c, in);
+    const Trans T = lane_trans(P);
+    for (int64_t base = lo; base < q.n; base += kCountStep) {
+        float x[kCountPpt], y[kCountPpt], z[kCountPpt];
+        uint32_t c[kCountPpt];
+        load_points_nan<kCountPpt, VEC>(q, base, x, y, z, c);   // past the end: NaN, culled
 #pragma unroll
-        for (int j = 0; j < kSortPpt; ++j) {
-            uint32_t px = 0, py = 0;
-            uint64_t qq = 0;
-            const bool live = fragment<PW>(P, x[j], y[j], z[j], px, py, qq) & in[j];
-            lds_rank(hist, live ? slot_of(px, py, ccols) : 0u, live);
+        for (int j = 0; j < kCountPpt; ++j) {
+            uint32_t px, py;
+            float cw, iw;
+            const bool vis = project(P, T, x[j], y[j], z[j], px, py, cw, iw);
+            lds_count(hist, bucket_pixel(px, py, ntx) >> 12, vis);
         }
     }
     __syncthreads();
-    for (int32_t i = threadIdx.x; i < nslots; i += blockDim.x) {
-        const uint32_t v = hist[i];
-        if (v)
-            atomicAdd(&total[i], v);
-    }
-    if ((int32_t)threadIdx.x < ncoarse) {
-        uint32_t sum = 0;
-        for (int k = 0; k < kSlotsPerCoarse; ++k)
-            sum += hist[threadIdx.x * kSlotsPerCoarse + k];
-        ccounts[(int64_t)blockIdx.x * ncoarse + threadIdx.x] = sum;
-    }
+    uint32_t *row = ccounts + (int64_t)blockIdx.x * nb;
+    for (int32_t i = threadIdx.x; i < nb; i += blockDim.x)
+        row[i] = hist[i];
 }
 
-__global__ void k_sort_zero(uint32_t *p, int32_t n)
-{
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n)
-        p[i] = 0u;
-}
-
-// Pass B, first part: for every column of the [groups][coarse] count matrix,
+// Pass B, first part: for every column of the [groups][nb] count matrix,
 // the exclusive prefix over groups (in place) and the column total.  A
 // workgroup takes kPrefixCols columns; each of its kPrefixSegs segments sums
 // a run of up to kPrefixSegs groups, the segment sums are scanned in LDS, and
@@ -246,34 +226,29 @@ __global__ void __launch_bounds__(kPrefixCols * kPrefixSegs)
     }
 }
 
-// Pass B, second part: one workgroup of 1024 threads, 16 slots each
-// (nslots <= 16384).
-//   fstart  exclusive scan of the tile totals (tile bucket starts), and
-//           fstart[nslots] = all fragments; fcursor = fstart;
-//   fchunk  exclusive scan of ceil(total / kChunk): work items of D and E;
-//   cchunk  exclusive scan of ceil(coarse total / kChunk): work items of C2.
-__global__ void __launch_bounds__(1024) k_sort_scan(const uint32_t *total, uint32_t *fstart,
-                                                    uint32_t *fchunk, uint32_t *fcursor,
-                                                    uint32_t *cchunk, int32_t nslots,
-                                                    int32_t ncoarse)
+// Pass B, second part: one workgroup, 4 buckets per thread.
+//   bstart  exclusive scan of the bucket totals; bstart[nb] = all entries;
+//   bchunk  exclusive scan of ceil(total / chunk): the work items of D and E;
+//           bchunk[nb] = all work items.
+__global__ void __launch_bounds__(kScanThreads) k_sort_scan(const uint32_t *total,
+                                                            uint32_t *bstart, uint32_t *bchunk,
+                                                            int32_t nb, uint32_t chunk)
 {
-    constexpr int K = kMaxSlots / 1024;
-    static_assert(kSlotsPerCoarse % K == 0, "a coarse bucket spans whole threads");
-    constexpr int kThreadsPerCoarse = kSlotsPerCoarse / K;
-    __shared__ uint32_t s_sum[1024], s_ch[1024];
+    constexpr int K = kMaxBuckets / kScanThreads;
+    __shared__ uint32_t s_sum[kScanThreads], s_ch[kScanThreads];
     const int32_t t0 = threadIdx.x * K;
     uint32_t v[K];
     uint32_t local = 0, lch = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        v[k] = t0 + k < nslots ? total[t0 + k] : 0u;
+        v[k] = t0 + k < nb ? total[t0 + k] : 0u;
         local += v[k];
-        lch += (v[k] + kChunk - 1) / kChunk;
+        lch += (v[k] + chunk - 1) / chunk;
     }
     s_sum[threadIdx.x] = local;
     s_ch[threadIdx.x] = lch;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {   // inclusive scans (Hillis-Steele)
+    for (int off = 1; off < kScanThreads; off <<= 1) {   // inclusive scans (Hillis-Steele)
         const bool has = threadIdx.x >= (uint32_t)off;
         const uint32_t add = has ? s_sum[threadIdx.x - off] : 0u;
         const uint32_t addc = has ? s_ch[threadIdx.x - off] : 0u;
@@ -285,79 +260,129 @@ __global__ void __launch_bounds__(1024) k_sort_scan(const uint32_t *total, uint3
     uint32_t run = s_sum[threadIdx.x] - local, runc = s_ch[threadIdx.x] - lch;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        if (t0 + k < nslots) {
-            fstart[t0 + k] = run;
-            fcursor[t0 + k] = run;
-            fchunk[t0 + k] = runc;
+        if (t0 + k < nb) {
+            bstart[t0 + k] = run;
+            bchunk[t0 + k] = runc;
         }
         run += v[k];
-        runc += (v[k] + kChunk - 1) / kChunk;
+        runc += (v[k] + chunk - 1) / chunk;
     }
-    if (threadIdx.x == 1023) {
-        fstart[nslots] = s_sum[1023];
-        fchunk[nslots] = s_ch[1023];
+    if (threadIdx.x == kScanThreads - 1) {
+        bstart[nb] = s_sum[kScanThreads - 1];
+        bchunk[nb] = s_ch[kScanThreads - 1];
     }
-    // coarse buckets: s_sum holds the inclusive sums per thread
-    uint32_t cn = 0;
-    if ((int32_t)threadIdx.x < ncoarse) {
-        const int32_t last = kThreadsPerCoarse * threadIdx.x + kThreadsPerCoarse - 1;
-        const uint32_t end = s_sum[last];
-        const uint32_t beg = threadIdx.x ? s_sum[last - kThreadsPerCoarse] : 0u;
-        cn = (end - beg + kChunk - 1) / kChunk;
-    }
-    __syncthreads();
-    s_ch[threadIdx.x] = cn;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t addc = threadIdx.x >= (uint32_t)off ? s_ch[threadIdx.x - off] : 0u;
-        __syncthreads();
-        s_ch[threadIdx.x] += addc;
-        __syncthreads();
-    }
-    if ((int32_t)threadIdx.x < ncoarse)
-        cchunk[threadIdx.x] = s_ch[threadIdx.x] - cn;
-    if (threadIdx.x == 1023)
-        cchunk[ncoarse] = s_ch[1023];
 }
 
-// Pass C1: the fragments of pass A again (same ranges, same arithmetic).
-// Workgroup g owns the run of every coarse bucket that starts at the
-// bucket's start plus g's offset from pass B; LDS cursors hand out its
-// places.
+// Pass C: the fragments of pass A's ranges, sorted into the buckets.
+// cursors holds, per workgroup row, the prefix offsets of pass B.  Thread t
+// owns buckets t * kScBuckets .. t * kScBuckets + kScBuckets - 1 in every
+// per-bucket phase and keeps the workgroup's cursors of those buckets in
+// registers.
 template <bool VEC, bool PW>
-__global__ void __launch_bounds__(kSortBlock) k_sort_coarse(Pts p, Proj P,
-                                                            const uint32_t *__restrict__ coff,
-                                                            const uint32_t *__restrict__ fstart,
-                                                            uint64_t *xkeys, uint16_t *xlpc,
-                                                            int32_t ccols, int32_t ncoarse,
-                                                            int64_t per_wg)
+__global__ void __launch_bounds__(kScBlock) k_sort_scatter(Pts p, Proj P,
+                                                           const uint32_t *__restrict__ cursors,
+                                                           const uint32_t *__restrict__ bstart,
+                                                           uint64_t *__restrict__ keys,
+                                                           uint16_t *__restrict__ lps,
+                                                           int32_t ntx, int32_t nb,
+                                                           int64_t per_wg)
 {
-    __shared__ uint32_t s_cur[kMaxCoarse];
-    const uint64_t end = (uint64_t)p.n;   // bucket arrays hold n entries
-    if ((int32_t)threadIdx.x < ncoarse)
-        s_cur[threadIdx.x] = fstart[threadIdx.x * kSlotsPerCoarse] +
-                             coff[(int64_t)blockIdx.x * ncoarse + threadIdx.x];
-    __syncthreads();
+    __shared__ uint32_t s_off[kMaxBuckets];   // counts, then offsets, then deltas
+    __shared__ uint64_t s_key[kScStep];       // the step's entries sorted by bucket
+    __shared__ uint32_t s_lb[kScStep];        // bucket << 12 | pixel in tile
+    __shared__ uint32_t s_wsum[kScBlock / 64];
+    __shared__ uint32_t s_total;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const int32_t b0 = (int32_t)tid * kScBuckets;
+    const uint32_t *row = cursors + (int64_t)blockIdx.x * nb;
+    uint32_t cur[kScBuckets];   // this workgroup's next place in each of the thread's buckets
+#pragma unroll
+    for (int r = 0; r < kScBuckets; ++r)
+        cur[r] = b0 + r < nb ? row[b0 + r] + bstart[b0 + r] : 0u;
     const int64_t lo = (int64_t)blockIdx.x * per_wg;
     Pts q = p;
     q.n = lo + per_wg < p.n ? lo + per_wg : p.n;
-    for (int64_t base = lo; base < q.n; base += kStep) {
-        float x[kSortPpt], y[kSortPpt], z[kSortPpt];
-        uint32_t c[kSortPpt];
-        bool in[kSortPpt];
-        load_points<kSortPpt, VEC>(q, base, x, y, z, c, in);
+    const Trans T = lane_trans(P);
+    // the points of the first step; each later step's are loaded while the
+    // step before it sorts and writes its entries
+    float x[kScPpt], y[kScPpt], z[kScPpt];
+    uint32_t c[kScPpt];
+    if (lo < q.n)
+        load_points_nan<kScPpt, VEC>(q, lo, x, y, z, c);   // past the end: NaN, culled
+    for (int64_t base = lo; base < q.n; base += kScStep) {
 #pragma unroll
-        for (int j = 0; j < kSortPpt; ++j) {
+        for (int r = 0; r < kScBuckets; ++r)
+            if (b0 + r < nb)
+                s_off[b0 + r] = 0u;
+        uint32_t lb[kScPpt], rank[kScPpt];
+        uint64_t key[kScPpt];
+        bool vis[kScPpt];
+        __syncthreads();   // counters zero (and the previous step's write-out done)
+#pragma unroll
+        for (int j = 0; j < kScPpt; ++j) {
             uint32_t px = 0, py = 0;
             uint64_t qq = 0;
-            const bool live = fragment<PW>(P, x[j], y[j], z[j], px, py, qq) & in[j];
-            const uint32_t cb = live ? slot_of(px, py, ccols) >> (2 * kCoarseShift) : 0u;
-            const uint64_t pos = lds_rank(s_cur, cb, live);
-            if (live && pos < end) {   // pos < end always: A and C1 agree
-                xkeys[pos] = (qq << 24) | ((uint64_t)c[j] & kRgbMask);
-                xlpc[pos] = (uint16_t)(((py & 255u) << 8) | (px & 255u));
+            double tq;
+            bool v = false;
+            const bool live = fragment<PW>(P, T, x[j], y[j], z[j], px, py, qq, tq, v);
+            vis[j] = v;
+            key[j] = live ? (qq << 24) | ((uint64_t)c[j] & kRgbMask) : ~0ull;
+            lb[j] = bucket_pixel(px, py, ntx);
+            rank[j] = v ? atomicAdd(&s_off[lb[j] >> 12], 1u) : 0u;
+        }
+        if (base + kScStep < q.n)   // workgroup-uniform
+            load_points_nan<kScPpt, VEC>(q, base + kScStep, x, y, z, c);
+        __syncthreads();   // counts complete
+        // exclusive scan of the counts over the buckets
+        uint32_t cnt[kScBuckets], off[kScBuckets];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int r = 0; r < kScBuckets; ++r) {
+            cnt[r] = b0 + r < nb ? s_off[b0 + r] : 0u;
+            sum += cnt[r];
+        }
+        const uint32_t incl = wave_inclusive_sum(sum);
+        if (lane == 63u)
+            s_wsum[wave] = incl;
+        __syncthreads();
+        uint32_t run = incl - sum;
+        for (uint32_t w = 0; w < wave; ++w)
+            run += s_wsum[w];
+#pragma unroll
+        for (int r = 0; r < kScBuckets; ++r) {
+            off[r] = run;
+            if (b0 + r < nb)
+                s_off[b0 + r] = run;
+            run += cnt[r];
+        }
+        if (tid == kScBlock - 1)
+            s_total = run;
+        __syncthreads();   // offsets complete
+#pragma unroll
+        for (int j = 0; j < kScPpt; ++j) {
+            if (vis[j]) {
+                const uint32_t i = s_off[lb[j] >> 12] + rank[j];
+                s_key[i] = key[j];
+                s_lb[i] = lb[j];
             }
         }
+        __syncthreads();   // staging complete, offsets read
+        // staging index i of bucket b goes to cursor(b) + (i - off(b))
+#pragma unroll
+        for (int r = 0; r < kScBuckets; ++r) {
+            if (b0 + r < nb)
+                s_off[b0 + r] = cur[r] - off[r];
+            cur[r] += cnt[r];
+        }
+        __syncthreads();   // deltas complete
+        const uint32_t total = s_total;
+        for (uint32_t i = tid; i < total; i += kScBlock) {
+            const uint32_t e = s_lb[i];
+            const uint32_t pos = s_off[e >> 12] + i;
+            keys[pos] = s_key[i];
+            lps[pos] = (uint16_t)(e & 0xFFFu);
+        }
+        __syncthreads();   // staging and deltas free for the next step
     }
 }
 
@@ -375,90 +400,37 @@ __device__ __forceinline__ int32_t find_item(const uint32_t *list, int32_t count
     return a;
 }
 
-// Pass C2: one chunk of a coarse bucket into the bucket's 64 tile buckets,
-// ranked in LDS as in C1.
-__global__ void __launch_bounds__(kSortBlock) k_sort_fine(const uint64_t *__restrict__ xkeys,
-                                                          const uint16_t *__restrict__ xlpc,
-                                                          const uint32_t *__restrict__ fstart,
-                                                          const uint32_t *__restrict__ cchunk,
-                                                          uint32_t *fcursor,
-                                                          uint64_t *__restrict__ ykeys,
-                                                          uint16_t *__restrict__ ylps,
-                                                          int32_t ncoarse, int64_t n)
-{
-    __shared__ uint32_t s_cnt[kSlotsPerCoarse], s_base[kSlotsPerCoarse];
-    const uint32_t b = blockIdx.x;
-    if (b >= cchunk[ncoarse])
-        return;
-    const int32_t cb = find_item(cchunk, ncoarse, b);
-    const uint32_t bucket_end = fstart[(cb + 1) * kSlotsPerCoarse];
-    const uint32_t lo = fstart[cb * kSlotsPerCoarse] + (b - cchunk[cb]) * kChunk;
-    const uint32_t hi = bucket_end - lo > kChunk ? lo + kChunk : bucket_end;
-    if (threadIdx.x < kSlotsPerCoarse)
-        s_cnt[threadIdx.x] = 0u;
-    __syncthreads();
-    constexpr int K = kChunk / kSortBlock;
-    uint64_t key[K];
-    uint32_t f[K], lp[K], rank[K];
-    bool ok[K];
-#pragma unroll
-    for (int u = 0; u < K; ++u) {
-        const uint64_t i = (uint64_t)lo + (uint64_t)u * kSortBlock + threadIdx.x;
-        ok[u] = i < hi;
-        key[u] = ok[u] ? ldnt(xkeys + i) : 0ull;
-        const uint32_t v = ok[u] ? (uint32_t)xlpc[i] : 0u;
-        f[u] = ((v >> 13) << kCoarseShift) | ((v & 255u) >> kTileShift);
-        lp[u] = (((v >> 8) & 31u) << kTileShift) | (v & 31u);
-    }
-#pragma unroll
-    for (int u = 0; u < K; ++u)
-        rank[u] = lds_rank(s_cnt, f[u], ok[u]);
-    __syncthreads();
-    if (threadIdx.x < kSlotsPerCoarse) {
-        const uint32_t k = s_cnt[threadIdx.x];
-        s_base[threadIdx.x] =
-            k ? atomicAdd(&fcursor[cb * kSlotsPerCoarse + threadIdx.x], k) : 0u;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < K; ++u) {
-        const uint64_t pos = (uint64_t)s_base[f[u]] + rank[u];
-        if (ok[u] && pos < (uint64_t)n) {   // pos < n always: the totals of A
-            ykeys[pos] = key[u];
-            ylps[pos] = (uint16_t)lp[u];
-        }
-    }
-}
-
-// The work item of this workgroup in passes D and E: slot t and the range
-// [lo, hi) of its tile bucket, at most kChunk entries.  Workgroups past the
+// The work item of this workgroup in passes D and E: bucket t and the range
+// [lo, hi) of its entries, at most `chunk` of them.  Workgroups past the
 // last item get lo >= hi.
-__device__ __forceinline__ void chunk_of(const uint32_t *fstart, const uint32_t *fchunk,
-                                         int32_t nslots, int32_t &t, uint32_t &lo, uint32_t &hi)
+__device__ __forceinline__ void chunk_of(const uint32_t *bstart, const uint32_t *bchunk,
+                                         int32_t nb, uint32_t chunk, int32_t &t, uint32_t &lo,
+                                         uint32_t &hi)
 {
     const uint32_t b = blockIdx.x;
     t = 0;
     hi = lo = 0;
-    if (b >= fchunk[nslots])
+    if (b >= bchunk[nb])
         return;
-    t = find_item(fchunk, nslots, b);
-    const uint32_t end = fstart[t + 1];
-    lo = fstart[t] + (b - fchunk[t]) * kChunk;
-    hi = end - lo > kChunk ? lo + kChunk : end;
+    t = find_item(bchunk, nb, b);
+    const uint32_t end = bstart[t + 1];
+    lo = bstart[t] + (b - bchunk[t]) * chunk;
+    hi = end - lo > chunk ? lo + chunk : end;
 }
 
-// Pass D: depth pass of one chunk of a tile bucket (section 2.1's minimum).
-__global__ void __launch_bounds__(256) k_sort_raster(const uint64_t *__restrict__ keys,
-                                                     const uint16_t *__restrict__ lps,
-                                                     const uint32_t *__restrict__ fstart,
-                                                     const uint32_t *__restrict__ fchunk,
-                                                     uint64_t *__restrict__ fb, int32_t ccols,
-                                                     int32_t nslots, int32_t width)
+// Pass D: depth pass of one chunk of a bucket (section 2.1's minimum).
+__global__ void __launch_bounds__(kRasterBlock) k_sort_raster(const uint64_t *__restrict__ keys,
+                                                              const uint16_t *__restrict__ lps,
+                                                              const uint32_t *__restrict__ bstart,
+                                                              const uint32_t *__restrict__ bchunk,
+                                                              uint64_t *__restrict__ fb,
+                                                              int32_t ntx, int32_t nb,
+                                                              uint32_t chunk, int32_t width)
 {
     __shared__ uint64_t tile[kTilePix];
     int32_t t;
     uint32_t lo, hi;
-    chunk_of(fstart, fchunk, nslots, t, lo, hi);
+    chunk_of(bstart, bchunk, nb, chunk, t, lo, hi);
     if (lo >= hi)
         return;
     for (int i = threadIdx.x; i < kTilePix; i += blockDim.x)
@@ -473,7 +445,7 @@ __global__ void __launch_bounds__(256) k_sort_raster(const uint64_t *__restrict_
             const uint64_t i = i0 + (uint64_t)u * blockDim.x;
             ok[u] = i < hi;
             k[u] = ok[u] ? ldnt(keys + i) : ~0ull;
-            l[u] = ok[u] ? lps[i] : 0u;
+            l[u] = ok[u] ? ldnt(lps + i) : 0u;
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
@@ -482,13 +454,13 @@ __global__ void __launch_bounds__(256) k_sort_raster(const uint64_t *__restrict_
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __syncthreads();
-    uint32_t x0, y0;
-    slot_origin((uint32_t)t, ccols, x0, y0);
+    const uint32_t x0 = ((uint32_t)t % (uint32_t)ntx) << kTileShift;
+    const uint32_t y0 = ((uint32_t)t / (uint32_t)ntx) << kTileShift;
     for (int l = threadIdx.x; l < kTilePix; l += blockDim.x) {
         const uint64_t v = tile[l];
-        if (v != ~0ull) {   // a fragment landed here, so the pixel is on screen
+        if (v != ~0ull) {   // a fragment in range landed here, so the pixel is on screen
             uint64_t *dst = fb + (uint64_t)(y0 + (l >> kTileShift)) * (uint32_t)width + x0 +
-                            (l & 31);
+                            (l & (kTileSide - 1));
             const uint64_t cur = __hip_atomic_load(dst, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT);
             if (v < cur)
@@ -497,29 +469,32 @@ __global__ void __launch_bounds__(256) k_sort_raster(const uint64_t *__restrict_
     }
 }
 
-// Pass E: splat accumulation of one chunk of a tile bucket (section 2.2),
-// from the bucket's keys; fb holds the finished depth pass.
+// Pass E: splat accumulation of one chunk of a bucket (section 2.2), from
+// the bucket's keys; fb holds the finished depth pass.
 template <bool PW>
-__global__ void __launch_bounds__(256) k_sort_accum(const uint64_t *__restrict__ keys,
-                                                    const uint16_t *__restrict__ lps,
-                                                    const uint32_t *__restrict__ fstart,
-                                                    const uint32_t *__restrict__ fchunk, Proj P,
-                                                    uint32_t eps_num, uint32_t eps_den,
-                                                    const uint64_t *__restrict__ fb,
-                                                    uint64_t *__restrict__ acc, int32_t ccols,
-                                                    int32_t nslots, int32_t width, int32_t height)
+__global__ void __launch_bounds__(kAccumBlock) k_sort_accum(const uint64_t *__restrict__ keys,
+                                                            const uint16_t *__restrict__ lps,
+                                                            const uint32_t *__restrict__ bstart,
+                                                            const uint32_t *__restrict__ bchunk,
+                                                            Proj P, uint32_t eps_num,
+                                                            uint32_t eps_den,
+                                                            const uint64_t *__restrict__ fb,
+                                                            uint64_t *__restrict__ acc,
+                                                            int32_t ntx, int32_t nb,
+                                                            uint32_t chunk, int32_t width,
+                                                            int32_t height)
 {
     __shared__ uint64_t qmin[kTilePix];
     __shared__ uint64_t sums[2 * kTilePix];
     int32_t t;
     uint32_t lo, hi;
-    chunk_of(fstart, fchunk, nslots, t, lo, hi);
+    chunk_of(bstart, bchunk, nb, chunk, t, lo, hi);
     if (lo >= hi)
         return;
-    uint32_t x0, y0;
-    slot_origin((uint32_t)t, ccols, x0, y0);
+    const uint32_t x0 = ((uint32_t)t % (uint32_t)ntx) << kTileShift;
+    const uint32_t y0 = ((uint32_t)t / (uint32_t)ntx) << kTileShift;
     for (int l = threadIdx.x; l < kTilePix; l += blockDim.x) {
-        const uint32_t x = x0 + (l & 31), y = y0 + (l >> kTileShift);
+        const uint32_t x = x0 + (l & (kTileSide - 1)), y = y0 + (l >> kTileShift);
         const bool on = x < (uint32_t)width && y < (uint32_t)height;
         qmin[l] = on ? fb[(uint64_t)y * (uint32_t)width + x] >> 24 : 0ull;
         sums[2 * l] = 0ull;
@@ -533,13 +508,14 @@ __global__ void __launch_bounds__(256) k_sort_accum(const uint64_t *__restrict__
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             const uint64_t i = i0 + (uint64_t)u * blockDim.x;
-            ok[u] = i < hi;
-            k[u] = ok[u] ? ldnt(keys + i) : 0ull;
-            l[u] = ok[u] ? lps[i] : 0u;
+            const bool in = i < hi;
+            k[u] = in ? ldnt(keys + i) : ~0ull;
+            l[u] = in ? ldnt(lps + i) : 0u;
+            ok[u] = k[u] != ~0ull;   // in range (the key ~0 marks a depth-culled point)
         }
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
-            ok[u] = ok[u] && in_window<PW>(P, eps_num, eps_den, k[u] >> 24, qmin[l[u]]);
+            ok[u] = in_window_live<PW>(P, eps_num, eps_den, k[u] >> 24, qmin[l[u]], ok[u]);
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
             if (ok[u]) {
@@ -556,66 +532,51 @@ __global__ void __launch_bounds__(256) k_sort_accum(const uint64_t *__restrict__
     __syncthreads();
     for (int l = threadIdx.x; l < kTilePix; l += blockDim.x) {
         const uint64_t a1 = sums[2 * l + 1];
-        if (a1 != 0ull) {   // count > 0 (at most kChunk), so the pixel is on screen
+        if (a1 != 0ull) {   // count > 0, so the pixel is on screen
             uint64_t *dst = acc + 2 * ((uint64_t)(y0 + (l >> kTileShift)) * (uint32_t)width +
-                                       x0 + (l & 31));
+                                       x0 + (l & (kTileSide - 1)));
             __hip_atomic_fetch_add(dst, sums[2 * l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(dst + 1, a1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
 
-// Passes A to C2: leaves the tile buckets (ykeys, ylps) and their starts.
+template <bool VEC, bool PW>
+void launch_count_scatter(const Pts &p, const Proj &P, const Layout &L, uint32_t *ccounts,
+                          uint32_t *btotal, uint32_t *bstart, uint32_t *bchunk, uint64_t *keys,
+                          uint16_t *lps, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_sort_count<VEC>), dim3(L.groups), dim3(kCountBlock), 0, s, p, P,
+                       ccounts, L.ntx, L.nb, L.per_wg);
+    hipLaunchKernelGGL(k_sort_prefix, dim3((L.nb + kPrefixCols - 1) / kPrefixCols),
+                       dim3(kPrefixCols * kPrefixSegs), 0, s, ccounts, L.groups, L.nb, btotal);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(kScanThreads), 0, s, btotal, bstart, bchunk,
+                       L.nb, L.chunk);
+    hipLaunchKernelGGL((k_sort_scatter<VEC, PW>), dim3(L.groups), dim3(kScBlock), 0, s, p, P,
+                       ccounts, bstart, keys, lps, L.ntx, L.nb, L.per_wg);
+}
+
+// Passes A to C: leaves the buckets (keys, lps), their starts and the work
+// list of D and E.
 hipError_t sort_passes(const Pts &p, const Proj &P, const Layout &L, char *ws, bool vec,
                        hipStream_t s)
 {
     uint32_t *ccounts = (uint32_t *)(ws + L.ccounts);
-    uint32_t *total = (uint32_t *)(ws + L.total);
-    uint32_t *ctotal = (uint32_t *)(ws + L.ctotal);
-    uint32_t *fstart = (uint32_t *)(ws + L.fstart);
-    uint32_t *fchunk = (uint32_t *)(ws + L.fchunk);
-    uint32_t *fcursor = (uint32_t *)(ws + L.fcursor);
-    uint32_t *cchunk = (uint32_t *)(ws + L.cchunk);
-    uint64_t *xkeys = (uint64_t *)(ws + L.xkeys);
-    uint16_t *xlpc = (uint16_t *)(ws + L.xlpc);
-    uint64_t *ykeys = (uint64_t *)(ws + L.ykeys);
-    uint16_t *ylps = (uint16_t *)(ws + L.ylps);
-    hipLaunchKernelGGL(k_sort_zero, dim3((L.nslots + 255) / 256), dim3(256), 0, s, total,
-                       L.nslots);
-    const size_t lds = (size_t)L.nslots * sizeof(uint32_t);
-    const dim3 g(L.groups), b(kSortBlock);
+    uint32_t *btotal = (uint32_t *)(ws + L.btotal);
+    uint32_t *bstart = (uint32_t *)(ws + L.bstart);
+    uint32_t *bchunk = (uint32_t *)(ws + L.bchunk);
+    uint64_t *keys = (uint64_t *)(ws + L.keys);
+    uint16_t *lps = (uint16_t *)(ws + L.lps);
     const bool pw = P.nr != 0;
     if (vec && pw)
-        hipLaunchKernelGGL((k_sort_count<true, true>), g, b, lds, s, p, P, total, ccounts,
-                           L.ccols, L.nslots, L.ncoarse, L.per_wg);
+        launch_count_scatter<true, true>(p, P, L, ccounts, btotal, bstart, bchunk, keys, lps, s);
     else if (vec)
-        hipLaunchKernelGGL((k_sort_count<true, false>), g, b, lds, s, p, P, total, ccounts,
-                           L.ccols, L.nslots, L.ncoarse, L.per_wg);
+        launch_count_scatter<true, false>(p, P, L, ccounts, btotal, bstart, bchunk, keys, lps, s);
     else if (pw)
-        hipLaunchKernelGGL((k_sort_count<false, true>), g, b, lds, s, p, P, total, ccounts,
-                           L.ccols, L.nslots, L.ncoarse, L.per_wg);
+        launch_count_scatter<false, true>(p, P, L, ccounts, btotal, bstart, bchunk, keys, lps, s);
     else
-        hipLaunchKernelGGL((k_sort_count<false, false>), g, b, lds, s, p, P, total, ccounts,
-                           L.ccols, L.nslots, L.ncoarse, L.per_wg);
-    hipLaunchKernelGGL(k_sort_prefix, dim3((L.ncoarse + kPrefixCols - 1) / kPrefixCols),
-                       dim3(kPrefixCols * kPrefixSegs), 0, s, ccounts, L.groups, L.ncoarse,
-                       ctotal);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, total, fstart, fchunk, fcursor,
-                       cchunk, L.nslots, L.ncoarse);
-    if (vec && pw)
-        hipLaunchKernelGGL((k_sort_coarse<true, true>), g, b, 0, s, p, P, ccounts, fstart, xkeys,
-                           xlpc, L.ccols, L.ncoarse, L.per_wg);
-    else if (vec)
-        hipLaunchKernelGGL((k_sort_coarse<true, false>), g, b, 0, s, p, P, ccounts, fstart, xkeys,
-                           xlpc, L.ccols, L.ncoarse, L.per_wg);
-    else if (pw)
-        hipLaunchKernelGGL((k_sort_coarse<false, true>), g, b, 0, s, p, P, ccounts, fstart, xkeys,
-                           xlpc, L.ccols, L.ncoarse, L.per_wg);
-    else
-        hipLaunchKernelGGL((k_sort_coarse<false, false>), g, b, 0, s, p, P, ccounts, fstart,
-                           xkeys, xlpc, L.ccols, L.ncoarse, L.per_wg);
-    hipLaunchKernelGGL(k_sort_fine, dim3((uint32_t)L.cchunks_max), dim3(kSortBlock), 0, s, xkeys,
-                       xlpc, fstart, cchunk, fcursor, ykeys, ylps, L.ncoarse, p.n);
+        launch_count_scatter<false, false>(p, P, L, ccounts, btotal, bstart, bchunk, keys, lps,
+                                           s);
     return hipGetLastError();
 }
 
@@ -631,7 +592,7 @@ int64_t rz_sorted_workspace_bytes(int64_t n, int32_t width, int32_t height)
     if (n < 0 || width < 1 || height < 1)
         return -1;
     const Layout L = layout(n, width, height);
-    if (L.ncoarse > kMaxCoarse)
+    if (L.nb > kMaxBuckets)
         return -1;
     return (int64_t)L.bytes;
 }
@@ -656,7 +617,7 @@ int rasterize_sorted(const rz_points *pts, const rz_view *view, const rz_depth_m
         (!(flags & RZ_KEEP_KEYS) && (!img || (hq && !status))))
         return RZ_EINVAL;
     const Layout L = layout(pts->n, P.width, P.height);
-    if (L.ncoarse > kMaxCoarse)
+    if (L.nb > kMaxBuckets)
         return RZ_EINVAL;
     if (pts->n > 0 && (!workspace || ((uintptr_t)workspace & 255u) ||
                        workspace_bytes < (int64_t)L.bytes))
@@ -670,25 +631,25 @@ int rasterize_sorted(const rz_points *pts, const rz_view *view, const rz_depth_m
                           15u) == 0;
         char *ws = (char *)workspace;
         e = sort_passes(p, P, L, ws, vec, s);
-        const uint64_t *keys = (const uint64_t *)(ws + L.ykeys);
-        const uint16_t *lps = (const uint16_t *)(ws + L.ylps);
-        const uint32_t *fstart = (const uint32_t *)(ws + L.fstart);
-        const uint32_t *fchunk = (const uint32_t *)(ws + L.fchunk);
-        const dim3 grid((uint32_t)L.fchunks_max);   // workgroups past the last item exit
+        const uint64_t *keys = (const uint64_t *)(ws + L.keys);
+        const uint16_t *lps = (const uint16_t *)(ws + L.lps);
+        const uint32_t *bstart = (const uint32_t *)(ws + L.bstart);
+        const uint32_t *bchunk = (const uint32_t *)(ws + L.bchunk);
+        const dim3 grid((uint32_t)L.chunks_max);   // workgroups past the last item exit
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_sort_raster, grid, dim3(256), 0, s, keys, lps, fstart, fchunk,
-                               fb, L.ccols, L.nslots, P.width);
+            hipLaunchKernelGGL(k_sort_raster, grid, dim3(kRasterBlock), 0, s, keys, lps, bstart,
+                               bchunk, fb, L.ntx, L.nb, L.chunk, P.width);
             e = hipGetLastError();
         }
         if (e == hipSuccess && hq) {
             if (P.nr)
-                hipLaunchKernelGGL((k_sort_accum<true>), grid, dim3(256), 0, s, keys, lps, fstart,
-                                   fchunk, P, num, den, fb, acc, L.ccols, L.nslots, P.width,
-                                   P.height);
+                hipLaunchKernelGGL((k_sort_accum<true>), grid, dim3(kAccumBlock), 0, s, keys,
+                                   lps, bstart, bchunk, P, num, den, fb, acc, L.ntx, L.nb,
+                                   L.chunk, P.width, P.height);
             else
-                hipLaunchKernelGGL((k_sort_accum<false>), grid, dim3(256), 0, s, keys, lps,
-                                   fstart, fchunk, P, num, den, fb, acc, L.ccols, L.nslots,
-                                   P.width, P.height);
+                hipLaunchKernelGGL((k_sort_accum<false>), grid, dim3(kAccumBlock), 0, s, keys,
+                                   lps, bstart, bchunk, P, num, den, fb, acc, L.ntx, L.nb,
+                                   L.chunk, P.width, P.height);
             e = hipGetLastError();
         }
     }
@@ -697,7 +658,6 @@ int rasterize_sorted(const rz_points *pts, const rz_view *view, const rz_depth_m
                : launch_resolve_min(fb, npix, background, img, s);
     return e == hipSuccess ? RZ_OK : hip_fail(e);
 }
-
 
 }  // extern "C"
 

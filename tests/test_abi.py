@@ -166,7 +166,7 @@ def test_sorted_path_validation(rz):
     small = lib.rz_sorted_workspace_bytes(0, 64, 48)
     big = lib.rz_sorted_workspace_bytes(1_000_000, 64, 48)
     assert small >= 0 and small % 256 == 0 and big % 256 == 0
-    assert big >= small + 20 * 1_000_000      # two levels of 8-byte key + 2-byte pixel
+    assert big >= small + 10 * 1_000_000      # an 8-byte key + 2-byte pixel per point
     ps, ds = rz.rz_points(1, 1, 1, 1, 10), rz.depth_struct()
     need = lib.rz_sorted_workspace_bytes(10, 64, 48)
 
@@ -178,7 +178,7 @@ def test_sorted_path_validation(rz):
                                     None, ws and ctypes.c_void_p(ws),
                                     need if ws_bytes is None else ws_bytes, 0, None)
     E = rz.RZ_EINVAL
-    assert call(view=_View(w=4352, h=4096)) == E            # 17 x 16 coarse buckets > 256
+    assert call(view=_View(w=4352, h=4096)) == E            # 68 x 64 buckets > 4096
     assert lib.rz_sorted_workspace_bytes(10, 4352, 4096) == -1
     assert lib.rz_sorted_workspace_bytes(10, 4096, 4096) > 0
     assert call(ws=0) == E                                   # no workspace

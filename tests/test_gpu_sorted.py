@@ -86,8 +86,8 @@ def test_ordered_terrain(rz, oracle):
 
 @pytest.mark.parametrize("size", [(3840, 2160), (4096, 4096)])
 def test_largest_screens(rz, oracle, size):
-    """4096x4096 is 16 x 16 coarse buckets, the limit (a 64 KiB tile
-    histogram in pass A)."""
+    """4096x4096 is 64 x 64 buckets of 64 x 64 pixels, the limit (pass A's
+    16 KiB histogram and pass C's bucket offsets)."""
     cloud = gen.shuffle(gen.terrain(1_000_000, 42, extent=100.0, amplitude=10.0,
                                     wavelength=40.0), 2)
     view = gen.orbit_views(1, 8, [size], extent=100.0, rmin=60.0, rmax=120.0, near=0.5,
@@ -99,7 +99,7 @@ def test_tile_limit(rz):
     import torch
     pts = rz.Points.from_cloud(gen.config1(n=1000)[0])
     view = gen.make_view((0.5, 0.5, 2.5), (0.5, 0.5, 0.5), (0, 1, 0), 60.0, 4352, 4096, 0.01,
-                         10.0)   # 17 x 16 coarse buckets > 256
+                         10.0)   # 68 x 64 buckets > 4096
     assert rz.load().rz_sorted_workspace_bytes(1000, 4352, 4096) == -1
     with pytest.raises(rz.RzError):
         rz.rasterize_sorted(pts, view, workspace=torch.empty(1 << 20, dtype=torch.uint8,
@@ -107,8 +107,8 @@ def test_tile_limit(rz):
 
 
 def test_many_slices(rz, oracle):
-    """2M fragments on a 64x48 screen (4 tiles): each tile is split over many
-    workgroups whose partial results merge in the global atomics."""
+    """2M fragments on a 64x48 screen (one bucket): its entries are split
+    over many chunks whose partial results merge in the global atomics."""
     cloud, _ = gen.config1(n=2_000_000)
     view = gen.make_view((0.5, 0.5, 2.0), (0.5, 0.5, 0.5), (0, 1, 0), 60.0, 64, 48, 0.01, 10.0)
     check(rz, oracle, gen.shuffle(cloud, 5), view, label="many slices")
