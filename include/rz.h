@@ -196,17 +196,17 @@ int rasterize_hq_splat(const rz_points *pts, const rz_view *view,
  * notes that shuffled points make the atomicMin method slower, section 3).
  * Same results as rasterize_atomicmin (hq == NULL) or rasterize_hq_splat
  * (hq != NULL), bit for bit, computed differently: the fragments are first
- * sorted into buckets per 32x32 screen tile (counted, then scattered in two
- * levels: 256x256-pixel buckets, then tiles), then each tile is reduced in
- * LDS and merged into fb (and acc) with one coalesced atomic per pixel; the
- * splat sums are taken straight from the buckets, without a second
- * projection.
+ * sorted into buckets per 64x64 screen tile (counted, then scattered once,
+ * each workgroup sorting its share by bucket in LDS so that its writes are
+ * runs), then each tile is reduced in LDS and merged into fb (and acc) with
+ * one coalesced atomic per pixel; the splat sums are taken straight from the
+ * buckets, without a second projection.
  *   workspace    device memory of at least
  *                rz_sorted_workspace_bytes(pts->n, width, height) bytes
- *                (about 20 bytes per point), owned by the caller, 256-byte
+ *                (about 10 bytes per point), owned by the caller, 256-byte
  *                aligned; its contents on entry do not matter.  May be NULL
  *                when pts->n == 0.
- *   Limits: ceil(width / 256) * ceil(height / 256) <= 256 (e.g. 4096x4096
+ *   Limits: ceil(width / 64) * ceil(height / 64) <= 4096 (e.g. 4096x4096
  *   or 7680x2160), else RZ_EINVAL; rz_sorted_workspace_bytes returns -1 for
  *   such a screen or a negative size.  Other arguments and errors as for
  *   the one-view calls (status required with hq unless RZ_KEEP_KEYS).
@@ -228,7 +228,7 @@ int rasterize_sorted(const rz_points *pts, const rz_view *view,
  * passes fb, acc, img and status as for rasterize_sorted, and gets the same
  * results bit for bit.
  *   Limit: rz_sorted_workspace_bytes(pts->n, width, height) <=
- *   RZ_NOALLOC_SCRATCH_BYTES (at 1920x1080 about 3 million points), else
+ *   RZ_NOALLOC_SCRATCH_BYTES (at 1920x1080 about 6 million points), else
  *   RZ_EBUDGET before anything is enqueued.
  *   Every call on one device shares that device's array and leaves it
  *   holding its own intermediate data: calls that overlap on one device
@@ -465,6 +465,13 @@ typedef struct rz_server_opts {
                                 dry_run_us on the host (tests of admission and
                                 error handling without a GPU)                  */
     int32_t dry_run_us;
+    int64_t work_cap;        /* > 0: the head of the queue is admitted only while
+                                the work in flight plus its own stays within
+                                work_cap, or when nothing is in flight; a
+                                request's work is its cloud's point count, twice
+                                for splatting (two passes over the points).
+                                Large requests then run (nearly) alone while
+                                small ones still overlap them.  0: no limit.   */
 } rz_server_opts;
 
 typedef struct rz_request {

@@ -112,6 +112,7 @@ struct Req {
     uint32_t num = 1, den = 100;
     uint64_t npix = 0;
     uint64_t fb_bytes = 0, acc_bytes = 0, bytes = 0, off = 0;
+    int64_t work = 0;          // point passes: the cloud's n, twice for splatting
     int32_t state = RZ_REQ_QUEUED;
     int32_t error = RZ_OK;
     int32_t stream = -1;
@@ -148,6 +149,7 @@ struct rz_server {
     std::unordered_map<uint64_t, Req *> tickets;
     uint64_t next_ticket = 1;
     uint64_t submitted = 0, completed = 0, failed = 0;
+    int64_t inflight_work = 0;
     int32_t peak_inflight = 0;
     bool stop = false;
     std::thread th;
@@ -170,6 +172,7 @@ namespace {
 
 void finish(rz_server *s, Req *r, int32_t state, int32_t error)
 {
+    s->inflight_work -= r->work;   // only admitted requests finish
     r->state = state;
     r->error = error;
     r->t_done = s->now_us();
@@ -260,6 +263,7 @@ void admit(rz_server *s, Req *r)
     r->stream = best;
     s->load[best]++;
     r->state = RZ_REQ_RUNNING;
+    s->inflight_work += r->work;
     s->inflight.push_back(r);
     s->peak_inflight = std::max(s->peak_inflight, (int32_t)s->inflight.size());
     int rc = RZ_OK;
@@ -310,6 +314,9 @@ void scheduler(rz_server *s)
             while (!s->queue.empty() && (int32_t)s->inflight.size() < s->o.max_inflight &&
                    !s->free_slots.empty()) {
                 Req *r = s->queue.front();
+                if (s->o.work_cap > 0 && !s->inflight.empty() &&
+                    s->inflight_work + r->work > s->o.work_cap)
+                    break;
                 if (!s->pool.alloc(r->bytes, &r->off))
                     break;
                 s->queue.pop_front();
@@ -364,6 +371,7 @@ int validate(rz_server *s, const rz_request *q, Req *r)
             return rc;
     }
     r->r = *q;
+    r->work = s->clouds[q->cloud].n * (q->mode == RZ_MODE_HQ ? 2 : 1);
     r->npix = (uint64_t)q->view.width * (uint64_t)q->view.height;
     r->fb_bytes = align_up(8 * r->npix);
     r->acc_bytes = q->mode == RZ_MODE_HQ ? align_up(16 * r->npix) : 0;
@@ -405,7 +413,7 @@ int rz_server_create(const rz_server_opts *opts, rz_server **out)
         o.max_inflight = 4 * o.streams;
     if (o.streams < 1 || o.streams > kMaxStreams || o.max_inflight < 1 ||
         o.max_inflight > 1024 || o.budget_bytes < (1u << 20) || (o.dry_run & ~1) ||
-        o.dry_run_us < 0)
+        o.dry_run_us < 0 || o.work_cap < 0)
         return RZ_EINVAL;
     rz_server *s = new (std::nothrow) rz_server();
     if (!s)

@@ -86,7 +86,7 @@ class rz_batch_opts(ctypes.Structure):
 
 class rz_server_opts(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("streams", c_int32), ("max_inflight", c_int32),
-                ("dry_run", c_int32), ("dry_run_us", c_int32)]
+                ("dry_run", c_int32), ("dry_run_us", c_int32), ("work_cap", c_int64)]
 
 
 class rz_request(ctypes.Structure):
@@ -701,11 +701,12 @@ class Server:
     renders one view into a caller-owned device image.  dry_run=True runs
     the scheduler without any device work (requests take dry_run_us)."""
 
-    def __init__(self, budget_bytes, streams=4, max_inflight=0, dry_run=False, dry_run_us=0):
+    def __init__(self, budget_bytes, streams=4, max_inflight=0, dry_run=False, dry_run_us=0,
+                 work_cap=0):
         if not dry_run:
             _require_gpu()
         o = rz_server_opts(int(budget_bytes), int(streams), int(max_inflight), 1 if dry_run else 0,
-                           int(dry_run_us))
+                           int(dry_run_us), int(work_cap))
         h = c_void_p()
         _check(load().rz_server_create(ctypes.byref(o), ctypes.byref(h)), "rz_server_create")
         self._h = h

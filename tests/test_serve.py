@@ -181,3 +181,31 @@ def test_scheduler_sleeps_while_waiting(rz):
     assert wall > 0.9
     assert cpu < 0.25 * wall, (cpu, wall)
     s.close()
+
+
+def test_work_cap_keeps_large_requests_apart(rz):
+    """With a work cap, two large requests never run together while small
+    ones still run beside a large one; arrival order is kept."""
+    s = rz.Server(64 << 20, streams=4, dry_run=True, dry_run_us=20_000, work_cap=1200)
+    big = s.add_cloud(rz.rz_points(1, 1, 1, 1, 1000))
+    small = s.add_cloud(rz.rz_points(1, 1, 1, 1, 10))
+    plan = [big, small, small, big, small, big]
+    ts = [s.submit(c, _View(32, 32), 0) for c in plan]
+    st = _wait(s, ts)
+    s.close()
+    assert all(x["state"] == rz.RZ_REQ_DONE for x in st)
+    spans = [(x["t_admit_us"], x["t_done_us"]) for x in st]
+    bigs = [spans[i] for i, c in enumerate(plan) if c == big]
+    for (a0, a1), (b0, b1) in zip(bigs, bigs[1:]):
+        assert b0 >= a1 - 1.0            # the next large request starts after the last ends
+    # the first small requests ran while the first large one did
+    assert spans[1][0] < spans[0][1] and spans[2][0] < spans[0][1]
+    for a, b in zip(st, st[1:]):
+        assert b["t_admit_us"] >= a["t_admit_us"]
+    # a splatting request counts its points twice: 2 x 1000 > 1200, yet it
+    # runs (alone) rather than waiting forever
+    s = rz.Server(64 << 20, streams=2, dry_run=True, dry_run_us=1000, work_cap=1200)
+    big = s.add_cloud(rz.rz_points(1, 1, 1, 1, 1000))
+    st = _wait(s, [s.submit(big, _View(32, 32), 1) for _ in range(3)])
+    s.close()
+    assert all(x["state"] == rz.RZ_REQ_DONE for x in st)
