@@ -111,3 +111,30 @@ def brute_force_min(pix, q, rgb, npix, clear):
         if key < fb[p]:
             fb[p] = key
     return np.array(fb, dtype=np.uint64)
+
+
+def round_ieee(v: F, p: int, emin: int) -> F:
+    """v rounded to the nearest binary floating-point number with p significand
+    bits and least normal exponent emin, ties to even (IEEE 754, section 4.3.1);
+    no overflow in these inputs."""
+    if v == 0:
+        return F(0)
+    sign, a = (-1, -v) if v < 0 else (1, v)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if F(2) ** e > a:
+        e -= 1
+    ulp = F(2) ** (max(e, emin) - p + 1)
+    m = a / ulp
+    k = m.numerator // m.denominator
+    r = m - k
+    if r > F(1, 2) or (r == F(1, 2) and k % 2 == 1):
+        k += 1
+    return sign * k * ulp
+
+
+def r32(v):
+    return round_ieee(v, 24, -126)
+
+
+def r64(v):
+    return round_ieee(v, 53, -1022)

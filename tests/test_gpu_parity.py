@@ -555,3 +555,28 @@ def test_reciprocal_matches_host_quotient(rz):
     bad = np.flatnonzero(got != want)
     assert bad.size == 0, [(hex(int(bits[i])), hex(int(got[i])), hex(int(want[i])))
                            for i in bad[:8]]
+
+
+@pytest.mark.parametrize("seed,kind,scale,eps,offset", [
+    (1, 0, 0.0, (1, 100), 0.0), (3, 1, 1000.0, (1, 100), 0.0), (2, 0, 0.0, (3, 100), 0.0),
+    (4, 0, 0.0, (1, 100), 3.0e4)])
+def test_window_edge_probes(rz, oracle, seed, kind, scale, eps, offset):
+    """Points placed within a few float steps of pixels' splat window edges
+    (section 2.2) and of the near and far planes, where the accumulate
+    pass's double-precision pre-test meets its integer test on ties: splat
+    sums and images equal the oracle's, with the points in pixel order
+    (each wave's points in a small rectangle: the per-wave LDS tile) and in
+    random order (rectangles too large for the tile: global atomics)."""
+    from tests.edge_scenes import window_edge_scene
+    sc = window_edge_scene(oracle, seed, kind, scale, eps, offset)
+    v = sc["view"]
+    pts = np.concatenate([sc["base"], sc["probes"]])
+    rgb = np.concatenate([sc["rgb"], np.full(len(sc["probes"]), 0x010203, np.uint32)])
+    pix, _ = oracle.fragments(pts[:, 0], pts[:, 1], pts[:, 2], v.vp, v.near, v.far, v.width,
+                              v.height, kind, scale)
+    order = np.argsort(np.where(pix < 0, 1 << 40, pix), kind="stable")
+    for label, idx in (("pixel order", order),
+                       ("random order", np.random.default_rng(seed).permutation(len(pts)))):
+        cloud = gen.Cloud(pts[idx, 0].copy(), pts[idx, 1].copy(), pts[idx, 2].copy(), rgb[idx])
+        check_scene(rz, oracle, cloud, v, depth=(kind, scale), eps=eps,
+                    label=f"window edges, {label}")

@@ -12,6 +12,7 @@ import pytest
 from paper_1908_02681_amd import gen
 from tests.edge_scenes import EDGE_H, EDGE_W, random_scene, rounding_edge_scene
 from tests.exact import ExactCamera, brute_force_min, fragments as exact_fragments
+from tests.exact import r32, r64, round_ieee
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 LINEAR, SCALE = 0, 1
@@ -198,31 +199,7 @@ def _random_scene(seed, n, W, H, kind=LINEAR, scale=0.0):
     return random_scene(seed, n, W, H)
 
 
-def _round_ieee(v: F, p: int, emin: int) -> F:
-    """v rounded to the nearest binary floating-point number with p significand
-    bits and least normal exponent emin, ties to even (IEEE 754, section 4.3.1);
-    no overflow in these inputs."""
-    if v == 0:
-        return F(0)
-    sign, a = (-1, -v) if v < 0 else (1, v)
-    e = a.numerator.bit_length() - a.denominator.bit_length()
-    if F(2) ** e > a:
-        e -= 1
-    ulp = F(2) ** (max(e, emin) - p + 1)
-    m = a / ulp
-    k = m.numerator // m.denominator
-    r = m - k
-    if r > F(1, 2) or (r == F(1, 2) and k % 2 == 1):
-        k += 1
-    return sign * k * ulp
-
-
-def _r32(v):
-    return _round_ieee(v, 24, -126)
-
-
-def _r64(v):
-    return _round_ieee(v, 53, -1022)
+_round_ieee, _r32, _r64 = round_ieee, r32, r64
 
 
 def _rounded_fragment(m, v, W, H, near, far, o, s, X, Y, Z, fused):
