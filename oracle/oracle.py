@@ -63,11 +63,15 @@ def configure(lib):
 
 
 def _load():
+    """The oracle library; RZ_ORACLE_LIB names another build of the same
+    source to load instead (the sanitizer tests use an instrumented one)."""
     global _lib
     with _lock:
         if _lib is None:
-            build()
-            _lib = configure(ctypes.CDLL(LIB))
+            other = os.environ.get("RZ_ORACLE_LIB")
+            if not other:
+                build()
+            _lib = configure(ctypes.CDLL(other or LIB))
     return _lib
 
 
