@@ -108,6 +108,18 @@ def cpu_baseline(cloud, view, eps, min_s=10.0, budget_s=20.0):
 BATCH_SIZES = [(256, 256), (640, 480), (1280, 720), (1920, 1080)]
 
 
+def calibration_copy(nbytes):
+    """One device-to-device copy of nbytes: a plain copy kernel of known size
+    whose HBM counters scale those of the kernels in the same counter run."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[bench] calibration copy of {src.numel() * 4} bytes done")
+
+
 def bench_batch(a):
     """64 views of one resident 100M-point terrain: one autotuned, graph-captured
     batch against the loop of 64 one-view calls (same views, same bits)."""
@@ -140,9 +152,14 @@ def bench_batch(a):
             else:
                 rz.rasterize_hq_splat(pts, v, fb=fb, acc=acc, img=img, status=st)
 
-    b = rz.Batch(pts, views, modes, use_graph=True)
-    chosen, tuned_ms = b.autotune(reps=2)
-    log(f"[batch] autotuned {chosen} ({tuned_ms:.3f} ms)")
+    if a.batch_k:
+        b = rz.Batch(pts, views, modes, views_per_group=a.batch_k, use_graph=False)
+        chosen = b.opts()
+        log(f"[batch] fixed {chosen}")
+    else:
+        b = rz.Batch(pts, views, modes, use_graph=True)
+        chosen, tuned_ms = b.autotune(reps=2)
+        log(f"[batch] autotuned {chosen} ({tuned_ms:.3f} ms)")
 
     def timed(fn, steps, warm):
         for _ in range(warm):
@@ -160,6 +177,8 @@ def bench_batch(a):
     log(f"[batch] plain {ms_plain:.3f} ms, batched {ms_batch:.3f} ms, identical={same}")
     if not same:
         raise SystemExit("batched images differ from the one-view calls")
+    if a.calibrate_copy:
+        calibration_copy(a.calibrate_copy)
     work = n * len(views)
     out = {
         "metric": METRIC, "value": round(work / (ms_batch * 1e-3) / 1e9, 3), "unit": "Gpoints/s",
@@ -173,7 +192,8 @@ def bench_batch(a):
         "detail": {"plain_loop_ms": round(ms_plain, 4),
                    "plain_loop_gpts": round(work / (ms_plain * 1e-3) / 1e9, 3),
                    "speedup_vs_plain": round(ms_plain / ms_batch, 3),
-                   "autotuned": chosen, "bit_identical_to_plain": same},
+                   ("fixed" if a.batch_k else "autotuned"): chosen,
+                   "bit_identical_to_plain": same},
     }
     print(json.dumps(out), flush=True)
 
@@ -187,76 +207,85 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q)) if len(a) else float("nan")
 
 
-def bench_serve(a):
-    """Continuous-batching server vs the FIFO one-call-per-request loop on the
-    same Poisson traces over 8 resident clouds."""
-    import torch
-    from paper_1908_02681_amd import gen, rz
+class ServingWorld:
+    """Resident serving clouds, output image rings and the two ways of
+    serving a request trace: the plain FIFO loop (one call, then a device
+    synchronisation, per request) and the continuous-batching server."""
 
-    clouds = gen.SERVE_CLOUDS[:a.serve_clouds]
-    pts, npts = [], []
-    for i, n in enumerate(clouds):
-        log(f"[serve] generating cloud {i}: {n} points")
-        c = gen.serve_cloud(i, n)
-        pts.append(rz.Points.from_cloud(c))
-        npts.append(c.n)
-        del c
-    torch.cuda.synchronize()
-    log(f"[serve] {sum(npts) / 1e6:.0f}M points resident")
-    # one reusable output image ring per resolution (requests in flight never share)
-    ring = a.serve_ring
-    imgs = {sz: [torch.empty(sz[0] * sz[1], dtype=torch.int32, device="cuda") for _ in range(ring)]
-            for sz in gen.SERVE_SIZES}
-    # plain loop buffers: one fb/acc per resolution
-    fbs = {sz: rz.new_framebuffer(gen.View(np.eye(4), 1, 2, *sz), 0, hq=True) for sz in gen.SERVE_SIZES}
-    st_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+    def __init__(self, a, clouds=None, log_prefix="[serve]"):
+        import torch
+        from paper_1908_02681_amd import gen, rz
+        self.torch, self.gen, self.rz, self.a = torch, gen, rz, a
+        self.pts, self.npts = [], []
+        for i, n in enumerate(gen.SERVE_CLOUDS[:a.serve_clouds]):
+            c = clouds.get(i) if clouds else None
+            if c is None:
+                log(f"{log_prefix} generating cloud {i}: {n} points")
+                c = gen.serve_cloud(i, n)
+            self.pts.append(rz.Points.from_cloud(c))
+            self.npts.append(c.n)
+            del c
+        torch.cuda.synchronize()
+        log(f"{log_prefix} {sum(self.npts) / 1e6:.0f}M points resident")
+        # one reusable output image ring per resolution (requests in flight never share)
+        self.ring = a.serve_ring
+        self.imgs = {sz: [torch.empty(sz[0] * sz[1], dtype=torch.int32, device="cuda")
+                          for _ in range(self.ring)] for sz in gen.SERVE_SIZES}
+        # plain loop buffers: one fb/acc per resolution
+        self.fbs = {sz: rz.new_framebuffer(gen.View(np.eye(4), 1, 2, *sz), 0, hq=True)
+                    for sz in gen.SERVE_SIZES}
+        self.st_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+        torch.cuda.synchronize()
 
-    def plain_one(c, v, m, img):
-        fb, acc = fbs[(v.width, v.height)]
+    def plain_one(self, c, v, m, img):
+        fb, acc = self.fbs[(v.width, v.height)]
         if m == 0:
-            rz.rasterize_atomicmin(pts[c], v, fb=fb, img=img)
+            self.rz.rasterize_atomicmin(self.pts[c], v, fb=fb, img=img)
         else:
-            rz.rasterize_hq_splat(pts[c], v, fb=fb, acc=acc, img=img, status=st_dev)
+            self.rz.rasterize_hq_splat(self.pts[c], v, fb=fb, acc=acc, img=img,
+                                       status=self.st_dev)
 
-    def run_plain(trace):
+    def run_plain(self, trace):
+        torch = self.torch
         lat, done_t = [], []
         t0 = time.perf_counter()
         for k, (t_arr, c, v, m) in enumerate(trace):
             while time.perf_counter() - t0 < t_arr:
                 pass
-            plain_one(c, v, m, imgs[(v.width, v.height)][k % ring])
+            self.plain_one(c, v, m, self.imgs[(v.width, v.height)][k % self.ring])
             torch.cuda.synchronize()
             t = time.perf_counter() - t0
             lat.append((t - t_arr) * 1e3)
             done_t.append(t)
         return lat, trace[0][0], done_t[-1]
 
-    def run_server(trace):
-        srv = rz.Server(a.serve_budget, streams=a.serve_streams)
-        ids = [srv.add_cloud(p) for p in pts]
+    def run_server(self, trace):
+        rz, a = self.rz, self.a
+        srv = rz.Server(a.serve_budget, streams=a.serve_streams, work_cap=a.serve_work_cap)
+        ids = [srv.add_cloud(p) for p in self.pts]
         pending, status = {}, {}
-        slot_owner = {sz: [None] * ring for sz in gen.SERVE_SIZES}
+        slot_owner = {sz: [None] * self.ring for sz in self.gen.SERVE_SIZES}
 
-        def reap(block=False):
+        def reap():
             for t in list(pending):
                 st = srv.poll(t)
                 if st["state"] >= rz.RZ_REQ_DONE:
                     status[t] = st
                     del pending[t]
         t0 = time.perf_counter()
-        base_us = None
         tick = []
         for k, (t_arr, c, v, m) in enumerate(trace):
             while time.perf_counter() - t0 < t_arr:
                 if pending:
                     reap()
             sz = (v.width, v.height)
-            j = k % ring
+            j = k % self.ring
             prev = slot_owner[sz][j]
             while prev is not None and prev in pending:
                 reap()
             late = time.perf_counter() - t0 - t_arr   # time spent before submission
-            t = srv.submit(ids[c], v, m, img=imgs[sz][j])
+            # the ring images were made and synchronised up front: no stream to wait for
+            t = srv.submit(ids[c], v, m, img=self.imgs[sz][j], after=None)
             slot_owner[sz][j] = t
             pending[t] = k
             tick.append((t, late))
@@ -275,29 +304,45 @@ def bench_serve(a):
         span = (max(x["t_done_us"] for x in sts) - first_arrival_us) / 1e6
         return lat, span, stats
 
-    # capacity of the plain loop: back-to-back requests
-    probe = serve_trace(200, 1e9, gen.CONFIG_SEEDS[5], len(pts))
-    for _ in range(2):
-        run_plain(probe[:20])
-    lat, _, t_end = run_plain(probe)
-    cap = len(probe) / t_end
+    def capacity(self):
+        """Requests per second of the plain loop on back-to-back requests."""
+        probe = serve_trace(200, 1e9, self.gen.CONFIG_SEEDS[5], len(self.pts))
+        for _ in range(2):
+            self.run_plain(probe[:20])
+        _, _, t_end = self.run_plain(probe)
+        return len(probe) / t_end
+
+    def load_row(self, rate, nreq):
+        """Both ways of serving one Poisson trace at `rate` requests per second."""
+        trace = serve_trace(nreq, rate, self.gen.CONFIG_SEEDS[5], len(self.pts))
+        work = sum(self.npts[c] for _, c, _, _ in trace)
+        lp, _, tp_end = self.run_plain(trace)
+        ls, span, stats = self.run_server(trace)
+        return {"offered_req_s": round(rate, 1), "requests": nreq,
+                "server": {"req_s": round(len(trace) / span, 1),
+                           "gpts": round(work / span / 1e9, 2),
+                           "p50_ms": round(pct(ls, 50), 3), "p99_ms": round(pct(ls, 99), 3),
+                           "peak_inflight": stats["peak_inflight"],
+                           "peak_fb_MB": round(stats["peak_bytes"] / 1e6, 1)},
+                "plain": {"req_s": round(len(trace) / (tp_end - trace[0][0]), 1),
+                          "gpts": round(work / (tp_end - trace[0][0]) / 1e9, 2),
+                          "p50_ms": round(pct(lp, 50), 3), "p99_ms": round(pct(lp, 99), 3)}}
+
+
+def bench_serve(a):
+    """Continuous-batching server vs the FIFO one-call-per-request loop on the
+    same Poisson traces over 8 resident clouds."""
+    import torch
+    from paper_1908_02681_amd import gen, rz
+
+    w = ServingWorld(a)
+    pts, npts = w.pts, w.npts
+    plain_one = w.plain_one
+    cap = w.capacity()
     log(f"[serve] plain loop capacity ~{cap:.0f} req/s")
     rows = []
     for f in a.serve_loads:
-        rate = f * cap
-        trace = serve_trace(a.serve_requests, rate, gen.CONFIG_SEEDS[5], len(pts))
-        work = sum(npts[c] for _, c, _, _ in trace)
-        lp, _, tp_end = run_plain(trace)
-        ls, span, stats = run_server(trace)
-        row = {"offered_req_s": round(rate, 1),
-               "server": {"req_s": round(len(trace) / span, 1),
-                          "gpts": round(work / span / 1e9, 2),
-                          "p50_ms": round(pct(ls, 50), 3), "p99_ms": round(pct(ls, 99), 3),
-                          "peak_inflight": stats["peak_inflight"],
-                          "peak_fb_MB": round(stats["peak_bytes"] / 1e6, 1)},
-               "plain": {"req_s": round(len(trace) / (tp_end - trace[0][0]), 1),
-                         "gpts": round(work / (tp_end - trace[0][0]) / 1e9, 2),  # same span rule
-                         "p50_ms": round(pct(lp, 50), 3), "p99_ms": round(pct(lp, 99), 3)}}
+        row = w.load_row(f * cap, a.serve_requests)
         log(f"[serve] load {f:.2f}: {row}")
         rows.append(row)
     # outside the timed runs: a burst of overlapping requests through the
@@ -361,18 +406,29 @@ def main():
     ap.add_argument("--depth", choices=("linear", "gl24", "f32rev"), default="linear",
                     help="depth encoding; gl24 and f32rev have no splat frame")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: skip the stress, serving and viewpoint legs")
+    ap.add_argument("--extras-budget", type=float, default=270.0,
+                    help="seconds from the start of the run after which no further extra "
+                         "leg starts (each leg is skipped, and named, when it would not fit)")
     ap.add_argument("--batch-points", type=int, default=100_000_000)
     ap.add_argument("--batch-views", type=int, default=64)
+    ap.add_argument("--batch-k", type=int, default=0,
+                    help="batch64: a fixed group size K, no graph and no autotuning "
+                         "(for counter runs, which count every dispatch on its own)")
     ap.add_argument("--serve-clouds", type=int, default=8)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget", type=int, default=4 << 30)
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--serve-ring", type=int, default=96)
+    ap.add_argument("--serve-work-cap", type=int, default=0,
+                    help="server work cap in point passes (0: none); see rz_server_opts")
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 1.0, 1.3, 2.0])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="after the timed region, copy BYTES between two device buffers "
                          "(a plain copy kernel of known size for scaling HBM counters)")
     a = ap.parse_args()
+    a.t_start = time.perf_counter()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the sort-last "
               "composition across GPUs is designed, with its merge kernels timed on one GPU, "
@@ -502,13 +558,16 @@ def main():
             kern["rasterize_points(HQ)"] = {"ms": avg[2], "bytes": 32 * n, "launches_per_step": 1}
             kern["k_resolve_hq"] = {"ms": avg[4], "bytes": 44 * npix, "launches_per_step": 1}
     elif a.path == "sorted":
-        # whole calls; bytes = the sort's own HBM traffic per point: count
-        # pass 16, coarse scatter 16 + 10, fine scatter 10 + 10, tile min 10
-        # (+ splat pass 10)
+        # whole calls, against the algorithmic bytes of the method (16 B per
+        # point for the depth pass, 32 for the splat frame's two passes);
+        # the sort's own traffic (count pass 12 B/pt, scatter 16 + 10, tile
+        # minimum 10, splat sums 10) is reported beside it
         kern = {
-            "rasterize_sorted(atomicMin)": {"ms": avg[0], "bytes": 72 * n,
+            "rasterize_sorted(atomicMin)": {"ms": avg[0], "bytes": 16 * n,
+                                            "sort_traffic_bytes": 48 * n,
                                             "launches_per_step": 1},
-            "rasterize_sorted(HQ)": {"ms": avg[2], "bytes": 82 * n, "launches_per_step": 1},
+            "rasterize_sorted(HQ)": {"ms": avg[2], "bytes": 32 * n,
+                                     "sort_traffic_bytes": 58 * n, "launches_per_step": 1},
             "k_resolve_min": {"ms": avg[1], "bytes": 20 * npix, "launches_per_step": 1},
             "k_resolve_hq": {"ms": avg[4], "bytes": 44 * npix, "launches_per_step": 1},
         }
@@ -522,6 +581,8 @@ def main():
         }
     for k in kern.values():
         k["GBps"] = k["bytes"] / (k["ms"] * 1e-3) / 1e9
+        if "sort_traffic_bytes" in k:
+            k["sort_traffic_GBps"] = k["sort_traffic_bytes"] / (k["ms"] * 1e-3) / 1e9
     dom = max(kern, key=lambda k: kern[k]["ms"] * kern[k]["launches_per_step"])
     dk = kern[dom]
     traffic = None
@@ -572,6 +633,8 @@ def main():
                         if with_hq else None),
             "kernels_ms": {k: round(v["ms"], 4) for k, v in kern.items()},
             "kernels_GBps": {k: round(v["GBps"], 1) for k, v in kern.items()},
+            "sort_traffic_GBps": {k: round(v["sort_traffic_GBps"], 1) for k, v in kern.items()
+                                  if "sort_traffic_GBps" in v} or None,
             "evented_ms_per_step": round(float(avg.sum()), 4),
             "valu_issue": valu,
             "launch": rz.get_launch(),
@@ -597,17 +660,150 @@ def main():
             "atomicmin_frame_ms": round(fl[0] + fl[1], 4),
             "hq_frame_ms": round(fl[2] + fl[3] + fl[4], 4) if with_hq else None}
     if a.calibrate_copy:
-        src = torch.empty(a.calibrate_copy // 4, dtype=torch.int32, device="cuda").fill_(1)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy of {src.numel() * 4} bytes done")
-        del src, dst
+        calibration_copy(a.calibrate_copy)
+    extras = (a.workload == "terrain50m" and a.path == "direct" and a.point_size == 1
+              and a.depth == "linear" and not a.no_extras)
+    if extras:
+        del pts, fb, acc, img, himg, status
+        torch.cuda.empty_cache()
+        out["detail"].update(extra_legs(a))
     if not a.no_cpu_baseline:
         log("[bench] timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(cloud, view, eps)
     print(json.dumps(out), flush=True)
+
+
+def frame_times(rz, pts, view, path, steps, warmup, ws=None):
+    """Median event times (ms) of one atomicMin frame and one HQ frame
+    (depth pass, accumulate, resolve) over `steps` runs."""
+    import torch
+    npix = view.width * view.height
+    fb, acc = rz.new_framebuffer(view, 0, hq=True)
+    img = torch.empty(npix, dtype=torch.int32, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = {}
+    for hq in (False, True):
+        def one(ev=None):
+            if ev:
+                ev[0].record()
+            if path == "sorted":
+                rz.rasterize_sorted(pts, view, hq=hq, fb=fb, acc=acc, img=img, status=st,
+                                    workspace=ws)
+            elif hq:
+                rz.rasterize_hq_splat(pts, view, fb=fb, acc=acc, img=img, status=st)
+            else:
+                rz.rasterize_atomicmin(pts, view, fb=fb, img=img)
+            if ev:
+                ev[1].record()
+        for _ in range(warmup):
+            one()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+        for e in evs:
+            one(e)
+        torch.cuda.synchronize()
+        t = sorted(e[0].elapsed_time(e[1]) for e in evs)
+        out["hq" if hq else "atomicmin"] = t[len(t) // 2]
+    if int(st.item()) != 0:
+        raise SystemExit("splat count overflow reported")
+    return out
+
+
+def extra_legs(a):
+    """The rest of the metric on the default run, each leg started only while
+    the run's wall clock allows it: the 300M-point stress cloud (Morton order
+    by the direct path; shuffled by the best path per frame) at 2560x1440,
+    the serving workload at 0.5, 0.8 and 1.0 times the plain loop's
+    capacity, and the one-view calls of both methods on each of the 64 orbit
+    cameras of the batched workload (viewpoint sensitivity)."""
+    import torch
+    from paper_1908_02681_amd import gen, rz
+    detail, skipped = {}, []
+
+    def left():
+        return a.extras_budget - (time.perf_counter() - a.t_start)
+
+    stress = None
+    if left() > 90:
+        log("[extras] generating the 300M-point stress cloud")
+        stress, views = gen.config3()
+        view = views[0]
+        n = stress.n
+        pts = rz.Points.from_cloud(stress)
+        mort = frame_times(rz, pts, view, "direct", 10, 3)
+        del pts
+        torch.cuda.empty_cache()
+        sh = gen.shuffle(stress, 3)
+        pts = rz.Points.from_cloud(sh)
+        del sh
+        ws = rz.new_workspace(n, view.width, view.height)
+        direct = frame_times(rz, pts, view, "direct", 5, 2)
+        srt = frame_times(rz, pts, view, "sorted", 10, 3, ws)
+        del pts, ws
+        torch.cuda.empty_cache()
+        best = {k: min(direct[k], srt[k]) for k in direct}
+        bpath = {k: "sorted" if srt[k] <= direct[k] else "direct" for k in direct}
+
+        def leg(t):
+            return {"atomicmin_ms": round(t["atomicmin"], 4), "hq_ms": round(t["hq"], 4),
+                    "atomicmin_gpts": round(n / t["atomicmin"] / 1e6, 2),
+                    "hq_gpts": round(n / t["hq"] / 1e6, 2),
+                    "atomicmin_hbm_frac": round(16 * n / (t["atomicmin"] * 1e-3) / 8e12, 4),
+                    "hq_hbm_frac": round(32 * n / (t["hq"] * 1e-3) / 8e12, 4)}
+        detail["stress300m"] = {
+            "workload": f"stress 300M points (250M terrain + 20 spheres of 2.5M), "
+                        f"{view.width}x{view.height}",
+            "morton_direct": leg(mort),
+            "shuffled_best": {**leg(best), "path": bpath},
+            "shuffled_direct": leg(direct), "shuffled_sorted": leg(srt)}
+        log(f"[extras] stress300m: {detail['stress300m']}")
+    else:
+        skipped.append("stress300m")
+
+    if left() > 90:
+        w = ServingWorld(a, clouds={7: stress} if stress is not None else None,
+                         log_prefix="[extras]")
+        stress = None
+        cap = w.capacity()
+        rows = [w.load_row(f * cap, 500) for f in (0.5, 0.8, 1.0)]
+        detail["served"] = {
+            "workload": f"{len(w.pts)} resident clouds "
+                        f"({', '.join(f'{n // 1_000_000}M' for n in w.npts)} points), Poisson "
+                        f"arrivals, resolutions 256x256 to 2560x1440, methods 50/50, "
+                        f"{a.serve_budget >> 20} MiB framebuffer budget, {a.serve_streams} streams",
+            "plain_capacity_req_s": round(cap, 1),
+            "loads": rows}
+        log(f"[extras] served: {detail['served']}")
+        del w
+        torch.cuda.empty_cache()
+    else:
+        skipped.append("served")
+    stress = None
+
+    if left() > 30:
+        log("[extras] viewpoints: generating the 100M-point terrain")
+        cloud = gen.terrain(100_000_000, gen.CONFIG_SEEDS[4])
+        views = gen.orbit_views(64, gen.CONFIG_SEEDS[4], BATCH_SIZES)
+        pts = rz.Points.from_cloud(cloud)
+        n = cloud.n
+        del cloud
+        rates = {"atomicmin": [], "hq": []}
+        for v in views:
+            t = frame_times(rz, pts, v, "direct", 3, 1)
+            for k in rates:
+                rates[k].append(n / t[k] / 1e6)
+        del pts
+        torch.cuda.empty_cache()
+        detail["viewpoints"] = {
+            "workload": "terrain 100M points (Morton order), 64 orbit cameras (radius 600-1200 m, "
+                        "elevation 20-60 deg, 256x256 to 1920x1080), one-view calls",
+            **{k: {"min_gpts": round(min(r), 2), "median_gpts": round(float(np.median(r)), 2),
+                   "max_gpts": round(max(r), 2)} for k, r in rates.items()}}
+        log(f"[extras] viewpoints: {detail['viewpoints']}")
+    else:
+        skipped.append("viewpoints")
+    detail["extras_skipped"] = skipped
+    detail["extras_wall_s"] = round(time.perf_counter() - a.t_start, 1)
+    return detail
 
 
 def time_sort_last(rz, pts, view, G, steps):
