@@ -63,6 +63,7 @@ extern "C" {
                                 calls report it through their status word) */
 #define RZ_EBUDGET (-5)      /* request does not fit the memory budget    */
 #define RZ_ESTATE (-6)       /* object used in the wrong state            */
+#define RZ_EIO (-7)          /* a file could not be written (autotune cache) */
 
 /* ---- flags -------------------------------------------------------------- */
 /* Skip the resolve step: fb (and acc) keep the raw keys (sums) so that they
@@ -435,6 +436,56 @@ int rz_batch_get_opts(const rz_batch *b, rz_batch_opts *opts);
 /* Frees the table and the graph (waits for nothing: the caller must not
    destroy a batch whose run is still in flight). */
 int rz_batch_destroy(rz_batch *b);
+
+/* ---- autotune cache ----------------------------------------------------- */
+/* The batch autotuner's choices persist in a text file, one line per key,
+   so that a later process with a batch of the same class skips the search.
+   Host-only calls (no device work) except rz_batch_autotune_cached. */
+typedef struct rz_tune_entry {
+    int32_t views_per_group;  /* K, 1..8                                     */
+    rz_launch depth;          /* launch shape of the depth passes            */
+    rz_launch accum;          /* launch shape of the accumulate passes       */
+    float ms;                 /* the batch's time when the entry was chosen   */
+} rz_tune_entry;
+
+/* Point order class of HOST arrays x, y, z (n points): windows of up to 4096
+   consecutive points at the start, middle and end of the arrays; a window is
+   ordered when the median distance between consecutive finite points is at
+   most 1/16 of its bounding-box diagonal (Morton or scan order), and the
+   majority of windows with at least 16 such pairs decides.  Returns 0
+   (ordered), 1 (shuffled, also when no window has 16 pairs) or RZ_EINVAL.
+   The batch engine samples its device points the same way (section 3 of the
+   paper: point order changes the atomic method's speed). */
+int rz_order_class_host(const float *x, const float *y, const float *z, int64_t n);
+
+/* key: six space-separated words without spaces inside, as built by
+   rz_batch_autotune_cached: "<arch> n<log2 points> px<log2 pixels>
+   v<views> hq<splatting views in eighths> <ordered|shuffled>".  Lookup
+   returns 1 and fills *out when the file holds a valid line for key (the
+   last one wins), 0 when it holds none or does not exist, RZ_EINVAL for a
+   NULL argument or a malformed key.  Lines that do not parse are ignored. */
+int rz_tune_cache_lookup(const char *path, const char *key, rz_tune_entry *out);
+/* Replaces key's line (or adds it) and rewrites the file through a private
+   temporary file and a rename, so that a reader never sees a torn file;
+   lines that do not parse are dropped.  Writers in one process are
+   serialised; between processes the last rename wins.  RZ_EINVAL for a bad
+   key or an entry out of range, RZ_EIO when the file cannot be written. */
+int rz_tune_cache_store(const char *path, const char *key, const rz_tune_entry *entry);
+
+/* rz_batch_autotune through the cache at cache_path.  The key is built from
+   the current device's architecture, the batch's point count and total
+   pixels (log2, rounded), its view count, its share of splatting views and
+   the order class of its points (three 4096-point windows copied to the
+   host).  On a hit the cached options are first checked against the
+   library-default options: one run of each, and the image checksums must
+   agree (else the full search runs); they are then timed (reps runs, median)
+   and applied, and *hit = 1.  On a miss the full search runs and its choice
+   is stored (*hit = 0); RZ_EIO then means the batch is tuned but the file
+   could not be written.  key_out (may be NULL) receives the key, at most
+   key_len bytes with the terminating zero.  Synchronous on `stream`. */
+int rz_batch_autotune_cached(rz_batch *b, void *stream, int32_t reps, const char *cache_path,
+                             rz_batch_opts *chosen, float *best_ms, int32_t *hit,
+                             char *key_out, int32_t key_len);
 
 /* ---- serving: continuous batching of render requests ----------------- */
 /*

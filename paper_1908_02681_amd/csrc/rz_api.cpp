@@ -3,6 +3,7 @@
 // kernel launches.  Nothing here allocates device memory or synchronises.
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
@@ -11,10 +12,20 @@
 
 #include "rz.h"
 #include "rz_internal.h"
+#include "rz_trace.h"
 
 namespace rz {
 
 static thread_local int g_last_hip = 0;
+
+bool roctx_on()
+{
+    static const bool on = [] {
+        const char *v = getenv("RZ_ROCTX");
+        return !(v && v[0] == '0' && v[1] == 0);
+    }();
+    return on;
+}
 
 int hip_fail(hipError_t e)
 {
@@ -193,6 +204,7 @@ int rasterize_atomicmin(const rz_points *pts, const rz_view *view, const rz_dept
                         uint32_t background, uint64_t *fb, uint32_t *img, uint32_t flags,
                         void *stream)
 {
+    Range range("rasterize_atomicmin");
     int rc = check_points(pts);
     if (rc)
         return rc;
@@ -218,6 +230,7 @@ int rasterize_hq_splat(const rz_points *pts, const rz_view *view, const rz_depth
                        const rz_hq_params *hq, uint32_t background, uint64_t *fb, uint64_t *acc,
                        uint32_t *img, uint32_t *status, uint32_t flags, void *stream)
 {
+    Range range("rasterize_hq_splat");
     int rc = check_points(pts);
     if (rc)
         return rc;
@@ -243,6 +256,7 @@ int rasterize_hq_splat(const rz_points *pts, const rz_view *view, const rz_depth
 int rz_hq_accumulate(const rz_points *pts, const rz_view *view, const rz_depth_map *depth,
                      const rz_hq_params *hq, const uint64_t *fb, uint64_t *acc, void *stream)
 {
+    Range range("rz_hq_accumulate");
     int rc = check_points(pts);
     if (rc)
         return rc;
@@ -264,6 +278,7 @@ int rasterize_points(const rz_points *pts, const rz_view *view, const rz_depth_m
                      uint64_t *fb, uint64_t *acc, uint32_t *img, uint32_t *status,
                      uint32_t flags, void *stream)
 {
+    Range range("rasterize_points");
     int rc = check_points(pts);
     if (rc)
         return rc;
@@ -365,6 +380,7 @@ const char *rz_error_string(int code)
     case RZ_EOVERFLOW: return "splat count overflow";
     case RZ_EBUDGET: return "request exceeds the memory budget";
     case RZ_ESTATE: return "object in the wrong state";
+    case RZ_EIO: return "file could not be written";
     default: return "unknown error";
     }
 }

@@ -11,7 +11,9 @@
 // The per-chunk arithmetic is the same code as the one-view kernels
 // (rz_device.h), so each view is bit-identical to its one-view call.
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -21,6 +23,7 @@
 #include "rz.h"
 #include "rz_device.h"
 #include "rz_internal.h"
+#include "rz_trace.h"
 
 namespace rz {
 
@@ -29,6 +32,8 @@ int make_proj(const rz_view *v, const rz_depth_map *dm, Proj *P);
 int check_hq(const rz_hq_params *hq, const Proj &P, uint32_t *num, uint32_t *den);
 int hip_fail(hipError_t e);
 Tune current_tune();
+int order_class_windows(const float *x, const float *y, const float *z, int64_t m, int nwin);
+int64_t order_sample_window();
 
 namespace {
 
@@ -297,6 +302,7 @@ struct rz_batch {
     rz_batch_opts opts;
     Tune tune;      // depth passes (opts.launch)
     Tune tune_hq;   // accumulate passes: opts.launch, or the autotuner's pick
+    int64_t total_px = 0;                 // pixels of all views
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -308,13 +314,20 @@ hipError_t enqueue(rz_batch *b, hipStream_t s)
 {
     const int32_t K = b->opts.views_per_group;
     hipError_t e = hipSuccess;
-    for (int32_t g = 0; g < b->nviews && e == hipSuccess; g += K)
-        e = mv_launch(false, b->any_pw, b->pts, b->d_raster + g, std::min(K, b->nviews - g),
-                      b->tune, s);
-    for (int32_t g = 0; g < b->nhq && e == hipSuccess; g += K)
-        e = mv_launch(true, b->hq_pw, b->pts, b->d_accum + g, std::min(K, b->nhq - g),
-                      b->tune_hq, s);
+    {
+        Range r("rz batch: depth passes");
+        for (int32_t g = 0; g < b->nviews && e == hipSuccess; g += K)
+            e = mv_launch(false, b->any_pw, b->pts, b->d_raster + g, std::min(K, b->nviews - g),
+                          b->tune, s);
+    }
+    if (b->nhq > 0) {
+        Range r("rz batch: splat accumulate passes");
+        for (int32_t g = 0; g < b->nhq && e == hipSuccess; g += K)
+            e = mv_launch(true, b->hq_pw, b->pts, b->d_accum + g, std::min(K, b->nhq - g),
+                          b->tune_hq, s);
+    }
     if (e == hipSuccess && b->resolve_blocks > 0) {
+        Range r("rz batch: resolve");
         hipLaunchKernelGGL(k_mv_resolve, dim3((uint32_t)b->resolve_blocks), dim3(256), 0, s,
                            b->d_resolve, b->nviews, b->opts.status);
         e = hipGetLastError();
@@ -330,6 +343,56 @@ void drop_graph(rz_batch *b)
         (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
+}
+
+// One run of the batch, then the checksum of every image (synchronous).
+hipError_t run_checksum(rz_batch *b, hipStream_t s, unsigned long long *sum)
+{
+    hipError_t e = enqueue(b, s);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(b->d_sum, 0, sizeof(unsigned long long), s);
+    if (e == hipSuccess && b->resolve_blocks > 0) {
+        hipLaunchKernelGGL(k_mv_checksum, dim3((uint32_t)b->resolve_blocks), dim3(256), 0, s,
+                           b->d_resolve, b->nviews, b->d_sum);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sum, b->d_sum, sizeof(*sum), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    return e;
+}
+
+// Median of reps timed runs (ms).
+hipError_t time_runs(rz_batch *b, hipStream_t s, int32_t reps, float *med)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess)
+        e = hipEventCreate(&e1);
+    std::vector<float> t;
+    for (int32_t r = 0; r < reps && e == hipSuccess; ++r) {
+        e = hipEventRecord(e0, s);
+        if (e == hipSuccess)
+            e = enqueue(b, s);
+        if (e == hipSuccess)
+            e = hipEventRecord(e1, s);
+        if (e == hipSuccess)
+            e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, e0, e1);
+        t.push_back(ms);
+    }
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    if (e == hipSuccess) {
+        std::sort(t.begin(), t.end());
+        *med = t[t.size() / 2];
+    }
+    return e;
 }
 
 int capture(rz_batch *b)
@@ -359,6 +422,49 @@ int capture(rz_batch *b)
         drop_graph(b);
         return hip_fail(e);
     }
+    return RZ_OK;
+}
+
+// The autotune cache key of a batch (see rz_batch_autotune_cached).
+int batch_key(rz_batch *b, char *key, size_t len)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess)
+        return hip_fail(e);
+    char arch[64];
+    size_t i = 0;
+    for (; i + 1 < sizeof(arch) && prop.gcnArchName[i] && prop.gcnArchName[i] != ':'; ++i)
+        arch[i] = prop.gcnArchName[i] == ' ' ? '_' : prop.gcnArchName[i];
+    arch[i] = 0;
+    if (!i)
+        strcpy(arch, "unknown");
+    // three windows of consecutive points, gathered on the host
+    const int64_t n = b->pts.n;
+    const int64_t m = std::min<int64_t>(n, order_sample_window());
+    const int64_t starts[3] = {0, (n - m) / 2, n - m};
+    std::vector<float> hx(3 * m), hy(3 * m), hz(3 * m);
+    for (int w = 0; w < 3 && m > 0 && e == hipSuccess; ++w) {
+        e = hipMemcpy(hx.data() + w * m, b->pts.x + starts[w], m * sizeof(float),
+                      hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            e = hipMemcpy(hy.data() + w * m, b->pts.y + starts[w], m * sizeof(float),
+                          hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            e = hipMemcpy(hz.data() + w * m, b->pts.z + starts[w], m * sizeof(float),
+                          hipMemcpyDeviceToHost);
+    }
+    if (e != hipSuccess)
+        return hip_fail(e);
+    const int order = order_class_windows(hx.data(), hy.data(), hz.data(), m, 3);
+    const int nlog = n > 0 ? (int)lround(log2((double)n)) : 0;
+    const int plog = b->total_px > 0 ? (int)lround(log2((double)b->total_px)) : 0;
+    const int hq8 = (int)((b->nhq * 8 + b->nviews / 2) / b->nviews);
+    snprintf(key, len, "%s n%d px%d v%d hq%d %s", arch, nlog, plog, b->nviews, hq8,
+             order == 0 ? "ordered" : "shuffled");
     return RZ_OK;
 }
 
@@ -448,6 +554,8 @@ int rz_batch_plan(const rz_points *pts, const rz_batch_view *views, int32_t nvie
     for (const MvView &m : raster)
         b->any_pw = b->any_pw || m.P.nr > 0;
     b->resolve_blocks = blocks;
+    for (const MvResolve &r : res)
+        b->total_px += r.npix;
     b->opts = o;
     b->tune = tune_of(o.launch);
     b->tune_hq = b->tune;
@@ -498,6 +606,7 @@ int rz_batch_capture(rz_batch *b)
 
 int rz_batch_run(rz_batch *b, void *stream)
 {
+    Range range("rz_batch_run");
     if (!b)
         return RZ_EINVAL;
     hipStream_t s = (hipStream_t)stream;
@@ -541,16 +650,14 @@ int rz_batch_autotune(rz_batch *b, void *stream, int32_t reps, rz_batch_opts *ch
             cands.push_back({k, sh[0], sh[1], 1, 1, sh[0], sh[1]});
     cands.push_back({4, 256, 16, 0, 1, 256, 16});
 
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipError_t e = hipEventCreate(&e0);
-    if (e == hipSuccess)
-        e = hipEventCreate(&e1);
+    hipError_t e = hipSuccess;
     unsigned long long ref = 0, sum = 0;
     bool have_ref = false;
     float best = 1e30f;
     rz_batch_opts best_opts = b->opts;
     Tune best_tune = b->tune, best_tune_hq = b->tune_hq;
     const rz_batch_opts saved = b->opts;
+    const Tune saved_tune = b->tune, saved_tune_hq = b->tune_hq;
     for (size_t ci = 0; ci < cands.size() && e == hipSuccess; ++ci) {
         const Cand &c = cands[ci];
         b->opts.views_per_group = c.k;
@@ -563,19 +670,7 @@ int rz_batch_autotune(rz_batch *b, void *stream, int32_t reps, rz_batch_opts *ch
         b->tune_hq.block = c.hq_block;
         b->tune_hq.ppt = c.hq_ppt;
         // correctness: one run, then the checksum of every image
-        e = enqueue(b, s);
-        if (e == hipSuccess)
-            e = hipMemsetAsync(b->d_sum, 0, sizeof(unsigned long long), s);
-        if (e == hipSuccess && b->resolve_blocks > 0) {
-            hipLaunchKernelGGL(k_mv_checksum, dim3((uint32_t)b->resolve_blocks), dim3(256), 0, s,
-                               b->d_resolve, b->nviews, b->d_sum);
-            e = hipGetLastError();
-        }
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(&sum, b->d_sum, sizeof(sum), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(s);
-        if (e != hipSuccess)
+        if ((e = run_checksum(b, s, &sum)) != hipSuccess)
             break;
         if (!have_ref) {
             ref = sum;
@@ -583,24 +678,9 @@ int rz_batch_autotune(rz_batch *b, void *stream, int32_t reps, rz_batch_opts *ch
         } else if (sum != ref) {
             continue;   // a candidate that renders other bits is never chosen
         }
-        std::vector<float> t;
-        for (int32_t r = 0; r < reps && e == hipSuccess; ++r) {
-            e = hipEventRecord(e0, s);
-            if (e == hipSuccess)
-                e = enqueue(b, s);
-            if (e == hipSuccess)
-                e = hipEventRecord(e1, s);
-            if (e == hipSuccess)
-                e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess)
-                e = hipEventElapsedTime(&ms, e0, e1);
-            t.push_back(ms);
-        }
-        if (e != hipSuccess)
+        float med = 0.f;
+        if ((e = time_runs(b, s, reps, &med)) != hipSuccess)
             break;
-        std::sort(t.begin(), t.end());
-        const float med = t[t.size() / 2];
         if (med < best) {
             best = med;
             best_opts = b->opts;
@@ -609,14 +689,10 @@ int rz_batch_autotune(rz_batch *b, void *stream, int32_t reps, rz_batch_opts *ch
             best_tune_hq = b->tune_hq;
         }
     }
-    if (e0)
-        (void)hipEventDestroy(e0);
-    if (e1)
-        (void)hipEventDestroy(e1);
     if (e != hipSuccess) {
         b->opts = saved;
-        b->tune = tune_of(saved.launch);
-        b->tune_hq = b->tune;
+        b->tune = saved_tune;
+        b->tune_hq = saved_tune_hq;
         return hip_fail(e);
     }
     b->opts = best_opts;
@@ -633,6 +709,86 @@ int rz_batch_autotune(rz_batch *b, void *stream, int32_t reps, rz_batch_opts *ch
     if (best_ms)
         *best_ms = best;
     return RZ_OK;
+}
+
+int rz_batch_autotune_cached(rz_batch *b, void *stream, int32_t reps, const char *cache_path,
+                             rz_batch_opts *chosen, float *best_ms, int32_t *hit,
+                             char *key_out, int32_t key_len)
+{
+    if (!b || !cache_path || reps < 1 || reps > 100 || (key_out && key_len < 1))
+        return RZ_EINVAL;
+    if (hit)
+        *hit = 0;
+    hipStream_t s = (hipStream_t)stream;
+    char key[160];
+    int rc = batch_key(b, key, sizeof(key));
+    if (rc)
+        return rc;
+    if (key_out) {
+        strncpy(key_out, key, (size_t)key_len - 1);
+        key_out[key_len - 1] = 0;
+    }
+    rz_tune_entry ent;
+    memset(&ent, 0, sizeof(ent));
+    const int found = rz_tune_cache_lookup(cache_path, key, &ent);
+    if (found < 0)
+        return found;
+    if (found == 1) {
+        const bool had_graph = b->exec != nullptr;
+        drop_graph(b);
+        const rz_batch_opts saved = b->opts;
+        const Tune saved_tune = b->tune, saved_tune_hq = b->tune_hq;
+        // the library defaults (the autotuner's first candidate) give the
+        // reference checksum; the cached options must render the same bits
+        b->opts.views_per_group = 1;
+        b->tune = Tune();
+        b->tune_hq = kHqTune;
+        unsigned long long ref = 0, sum = 0;
+        hipError_t e = run_checksum(b, s, &ref);
+        b->opts.views_per_group = ent.views_per_group;
+        b->tune = tune_of(ent.depth);
+        b->tune_hq = tune_of(ent.accum);
+        if (e == hipSuccess)
+            e = run_checksum(b, s, &sum);
+        float med = 0.f;
+        if (e == hipSuccess && sum == ref)
+            e = time_runs(b, s, reps, &med);
+        if (e != hipSuccess || sum != ref) {
+            b->opts = saved;
+            b->tune = saved_tune;
+            b->tune_hq = saved_tune_hq;
+            if (e != hipSuccess) {
+                if (had_graph)
+                    (void)capture(b);
+                return hip_fail(e);
+            }
+            if (had_graph && (rc = capture(b)))
+                return rc;
+            // other bits under the cached options: fall through to the search
+        } else {
+            b->opts.launch = ent.depth;
+            b->opts.use_graph = had_graph ? 1 : 0;
+            if (had_graph && (rc = capture(b)))
+                return rc;
+            if (chosen)
+                *chosen = b->opts;
+            if (best_ms)
+                *best_ms = med;
+            if (hit)
+                *hit = 1;
+            return RZ_OK;
+        }
+    }
+    float ms = 0.f;
+    if ((rc = rz_batch_autotune(b, stream, reps, chosen, &ms)))
+        return rc;
+    if (best_ms)
+        *best_ms = ms;
+    ent.views_per_group = b->opts.views_per_group;
+    ent.depth = launch_of(b->tune);
+    ent.accum = launch_of(b->tune_hq);
+    ent.ms = ms;
+    return rz_tune_cache_store(cache_path, key, &ent);
 }
 
 int rz_batch_destroy(rz_batch *b)

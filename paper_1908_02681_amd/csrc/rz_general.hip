@@ -17,6 +17,7 @@
 #include "rz.h"
 #include "rz_device.h"
 #include "rz_internal.h"
+#include "rz_trace.h"
 
 namespace rz {
 namespace {
@@ -277,6 +278,7 @@ bool aligned16(const Pts &p)
 hipError_t launch_raster_points(const Pts &p, const Proj &P, int32_t k, uint64_t *fb,
                                 hipStream_t s)
 {
+    Range r("rz depth pass (k x k points)");
     if (p.n == 0)
         return hipSuccess;
     const dim3 grid((uint32_t)((p.n + kGenBlock * kGenPpt - 1) / (kGenBlock * kGenPpt)));
@@ -290,6 +292,7 @@ hipError_t launch_raster_points(const Pts &p, const Proj &P, int32_t k, uint64_t
 hipError_t launch_hq_points(const Pts &p, const Proj &P, int32_t k, uint32_t eps_num,
                             uint32_t eps_den, const uint64_t *fb, uint64_t *acc, hipStream_t s)
 {
+    Range r("rz splat accumulate pass (k x k points)");
     if (p.n == 0)
         return hipSuccess;
     const dim3 grid((uint32_t)((p.n + kGenBlock * kGenPpt - 1) / (kGenBlock * kGenPpt)));

@@ -11,6 +11,7 @@
 #include "rz.h"
 #include "rz_device.h"
 #include "rz_internal.h"
+#include "rz_trace.h"
 
 namespace rz {
 namespace {
@@ -289,6 +290,7 @@ hipError_t raster_min_zk(const Pts &p, const Proj &P, uint64_t *fb, const Tune &
 hipError_t launch_raster_min(const Pts &p, const Proj &P, uint64_t *fb, const Tune &t,
                              hipStream_t s)
 {
+    Range r("rz depth pass");
     if (p.n == 0)
         return hipSuccess;
     if (P.zkind != 0) {
@@ -310,6 +312,7 @@ hipError_t launch_raster_min(const Pts &p, const Proj &P, uint64_t *fb, const Tu
 hipError_t launch_hq_accum(const Pts &p, const Proj &P, uint32_t num, uint32_t den,
                            const uint64_t *fb, uint64_t *acc, const Tune &t, hipStream_t s)
 {
+    Range r("rz splat accumulate pass");
     if (p.n == 0)
         return hipSuccess;
     switch (t.ppt) {
@@ -323,6 +326,7 @@ hipError_t launch_hq_accum(const Pts &p, const Proj &P, uint32_t num, uint32_t d
 hipError_t launch_resolve_min(uint64_t *fb, int64_t npix, uint32_t bg, uint32_t *img,
                               hipStream_t s)
 {
+    Range r("rz resolve (atomicMin)");
     if (npix == 0)
         return hipSuccess;
     const uint64_t clear = kDepthOnes | ((uint64_t)bg & kRgbMask);
@@ -336,6 +340,7 @@ hipError_t launch_resolve_min(uint64_t *fb, int64_t npix, uint32_t bg, uint32_t 
 hipError_t launch_resolve_hq(uint64_t *fb, uint64_t *acc, int64_t npix, uint32_t bg,
                              uint32_t *img, uint32_t *status, hipStream_t s)
 {
+    Range r("rz resolve (splatting)");
     if (npix == 0)
         return hipSuccess;
     const uint64_t clear = kDepthOnes | ((uint64_t)bg & kRgbMask);
@@ -346,6 +351,7 @@ hipError_t launch_resolve_hq(uint64_t *fb, uint64_t *acc, int64_t npix, uint32_t
 
 hipError_t launch_clear(uint64_t *fb, uint64_t *acc, int64_t npix, uint32_t bg, hipStream_t s)
 {
+    Range r("rz clear");
     if (npix == 0)
         return hipSuccess;
     const uint64_t clear = kDepthOnes | ((uint64_t)bg & kRgbMask);

@@ -8,6 +8,7 @@
 
 #include "rz.h"
 #include "rz_internal.h"
+#include "rz_trace.h"
 
 namespace rz {
 
@@ -66,6 +67,7 @@ extern "C" {
 
 int rz_merge_min(uint64_t *dst, const uint64_t *src, int64_t npix, void *stream)
 {
+    Range range("rz_merge_min");
     if (npix < 0)
         return RZ_EINVAL;
     if (npix == 0)
@@ -82,6 +84,7 @@ int rz_merge_min(uint64_t *dst, const uint64_t *src, int64_t npix, void *stream)
 
 int rz_merge_sum(uint64_t *dst, const uint64_t *src, int64_t npix, void *stream)
 {
+    Range range("rz_merge_sum");
     if (npix < 0)
         return RZ_EINVAL;
     if (npix == 0)

@@ -38,6 +38,7 @@
 
 #include "rz.h"
 #include "rz_internal.h"
+#include "rz_trace.h"
 
 namespace rz {
 
@@ -219,6 +220,8 @@ void on_device_done(void *p)
 // Enqueues the request's kernels; returns an RZ_* code.
 int launch(rz_server *s, Req *r)
 {
+    Range range(r->r.mode == RZ_MODE_HQ ? "rz_server request (splatting)"
+                                        : "rz_server request (atomicMin)");
     hipStream_t st = s->streams[r->stream];
     uint64_t *fb = (uint64_t *)(s->dmem + r->off);
     uint64_t *acc = r->acc_bytes ? (uint64_t *)(s->dmem + r->off + r->fb_bytes) : nullptr;

@@ -34,6 +34,7 @@
 #include "rz.h"
 #include "rz_device.h"
 #include "rz_internal.h"
+#include "rz_trace.h"
 
 namespace rz {
 
@@ -561,6 +562,7 @@ void launch_count_scatter(const Pts &p, const Proj &P, const Layout &L, uint32_t
 hipError_t sort_passes(const Pts &p, const Proj &P, const Layout &L, char *ws, bool vec,
                        hipStream_t s)
 {
+    Range r("rz sort: count, offsets, scatter");
     uint32_t *ccounts = (uint32_t *)(ws + L.ccounts);
     uint32_t *btotal = (uint32_t *)(ws + L.btotal);
     uint32_t *bstart = (uint32_t *)(ws + L.bstart);
@@ -602,6 +604,7 @@ int rasterize_sorted(const rz_points *pts, const rz_view *view, const rz_depth_m
                      uint32_t *img, uint32_t *status, void *workspace, int64_t workspace_bytes,
                      uint32_t flags, void *stream)
 {
+    Range range("rasterize_sorted");
     int rc = check_points(pts);
     if (rc)
         return rc;
@@ -637,11 +640,13 @@ int rasterize_sorted(const rz_points *pts, const rz_view *view, const rz_depth_m
         const uint32_t *bchunk = (const uint32_t *)(ws + L.bchunk);
         const dim3 grid((uint32_t)L.chunks_max);   // workgroups past the last item exit
         if (e == hipSuccess) {
+            Range r("rz sort: bucket minima");
             hipLaunchKernelGGL(k_sort_raster, grid, dim3(kRasterBlock), 0, s, keys, lps, bstart,
                                bchunk, fb, L.ntx, L.nb, L.chunk, P.width);
             e = hipGetLastError();
         }
         if (e == hipSuccess && hq) {
+            Range r("rz sort: bucket sums");
             if (P.nr)
                 hipLaunchKernelGGL((k_sort_accum<true>), grid, dim3(kAccumBlock), 0, s, keys,
                                    lps, bstart, bchunk, P, num, den, fb, acc, L.ntx, L.nb,

@@ -23,6 +23,7 @@ RZ_EHIP = -3
 RZ_EOVERFLOW = -4
 RZ_EBUDGET = -5
 RZ_ESTATE = -6
+RZ_EIO = -7
 RZ_KEEP_KEYS = 1
 RZ_STATUS_HQ_OVERFLOW = 1
 RZ_CHECK_ESTIMATE_ONLY = 1
@@ -82,6 +83,11 @@ class rz_batch_view(ctypes.Structure):
 class rz_batch_opts(ctypes.Structure):
     _fields_ = [("views_per_group", c_int32), ("launch", rz_launch), ("use_graph", c_int32),
                 ("status", c_void_p)]
+
+
+class rz_tune_entry(ctypes.Structure):
+    _fields_ = [("views_per_group", c_int32), ("depth", rz_launch), ("accum", rz_launch),
+                ("ms", ctypes.c_float)]
 
 
 class rz_server_opts(ctypes.Structure):
@@ -147,6 +153,12 @@ SIGNATURES = {
     "rz_batch_autotune": ([c_void_p, c_void_p, c_int32, P(rz_batch_opts), P(ctypes.c_float)],
                           ctypes.c_int),
     "rz_batch_get_opts": ([c_void_p, P(rz_batch_opts)], ctypes.c_int),
+    "rz_batch_autotune_cached": ([c_void_p, c_void_p, c_int32, ctypes.c_char_p, P(rz_batch_opts),
+                                  P(ctypes.c_float), P(c_int32), ctypes.c_char_p, c_int32],
+                                 ctypes.c_int),
+    "rz_order_class_host": ([c_void_p, c_void_p, c_void_p, c_int64], ctypes.c_int),
+    "rz_tune_cache_lookup": ([ctypes.c_char_p, ctypes.c_char_p, P(rz_tune_entry)], ctypes.c_int),
+    "rz_tune_cache_store": ([ctypes.c_char_p, ctypes.c_char_p, P(rz_tune_entry)], ctypes.c_int),
     "rz_batch_destroy": ([c_void_p], ctypes.c_int),
     "rz_server_create": ([P(rz_server_opts), P(c_void_p)], ctypes.c_int),
     "rz_server_add_cloud": ([c_void_p, P(rz_points), P(c_int32)], ctypes.c_int),
@@ -570,6 +582,42 @@ def get_launch() -> dict:
     return {f: getattr(l, f) for f, _ in rz_launch._fields_}
 
 
+def order_class(x, y, z) -> str:
+    """Point order class of host float32 arrays ("ordered" or "shuffled"), as
+    the batch autotune cache keys it (rz_order_class_host)."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (x, y, z)]
+    n = arrs[0].size
+    if any(a.size != n for a in arrs):
+        raise RzError(RZ_EINVAL, "x, y and z must have the same length")
+    rc = load().rz_order_class_host(*(a.ctypes.data_as(c_void_p) for a in arrs), n)
+    if rc < 0:
+        _check(rc, "rz_order_class_host")
+    return "ordered" if rc == 0 else "shuffled"
+
+
+def _entry_dict(e: rz_tune_entry) -> dict:
+    return {"views_per_group": e.views_per_group,
+            "depth": {f: getattr(e.depth, f) for f, _ in rz_launch._fields_},
+            "accum": {f: getattr(e.accum, f) for f, _ in rz_launch._fields_},
+            "ms": float(e.ms)}
+
+
+def tune_cache_lookup(path, key):
+    """The cached entry for `key` as a dict, or None (rz_tune_cache_lookup)."""
+    e = rz_tune_entry()
+    rc = load().rz_tune_cache_lookup(os.fsencode(path), key.encode(), ctypes.byref(e))
+    if rc < 0:
+        _check(rc, "rz_tune_cache_lookup")
+    return _entry_dict(e) if rc == 1 else None
+
+
+def tune_cache_store(path, key, views_per_group, depth, accum, ms):
+    """Stores one entry (depth / accum: dicts of rz_launch fields)."""
+    e = rz_tune_entry(views_per_group, rz_launch(**depth), rz_launch(**accum), ms)
+    _check(load().rz_tune_cache_store(os.fsencode(path), key.encode(), ctypes.byref(e)),
+           "rz_tune_cache_store")
+
+
 # --------------------------------------------------------------------------
 # host-side views of results
 # --------------------------------------------------------------------------
@@ -669,6 +717,19 @@ class Batch:
         _check(load().rz_batch_autotune(self._h, _stream(stream), int(reps), ctypes.byref(o),
                                         ctypes.byref(ms)), "rz_batch_autotune")
         return _opts_dict(o), float(ms.value)
+
+    def autotune_cached(self, path, reps=3, stream=None):
+        """autotune() through the cache file at `path` (rz_batch_autotune_cached):
+        returns (options, ms, hit, key)."""
+        o = rz_batch_opts()
+        ms = ctypes.c_float()
+        hit = c_int32()
+        key = ctypes.create_string_buffer(160)
+        _check(load().rz_batch_autotune_cached(self._h, _stream(stream), int(reps),
+                                               os.fsencode(path), ctypes.byref(o),
+                                               ctypes.byref(ms), ctypes.byref(hit), key, 160),
+               "rz_batch_autotune_cached")
+        return _opts_dict(o), float(ms.value), bool(hit.value), key.value.decode()
 
     def opts(self) -> dict:
         o = rz_batch_opts()

@@ -135,6 +135,44 @@ def test_autotune_keeps_bits(rz, scene, expected):
     b.close()
 
 
+def test_autotune_cache_round_trip(rz, scene, expected, tmp_path):
+    """The first cached autotune searches and stores its choice under the
+    batch's key; a second batch of the same class finds it, checks it against
+    the default options' checksum and uses it; both render the oracle's bits."""
+    cloud, views, modes, bgs = scene
+    path = str(tmp_path / "tune.txt")
+    pts = rz.Points.from_cloud(cloud)
+    b = rz.Batch(pts, views, modes, backgrounds=bgs, use_graph=True)
+    opts, ms, hit, key = b.autotune_cached(path, reps=1)
+    say(f"[tune-cache] miss: {key} -> {opts} {ms:.3f} ms")
+    assert not hit and ms > 0
+    words = key.split(" ")
+    assert len(words) == 6 and words[5] == "ordered" and words[3] == f"v{len(views)}"
+    assert words[1] == f"n{round(np.log2(cloud.n))}"
+    ent = rz.tune_cache_lookup(path, key)
+    assert ent is not None and ent["views_per_group"] == opts["views_per_group"]
+    assert ent["depth"] == {f: opts[f] for f in ("block", "ppt", "early_out", "xcd_remap", "bin")}
+    b.run()
+    check_images(rz, b, expected, "after the cached search")
+    b.close()
+    b2 = rz.Batch(pts, views, modes, backgrounds=bgs, use_graph=True)
+    opts2, ms2, hit2, key2 = b2.autotune_cached(path, reps=1)
+    say(f"[tune-cache] hit={hit2}: {opts2} {ms2:.3f} ms")
+    assert hit2 and key2 == key and opts2 == opts and ms2 > 0
+    b2.run()
+    check_images(rz, b2, expected, "with the cached options")
+    b2.close()
+    # the same cloud shuffled: another order class, so another key (a miss)
+    perm = np.random.default_rng(9).permutation(cloud.n)
+    sh = rz.Points.from_numpy(cloud.x[perm], cloud.y[perm], cloud.z[perm], cloud.rgb[perm])
+    b3 = rz.Batch(sh, views, modes, backgrounds=bgs)
+    _, _, hit3, key3 = b3.autotune_cached(path, reps=1)
+    assert not hit3 and key3.endswith(" shuffled") and key3.split(" ")[:5] == words[:5]
+    b3.run()
+    check_images(rz, b3, expected, "shuffled, after the cached search")
+    b3.close()
+
+
 def test_batch_status_flags_overflow(rz):
     """The fused resolve reports splat counts beyond the exact range like the
     one-view call does."""

@@ -62,7 +62,7 @@ def _build_driver(tmp_path, name, flags):
            "-D__HIP_PLATFORM_AMD__", f"-I{ROOT}/include", f"-I{CSRC}", f"-I{ROCM}/include",
            os.path.join(ROOT, "tests", "sanitize", "serve_stress.cpp"),
            os.path.join(CSRC, "rz_serve.cpp"), os.path.join(CSRC, "rz_api.cpp"),
-           f"-L{ROCM}/lib", "-lamdhip64", f"-Wl,-rpath,{ROCM}/lib", "-lpthread", "-o", exe]
+           f"-L{ROCM}/lib", "-lamdhip64", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM}/lib", "-lpthread", "-o", exe]
     subprocess.run(cmd, check=True, capture_output=True, text=True)
     return exe
 
