@@ -306,7 +306,10 @@ int rz_resolve_hq(uint64_t *fb, uint64_t *acc, int64_t npix,
  *   bin        how fragments are merged before the global atomics:
  *              0: none (direct atomics); 1: one LDS tile per workgroup (when
  *              its fragments fall in a small screen rectangle); 2: one LDS
- *              tile per wave (no workgroup barrier).
+ *              tile per wave (no workgroup barrier), 8 KiB; 3: the same with
+ *              a 2 KiB tile (more waves per SIMD when registers allow them;
+ *              a wave whose fragments span more than 256 pixels, 128 when
+ *              splatting, takes the direct atomics instead).
  */
 typedef struct rz_launch {
     int32_t block;

@@ -345,7 +345,7 @@ int rz_set_launch(const rz_launch *l)
         return RZ_EINVAL;
     if (!(l->ppt == 4 || l->ppt == 8 || l->ppt == 16))
         return RZ_EINVAL;
-    if ((l->early_out & ~1) || (l->xcd_remap & ~1) || l->bin < 0 || l->bin > 2)
+    if ((l->early_out & ~1) || (l->xcd_remap & ~1) || l->bin < 0 || l->bin > 3)
         return RZ_EINVAL;
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune.block = l->block;

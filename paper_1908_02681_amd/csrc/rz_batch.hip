@@ -67,7 +67,8 @@ struct MvResolve {
 // once and stay in registers while each view is rasterized in turn.
 template <int PPT, bool VEC, bool XCD, int BIN, bool PW>
 __global__ void __launch_bounds__(512) k_mv_raster_min(Pts p, const MvView *__restrict__ views,
-                                                       int32_t nv, int64_t nchunks)
+                                                       int32_t nv, int64_t nchunks,
+                                                       uint32_t words)
 {
     __shared__ uint64_t s_tile[BIN == kBinBlock ? kTileMin : 1];
     __shared__ uint32_t s_box[kMaxWaves][4];
@@ -87,7 +88,7 @@ __global__ void __launch_bounds__(512) k_mv_raster_min(Pts p, const MvView *__re
         const Proj P = views[k].P;
         if (BIN == kBinWave) {
             raster_chunk_wave<PPT, PW>(P, views[k].fb, x, y, z, c, in,
-                                   s_waves + (threadIdx.x >> 6) * kWaveTileWords);
+                                       s_waves + (threadIdx.x >> 6) * words, words);
         } else {
             if (BIN == kBinBlock && k > 0)
                 __syncthreads();   // previous view's tile fully flushed
@@ -100,7 +101,8 @@ __global__ void __launch_bounds__(512) k_mv_raster_min(Pts p, const MvView *__re
 // Accumulate passes of the splatting views views[0 .. nv) over one chunk.
 template <int PPT, bool VEC, bool XCD, int BIN, bool PW>
 __global__ void __launch_bounds__(512) k_mv_hq_accum(Pts p, const MvView *__restrict__ views,
-                                                     int32_t nv, int64_t nchunks)
+                                                     int32_t nv, int64_t nchunks,
+                                                     uint32_t words)
 {
     __shared__ uint64_t s_tile[BIN == kBinBlock ? 2 * kTileHq : 2];
     __shared__ uint32_t s_box[kMaxWaves][4];
@@ -121,7 +123,7 @@ __global__ void __launch_bounds__(512) k_mv_hq_accum(Pts p, const MvView *__rest
         if (BIN == kBinWave) {
             accum_chunk_wave<PPT, PW>(P, views[k].eps_num, views[k].eps_den, views[k].fb,
                                       views[k].acc, x, y, z, c, in,
-                                      s_waves + (threadIdx.x >> 6) * kWaveTileWords);
+                                      s_waves + (threadIdx.x >> 6) * words, words);
         } else {
             if (BIN == kBinBlock && k > 0)
                 __syncthreads();
@@ -196,20 +198,21 @@ hipError_t mv_launch_ppt(bool hq, bool pw, const Pts &p, const MvView *views, in
 {
     const int64_t nchunks = (p.n + (int64_t)t.block * PPT - 1) / ((int64_t)t.block * PPT);
     const int64_t grid = XCD ? (nchunks + kXcds - 1) / kXcds * kXcds : nchunks;
+    const uint32_t words = wave_tile_words(t.bin);
     const size_t lds =
-        BIN == kBinWave ? (size_t)(t.block / 64) * kWaveTileWords * sizeof(uint64_t) : 0;
+        BIN == kBinWave ? (size_t)(t.block / 64) * words * sizeof(uint64_t) : 0;
     if (hq && pw)
         hipLaunchKernelGGL((k_mv_hq_accum<PPT, VEC, XCD, BIN, true>), dim3((uint32_t)grid),
-                           dim3(t.block), lds, s, p, views, nv, nchunks);
+                           dim3(t.block), lds, s, p, views, nv, nchunks, words);
     else if (hq)
         hipLaunchKernelGGL((k_mv_hq_accum<PPT, VEC, XCD, BIN, false>), dim3((uint32_t)grid),
-                           dim3(t.block), lds, s, p, views, nv, nchunks);
+                           dim3(t.block), lds, s, p, views, nv, nchunks, words);
     else if (pw)
         hipLaunchKernelGGL((k_mv_raster_min<PPT, VEC, XCD, BIN, true>), dim3((uint32_t)grid),
-                           dim3(t.block), lds, s, p, views, nv, nchunks);
+                           dim3(t.block), lds, s, p, views, nv, nchunks, words);
     else
         hipLaunchKernelGGL((k_mv_raster_min<PPT, VEC, XCD, BIN, false>), dim3((uint32_t)grid),
-                           dim3(t.block), lds, s, p, views, nv, nchunks);
+                           dim3(t.block), lds, s, p, views, nv, nchunks, words);
     return hipGetLastError();
 }
 
@@ -219,7 +222,9 @@ hipError_t mv_launch_bin(bool hq, bool pw, const Pts &p, const MvView *views, in
 {
     switch (t.bin) {
     case kBinBlock: return mv_launch_ppt<PPT, VEC, XCD, kBinBlock>(hq, pw, p, views, nv, t, s);
-    case kBinWave: return mv_launch_ppt<PPT, VEC, XCD, kBinWave>(hq, pw, p, views, nv, t, s);
+    case kBinWave:
+    case kBinWaveSmall:
+        return mv_launch_ppt<PPT, VEC, XCD, kBinWave>(hq, pw, p, views, nv, t, s);
     default: return mv_launch_ppt<PPT, VEC, XCD, kBinNone>(hq, pw, p, views, nv, t, s);
     }
 }
@@ -255,7 +260,7 @@ int check_launch(const rz_launch &l)
         return RZ_EINVAL;
     if (!(l.ppt == 4 || l.ppt == 8 || l.ppt == 16))
         return RZ_EINVAL;
-    if ((l.early_out & ~1) || (l.xcd_remap & ~1) || l.bin < 0 || l.bin > 2)
+    if ((l.early_out & ~1) || (l.xcd_remap & ~1) || l.bin < 0 || l.bin > kBinWaveSmall)
         return RZ_EINVAL;
     return RZ_OK;
 }
@@ -648,6 +653,12 @@ int rz_batch_autotune(rz_batch *b, void *stream, int32_t reps, rz_batch_opts *ch
     for (int32_t k : ks)
         for (auto &sh : shapes)
             cands.push_back({k, sh[0], sh[1], 1, 1, sh[0], sh[1]});
+    // the small per-wave tile: more waves per SIMD for the leaner shapes
+    for (int32_t k : ks) {
+        cands.push_back({k, 64, 16, kBinWaveSmall, 0, 128, 8});
+        for (auto &sh : shapes)
+            cands.push_back({k, sh[0], sh[1], kBinWaveSmall, 0, sh[0], sh[1]});
+    }
     cands.push_back({4, 256, 16, 0, 1, 256, 16});
 
     hipError_t e = hipSuccess;

@@ -40,9 +40,21 @@ constexpr uint32_t kTileHq = 2048;           // workgroup tile of the accumulate
 constexpr uint32_t kWaveTileWords = 1024;    // per-wave tile: 8 KiB of LDS
 constexpr uint32_t kWaveTileMin = kWaveTileWords;        // pixels (one key each)
 constexpr uint32_t kWaveTileHq = kWaveTileWords / 2;     // pixels (two sums each)
+// The small per-wave tile (2 KiB): a quarter of the LDS per wave, so that
+// LDS no longer caps the waves per SIMD of kernels with few registers
+// (measured: the multi-view kernels at 4 points per thread).
+constexpr uint32_t kWaveTileSmallWords = 256;
 
-// Tiling modes of the point kernels.
-enum : int { kBinNone = 0, kBinBlock = 1, kBinWave = 2 };
+// Tiling modes of the point kernels.  kBinWaveSmall is kBinWave with the
+// small tile: the kernels take the tile size as an argument, so both modes
+// share the kBinWave code.
+enum : int { kBinNone = 0, kBinBlock = 1, kBinWave = 2, kBinWaveSmall = 3 };
+
+// Words of one wave's tile in a per-wave tiling mode.
+__host__ __device__ constexpr uint32_t wave_tile_words(int bin)
+{
+    return bin == kBinWaveSmall ? kWaveTileSmallWords : kWaveTileWords;
+}
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -728,13 +740,14 @@ __device__ __forceinline__ Box wave_box_live_min(const uint32_t (&px)[PPT],
 
 // Depth pass over one chunk with a private LDS tile per wave: like
 // raster_chunk with BIN, but every wave gathers its own 64 * PPT fragments
-// in its own 8 KiB slice (w_tile) and flushes it, so no workgroup barrier
-// is needed.  Same result bits as raster_chunk.
+// in its own slice of `words` keys (w_tile) and flushes it, so no workgroup
+// barrier is needed.  Same result bits as raster_chunk, for any tile size.
 template <int PPT, bool PW, int ZK = 0>
 __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__restrict__ fb,
                                                   const float (&x)[PPT], const float (&y)[PPT],
                                                   const float (&z)[PPT], const uint32_t (&c)[PPT],
-                                                  const bool (&in)[PPT], uint64_t *w_tile)
+                                                  const bool (&in)[PPT], uint64_t *w_tile,
+                                                  uint32_t words)
 {
     uint32_t px[PPT], py[PPT], pix[PPT];
     uint64_t key[PPT];
@@ -756,7 +769,7 @@ __device__ __forceinline__ void raster_chunk_wave(const Proj &P, uint64_t *__res
     if (box.x0 <= box.x1) {
         bw = box.x1 - box.x0 + 1;
         bh = box.y1 - box.y0 + 1;
-        tiled = (uint64_t)bw * bh <= kWaveTileMin;
+        tiled = (uint64_t)bw * bh <= words;
     }
     if (tiled) {
         // the box bounds every live fragment of the wave, so all of them
@@ -935,8 +948,9 @@ __device__ __forceinline__ void accum_chunk(const Proj &P, uint32_t eps_num, uin
     }
 }
 
-// Accumulate pass over one chunk with a private LDS tile per wave (see
-// raster_chunk_wave).  Same result bits as accum_chunk.
+// Accumulate pass over one chunk with a private LDS tile per wave of
+// `words` words, two per pixel (see raster_chunk_wave).  Same result bits as
+// accum_chunk.
 template <int PPT, bool PW>
 __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num,
                                                  uint32_t eps_den,
@@ -944,7 +958,8 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
                                                  uint64_t *__restrict__ acc,
                                                  const float (&x)[PPT], const float (&y)[PPT],
                                                  const float (&z)[PPT], const uint32_t (&c)[PPT],
-                                                 const bool (&in)[PPT], uint64_t *w_tile)
+                                                 const bool (&in)[PPT], uint64_t *w_tile,
+                                                 uint32_t words)
 {
     uint32_t px[PPT], py[PPT], pix[PPT];
     uint64_t q[PPT];
@@ -1026,7 +1041,7 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
     if (box.x0 <= box.x1) {
         bw = box.x1 - box.x0 + 1;
         bh = box.y1 - box.y0 + 1;
-        tiled = (uint64_t)bw * bh <= kWaveTileHq;
+        tiled = (uint64_t)bw * bh <= words / 2;
     }
     if (tiled) {
         // every accepted fragment of the wave lies in the box (see

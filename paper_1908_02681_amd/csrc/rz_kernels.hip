@@ -22,11 +22,11 @@ using namespace dev;
 // blockDim * PPT consecutive points.
 template <int PPT, bool VEC, bool EARLY, bool XCD, int BIN, bool PW>
 __global__ void __launch_bounds__(512) k_raster_min(Pts p, Proj P, uint64_t *__restrict__ fb,
-                                                    int64_t nchunks)
+                                                    int64_t nchunks, uint32_t words)
 {
     __shared__ uint64_t s_tile[BIN == kBinBlock ? kTileMin : 1];
     __shared__ uint32_t s_box[kMaxWaves][4];
-    extern __shared__ uint64_t s_waves[];   // kBinWave: kWaveTileWords per wave
+    extern __shared__ uint64_t s_waves[];   // kBinWave: `words` per wave
     const int64_t chunk = chunk_index<XCD>();
     if (chunk >= nchunks)
         return;
@@ -34,14 +34,14 @@ __global__ void __launch_bounds__(512) k_raster_min(Pts p, Proj P, uint64_t *__r
     uint32_t c[PPT];
     bool in[PPT];
     const int64_t base = chunk * (int64_t)blockDim.x * PPT;
-    uint64_t *w_tile = s_waves + (threadIdx.x >> 6) * kWaveTileWords;
+    uint64_t *w_tile = s_waves + (threadIdx.x >> 6) * words;
     // no per-point bounds flags: points past the end load as NaN and are culled
     load_points_nan<PPT, VEC>(p, base, x, y, z, c);
 #pragma unroll
     for (int j = 0; j < PPT; ++j)
         in[j] = true;
     if (BIN == kBinWave)
-        raster_chunk_wave<PPT, PW>(P, fb, x, y, z, c, in, w_tile);
+        raster_chunk_wave<PPT, PW>(P, fb, x, y, z, c, in, w_tile, words);
     else
         raster_chunk<PPT, EARLY, BIN == kBinBlock, PW>(P, fb, x, y, z, c, in, s_tile, s_box);
 }
@@ -65,7 +65,8 @@ __global__ void __launch_bounds__(512) k_raster_min_zk(Pts p, Proj P, uint64_t *
     for (int j = 0; j < PPT; ++j)
         in[j] = true;
     raster_chunk_wave<PPT, false, ZK>(P, fb, x, y, z, c, in,
-                                      s_waves + (threadIdx.x >> 6) * kWaveTileWords);
+                                      s_waves + (threadIdx.x >> 6) * kWaveTileWords,
+                                      kWaveTileWords);
 }
 
 // Accumulation pass of section 2.2 for one view.
@@ -73,7 +74,8 @@ template <int PPT, bool VEC, bool XCD, int BIN, bool PW>
 __global__ void __launch_bounds__(512) k_hq_accum(Pts p, Proj P, uint32_t eps_num,
                                                   uint32_t eps_den,
                                                   const uint64_t *__restrict__ fb,
-                                                  uint64_t *__restrict__ acc, int64_t nchunks)
+                                                  uint64_t *__restrict__ acc, int64_t nchunks,
+                                                  uint32_t words)
 {
     __shared__ uint64_t s_tile[BIN == kBinBlock ? 2 * kTileHq : 2];
     __shared__ uint32_t s_box[kMaxWaves][4];
@@ -85,13 +87,13 @@ __global__ void __launch_bounds__(512) k_hq_accum(Pts p, Proj P, uint32_t eps_nu
     uint32_t c[PPT];
     bool in[PPT];
     const int64_t base = chunk * (int64_t)blockDim.x * PPT;
-    uint64_t *w_tile = s_waves + (threadIdx.x >> 6) * kWaveTileWords;
+    uint64_t *w_tile = s_waves + (threadIdx.x >> 6) * words;
     load_points_nan<PPT, VEC>(p, base, x, y, z, c);
 #pragma unroll
     for (int j = 0; j < PPT; ++j)
         in[j] = true;
     if (BIN == kBinWave)
-        accum_chunk_wave<PPT, PW>(P, eps_num, eps_den, fb, acc, x, y, z, c, in, w_tile);
+        accum_chunk_wave<PPT, PW>(P, eps_num, eps_den, fb, acc, x, y, z, c, in, w_tile, words);
     else
         accum_chunk<PPT, BIN == kBinBlock, PW>(P, eps_num, eps_den, fb, acc, x, y, z, c, in,
                                                s_tile, s_box);
@@ -169,10 +171,12 @@ bool aligned16(const void *ptr) { return ((uintptr_t)ptr & 15u) == 0; }
 
 int64_t blocks_for(int64_t n, int64_t per) { return (n + per - 1) / per; }
 
-// Dynamic LDS of a launch: the per-wave tiles of kBinWave.
+// Dynamic LDS of a launch: the per-wave tiles of kBinWave / kBinWaveSmall.
 size_t wave_lds(int bin, int block)
 {
-    return bin == kBinWave ? (size_t)(block / 64) * kWaveTileWords * sizeof(uint64_t) : 0;
+    return bin == kBinWave || bin == kBinWaveSmall
+               ? (size_t)(block / 64) * wave_tile_words(bin) * sizeof(uint64_t)
+               : 0;
 }
 
 template <int PPT, bool VEC, bool EARLY, int BIN, bool PW>
@@ -180,15 +184,16 @@ hipError_t raster_min_ppt(const Pts &p, const Proj &P, uint64_t *fb, const Tune 
                           hipStream_t s)
 {
     const int64_t nchunks = blocks_for(p.n, (int64_t)t.block * PPT);
-    const size_t lds = wave_lds(BIN, t.block);
+    const size_t lds = wave_lds(t.bin, t.block);
+    const uint32_t words = wave_tile_words(t.bin);
     if (t.xcd_remap) {
         const int64_t grid = (nchunks + kXcds - 1) / kXcds * kXcds;
         hipLaunchKernelGGL((k_raster_min<PPT, VEC, EARLY, true, BIN, PW>), dim3((uint32_t)grid),
-                           dim3(t.block), lds, s, p, P, fb, nchunks);
+                           dim3(t.block), lds, s, p, P, fb, nchunks, words);
     } else {
         hipLaunchKernelGGL((k_raster_min<PPT, VEC, EARLY, false, BIN, PW>),
                            dim3((uint32_t)nchunks),
-                           dim3(t.block), lds, s, p, P, fb, nchunks);
+                           dim3(t.block), lds, s, p, P, fb, nchunks, words);
     }
     return hipGetLastError();
 }
@@ -198,14 +203,15 @@ hipError_t hq_accum_ppt(const Pts &p, const Proj &P, uint32_t num, uint32_t den,
                         const uint64_t *fb, uint64_t *acc, const Tune &t, hipStream_t s)
 {
     const int64_t nchunks = blocks_for(p.n, (int64_t)t.block * PPT);
-    const size_t lds = wave_lds(BIN, t.block);
+    const size_t lds = wave_lds(t.bin, t.block);
+    const uint32_t words = wave_tile_words(t.bin);
     if (t.xcd_remap) {
         const int64_t grid = (nchunks + kXcds - 1) / kXcds * kXcds;
         hipLaunchKernelGGL((k_hq_accum<PPT, VEC, true, BIN, PW>), dim3((uint32_t)grid),
-                           dim3(t.block), lds, s, p, P, num, den, fb, acc, nchunks);
+                           dim3(t.block), lds, s, p, P, num, den, fb, acc, nchunks, words);
     } else {
         hipLaunchKernelGGL((k_hq_accum<PPT, VEC, false, BIN, PW>), dim3((uint32_t)nchunks),
-                           dim3(t.block), lds, s, p, P, num, den, fb, acc, nchunks);
+                           dim3(t.block), lds, s, p, P, num, den, fb, acc, nchunks, words);
     }
     return hipGetLastError();
 }
@@ -221,7 +227,8 @@ hipError_t raster_min_bin(const Pts &p, const Proj &P, uint64_t *fb, const Tune 
 {
     switch (t.bin) {
     case kBinBlock: return raster_min_ppt<PPT, VEC, true, kBinBlock, PW>(p, P, fb, t, s);
-    case kBinWave: return raster_min_ppt<PPT, VEC, true, kBinWave, PW>(p, P, fb, t, s);
+    case kBinWave:
+    case kBinWaveSmall: return raster_min_ppt<PPT, VEC, true, kBinWave, PW>(p, P, fb, t, s);
     default:
         return t.early_out ? raster_min_ppt<PPT, VEC, true, kBinNone, PW>(p, P, fb, t, s)
                            : raster_min_ppt<PPT, VEC, false, kBinNone, PW>(p, P, fb, t, s);
@@ -250,7 +257,9 @@ hipError_t hq_accum_bin(const Pts &p, const Proj &P, uint32_t num, uint32_t den,
 {
     switch (t.bin) {
     case kBinBlock: return hq_accum_ppt<PPT, VEC, kBinBlock, PW>(p, P, num, den, fb, acc, t, s);
-    case kBinWave: return hq_accum_ppt<PPT, VEC, kBinWave, PW>(p, P, num, den, fb, acc, t, s);
+    case kBinWave:
+    case kBinWaveSmall:
+        return hq_accum_ppt<PPT, VEC, kBinWave, PW>(p, P, num, den, fb, acc, t, s);
     default: return hq_accum_ppt<PPT, VEC, kBinNone, PW>(p, P, num, den, fb, acc, t, s);
     }
 }

@@ -37,7 +37,7 @@ bool valid_launch(const rz_launch &l)
 {
     return (l.block == 64 || l.block == 128 || l.block == 256 || l.block == 512) &&
            (l.ppt == 4 || l.ppt == 8 || l.ppt == 16) && (l.early_out & ~1) == 0 &&
-           (l.xcd_remap & ~1) == 0 && l.bin >= 0 && l.bin <= 2;
+           (l.xcd_remap & ~1) == 0 && l.bin >= 0 && l.bin <= 3;
 }
 
 bool valid_entry(const rz_tune_entry &e)

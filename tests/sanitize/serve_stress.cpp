@@ -7,11 +7,18 @@
 //     several threads submit, poll and read statistics at once while the
 //     scheduler admits and completes requests; then drain, a destroy that
 //     times out while work is queued, and a final destroy.
+//  3. The batch autotune cache's file handling (stores and lookups from
+//     several threads, malformed lines, bad keys) and the point-order
+//     classifier on ragged, NaN-laden and empty inputs.
 // The kernel launchers are stubs: none of these calls reaches a launch.
+#include <math.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
+#include <unistd.h>
 
 #include <atomic>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -120,10 +127,89 @@ static int api_checks()
     return bad;
 }
 
+// The autotune cache and the order classifier (host code of rz_tune.cpp).
+static int tune_checks()
+{
+    int bad = 0;
+    char path[64];
+    snprintf(path, sizeof(path), "/tmp/rz_tune_sanitize_%d.txt", (int)getpid());
+    unlink(path);
+    rz_tune_entry e = {};
+    e.views_per_group = 4;
+    e.depth = {64, 16, 1, 0, 2};
+    e.accum = {128, 8, 1, 0, 3};
+    e.ms = 1.5f;
+    std::vector<std::thread> th;
+    std::atomic<int> errs{0};
+    for (int t = 0; t < 4; ++t) {
+        th.emplace_back([&, t] {
+            for (int i = 0; i < 20; ++i) {
+                char key[96];
+                snprintf(key, sizeof(key), "gfx950 n%d px%d v8 hq2 ordered", t, i);
+                rz_tune_entry x = e;
+                x.ms = (float)(t * 100 + i);
+                rz_tune_entry got = {};
+                if (rz_tune_cache_store(path, key, &x) != RZ_OK ||
+                    rz_tune_cache_lookup(path, key, &got) != 1 || got.ms != x.ms)
+                    errs++;
+            }
+        });
+    }
+    for (auto &x : th)
+        x.join();
+    bad += errs.load();
+    FILE *f = fopen(path, "a");
+    if (f) {
+        fputs("gfx950 n1 px1 v8 hq2 ordered k=4 block=64\n", f);
+        fputs("gfx950 n1 px1 v8 hq2 ordered k=99 block=64 ppt=16 early_out=1 xcd=0 bin=2 "
+              "hq_block=64 hq_ppt=16 hq_early_out=1 hq_xcd=0 hq_bin=2 ms=1\n", f);
+        fputs(std::string(5000, 'x').c_str(), f);
+        fputs("\n\n#\n= = = = = = =\n", f);
+        fclose(f);
+    }
+    rz_tune_entry got = {};
+    if (rz_tune_cache_lookup(path, "gfx950 n1 px1 v8 hq2 ordered", &got) != 1 ||
+        got.ms != 101.0f)
+        bad++;
+    if (rz_tune_cache_store(path, "bad key", &e) != RZ_EINVAL ||
+        rz_tune_cache_lookup(path, " a b c d e f", &got) != RZ_EINVAL ||
+        rz_tune_cache_lookup(nullptr, "a b c d e f", &got) != RZ_EINVAL)
+        bad++;
+    unlink(path);
+    // order classes: a line, a shuffled line, NaNs, tiny and empty inputs
+    const int n = 20000;
+    std::vector<float> x(n), y(n), z(n);
+    for (int i = 0; i < n; ++i) {
+        x[i] = (float)i;
+        y[i] = 0.5f * (float)i;
+        z[i] = 0.f;
+    }
+    if (rz_order_class_host(x.data(), y.data(), z.data(), n) != 0)
+        bad++;
+    srand(7);
+    for (int i = n - 1; i > 0; --i) {
+        const int j = rand() % (i + 1);
+        std::swap(x[i], x[j]);
+        std::swap(y[i], y[j]);
+    }
+    if (rz_order_class_host(x.data(), y.data(), z.data(), n) != 1)
+        bad++;
+    for (int i = 0; i < n; i += 3)
+        x[i] = NAN;
+    (void)rz_order_class_host(x.data(), y.data(), z.data(), n);
+    (void)rz_order_class_host(x.data(), y.data(), z.data(), 17);
+    if (rz_order_class_host(nullptr, nullptr, nullptr, 0) != 1 ||
+        rz_order_class_host(nullptr, y.data(), z.data(), 5) != RZ_EINVAL)
+        bad++;
+    return bad;
+}
+
 int main()
 {
     if (api_checks())
         return 6;
+    if (tune_checks())
+        return 7;
     rz_server_opts o = {};
     o.budget_bytes = 8u << 20;
     o.streams = 4;

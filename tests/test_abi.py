@@ -273,11 +273,14 @@ def test_reciprocal_values_validation(rz):
 def test_launch_shape_validation(rz):
     lib = rz.load()
     before = rz.get_launch()
-    for bad in ((96, 8, 1, 1, 0), (256, 6, 1, 1, 0), (256, 8, 2, 1, 0), (256, 8, 1, 5, 0)):
+    for bad in ((96, 8, 1, 1, 0), (256, 6, 1, 1, 0), (256, 8, 2, 1, 0), (256, 8, 1, 5, 0),
+                (256, 8, 1, 1, 4), (256, 8, 1, 1, -1)):
         assert lib.rz_set_launch(ctypes.byref(rz.rz_launch(*bad))) == rz.RZ_EINVAL
     assert rz.get_launch() == before
     rz.set_launch(128, 4, 0, 0)
     assert rz.get_launch()["block"] == 128 and rz.get_launch()["ppt"] == 4
+    rz.set_launch(256, 4, 1, 0, 3)   # the small per-wave tile
+    assert rz.get_launch()["bin"] == 3
     rz.set_launch(**before)
     rz.reset_launch()
     assert rz.get_launch() == {"block": 64, "ppt": 16, "early_out": 1, "xcd_remap": 0, "bin": 2}

@@ -92,7 +92,8 @@ def test_one_view_calls_match(rz, scene, expected):
 
 @pytest.mark.parametrize("k", [1, 3, 8])
 @pytest.mark.parametrize("launch", [(256, 4, 1, 1, 1), (512, 8, 1, 0, 1), (128, 16, 1, 1, 0),
-                                    (256, 8, 1, 1, 2), (512, 16, 1, 0, 2)])
+                                    (256, 8, 1, 1, 2), (512, 16, 1, 0, 2), (256, 4, 1, 0, 3),
+                                    (64, 16, 1, 1, 3)])
 def test_group_sizes_and_shapes(rz, scene, expected, k, launch):
     cloud, views, modes, bgs = scene
     say(f"[batch] K={k} launch={launch}")

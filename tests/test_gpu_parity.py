@@ -176,7 +176,7 @@ def test_ragged_sizes(rz, oracle, n):
 
 
 LAUNCHES = [(b, p, e, x, n) for b in (64, 256, 512) for p in (4, 8, 16) for e in (0, 1)
-            for x in (0, 1) for n in (0, 1, 2)]
+            for x in (0, 1) for n in (0, 1, 2, 3)]
 
 
 def test_every_launch_shape_is_bit_identical(rz, oracle):
@@ -199,7 +199,7 @@ def test_every_launch_shape_is_bit_identical(rz, oracle):
         rz.reset_launch()
 
 
-@pytest.mark.parametrize("bin_", [0, 1, 2])
+@pytest.mark.parametrize("bin_", [0, 1, 2, 3])
 def test_tile_fallback_and_sparse_screens(rz, oracle, bin_):
     """Workgroups whose fragments span more than one LDS tile (random points
     over a wide screen) take the direct path; both give the oracle's bits."""
@@ -230,7 +230,7 @@ def test_tiny_screens(rz, oracle, size):
     cloud, _ = gen.config1(n=20_000)
     view = gen.make_view((0.5, 0.5, 2.5), (0.5, 0.5, 0.5), (0, 1, 0), 60.0, *size, 0.01, 10.0)
     try:
-        for bin_ in (2, 1, 0):
+        for bin_ in (3, 2, 1, 0):
             rz.set_launch(bin=bin_)
             check_scene(rz, oracle, cloud, view, bg=0x0A0B0C, label=f"tiny {size} bin={bin_}")
     finally:

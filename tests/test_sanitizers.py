@@ -2,11 +2,12 @@
   - the oracle library built with AddressSanitizer and UndefinedBehavior-
     Sanitizer (gcc), running its own pins (tests/test_oracle.py);
   - the library's host code (argument validation, per-view constants, the
-    render server) built with AddressSanitizer + UndefinedBehaviorSanitizer
+    render server, the autotune cache) built with AddressSanitizer + UndefinedBehaviorSanitizer
     and, separately, ThreadSanitizer (clang), driven by
     tests/sanitize/serve_stress.cpp: validation of every one-view entry
-    point, and the server's scheduler in dry-run mode with concurrent
-    submitters, pollers and statistics readers, drain and timed destroy.
+    point, the server's scheduler in dry-run mode with concurrent
+    submitters, pollers and statistics readers, drain and timed destroy,
+    and the batch autotune cache's file handling and order classifier.
 Any sanitizer report fails the run."""
 import os
 import shutil
@@ -62,6 +63,7 @@ def _build_driver(tmp_path, name, flags):
            "-D__HIP_PLATFORM_AMD__", f"-I{ROOT}/include", f"-I{CSRC}", f"-I{ROCM}/include",
            os.path.join(ROOT, "tests", "sanitize", "serve_stress.cpp"),
            os.path.join(CSRC, "rz_serve.cpp"), os.path.join(CSRC, "rz_api.cpp"),
+           os.path.join(CSRC, "rz_tune.cpp"),
            f"-L{ROCM}/lib", "-lamdhip64", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM}/lib", "-lpthread", "-o", exe]
     subprocess.run(cmd, check=True, capture_output=True, text=True)
     return exe

@@ -85,7 +85,7 @@ def test_bad_keys_are_refused(rz, tmp_path, key):
 @pytest.mark.parametrize("k,depth,ms", [(0, DEPTH, 1.0), (9, DEPTH, 1.0),
                                         (4, dict(DEPTH, block=32), 1.0),
                                         (4, dict(DEPTH, ppt=2), 1.0),
-                                        (4, dict(DEPTH, bin=3), 1.0),
+                                        (4, dict(DEPTH, bin=4), 1.0),
                                         (4, dict(DEPTH, early_out=2), 1.0),
                                         (4, DEPTH, -1.0), (4, DEPTH, float("inf"))])
 def test_bad_entries_are_refused(rz, tmp_path, k, depth, ms):
