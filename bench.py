@@ -153,7 +153,8 @@ def bench_batch(a):
                 rz.rasterize_hq_splat(pts, v, fb=fb, acc=acc, img=img, status=st)
 
     if a.batch_k:
-        b = rz.Batch(pts, views, modes, views_per_group=a.batch_k, use_graph=False)
+        b = rz.Batch(pts, views, modes, views_per_group=a.batch_k, use_graph=False,
+                     launch=tuple(a.batch_launch) if a.batch_launch else None)
         chosen = b.opts()
         log(f"[batch] fixed {chosen}")
     else:
@@ -416,6 +417,9 @@ def main():
     ap.add_argument("--batch-k", type=int, default=0,
                     help="batch64: a fixed group size K, no graph and no autotuning "
                          "(for counter runs, which count every dispatch on its own)")
+    ap.add_argument("--batch-launch", type=int, nargs=5, default=None,
+                    metavar=("BLOCK", "PPT", "EARLY", "XCD", "BIN"),
+                    help="with --batch-k: the launch shape of both passes of the batch")
     ap.add_argument("--serve-clouds", type=int, default=8)
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget", type=int, default=4 << 30)
