@@ -262,7 +262,7 @@ class ServingWorld:
 
     def run_server(self, trace):
         rz, a = self.rz, self.a
-        srv = rz.Server(a.serve_budget, streams=a.serve_streams, work_cap=a.serve_work_cap)
+        srv = rz.Server(a.serve_budget, streams=a.serve_streams, work_cap=self.work_cap())
         ids = [srv.add_cloud(p) for p in self.pts]
         pending, status = {}, {}
         slot_owner = {sz: [None] * self.ring for sz in self.gen.SERVE_SIZES}
@@ -304,6 +304,12 @@ class ServingWorld:
         first_arrival_us = sts[0]["t_submit_us"] - tick[0][1] * 1e6
         span = (max(x["t_done_us"] for x in sts) - first_arrival_us) / 1e6
         return lat, span, stats
+
+    def work_cap(self):
+        """The server's work cap: the option's value, or by default the work
+        of the largest request (a splat frame of the largest cloud), so that
+        such a request runs alone while smaller ones still overlap."""
+        return self.a.serve_work_cap if self.a.serve_work_cap >= 0 else 2 * max(self.npts)
 
     def capacity(self):
         """Requests per second of the plain loop on back-to-back requests."""
@@ -379,7 +385,8 @@ def bench_serve(a):
                                f"arrivals, resolutions {gen.SERVE_SIZES}, methods 50/50, "
                                f"framebuffer budget {a.serve_budget >> 20} MiB, "
                                f"{a.serve_streams} streams",
-                   "requests_per_rate": a.serve_requests, "plain_capacity_req_s": round(cap, 1)},
+                   "requests_per_rate": a.serve_requests, "plain_capacity_req_s": round(cap, 1),
+                   "server_work_cap": w.work_cap()},
         "detail": {"rates": rows,
                    "p50_ms": top["server"]["p50_ms"], "p99_ms": top["server"]["p99_ms"],
                    "plain_p50_ms": top["plain"]["p50_ms"], "plain_p99_ms": top["plain"]["p99_ms"],
@@ -425,8 +432,9 @@ def main():
     ap.add_argument("--serve-budget", type=int, default=4 << 30)
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--serve-ring", type=int, default=96)
-    ap.add_argument("--serve-work-cap", type=int, default=0,
-                    help="server work cap in point passes (0: none); see rz_server_opts")
+    ap.add_argument("--serve-work-cap", type=int, default=-1,
+                    help="server work cap in point passes (0: none; default: the work of the "
+                         "largest request); see rz_server_opts")
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 1.0, 1.3, 2.0])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="after the timed region, copy BYTES between two device buffers "
@@ -774,6 +782,7 @@ def extra_legs(a):
                         f"({', '.join(f'{n // 1_000_000}M' for n in w.npts)} points), Poisson "
                         f"arrivals, resolutions 256x256 to 2560x1440, methods 50/50, "
                         f"{a.serve_budget >> 20} MiB framebuffer budget, {a.serve_streams} streams",
+            "server_work_cap": w.work_cap(),
             "plain_capacity_req_s": round(cap, 1),
             "loads": rows}
         log(f"[extras] served: {detail['served']}")

@@ -320,8 +320,8 @@ typedef struct rz_launch {
 } rz_launch;
 /* Sets the launch shape of both point passes of the one-view calls and the
    server (RZ_EINVAL if out of range); NULL restores the library defaults
-   (depth pass 64 threads x 16 points, splat pass 128 x 8, early-out, no XCD
-   remap, per-wave tiles).  rz_get_launch reports the depth pass's shape.
+   (depth pass 64 threads x 16 points with the 8 KiB per-wave tile, splat
+   pass 64 x 8 with the 2 KiB per-wave tile, early-out, no XCD remap).  rz_get_launch reports the depth pass's shape.
    Thread-safe: a call running concurrently launches with either the old
    or the new shape, and both give the same result. */
 int rz_set_launch(const rz_launch *launch);

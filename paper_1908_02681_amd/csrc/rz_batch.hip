@@ -749,8 +749,8 @@ int rz_batch_autotune_cached(rz_batch *b, void *stream, int32_t reps, const char
         drop_graph(b);
         const rz_batch_opts saved = b->opts;
         const Tune saved_tune = b->tune, saved_tune_hq = b->tune_hq;
-        // the library defaults (the autotuner's first candidate) give the
-        // reference checksum; the cached options must render the same bits
+        // the library defaults give the reference checksum; the cached
+        // options must render the same bits
         b->opts.views_per_group = 1;
         b->tune = Tune();
         b->tune_hq = kHqTune;

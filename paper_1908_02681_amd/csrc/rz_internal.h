@@ -36,16 +36,17 @@ struct Proj {
 
 // Launch shape of the point kernels.  The defaults are those of the depth
 // pass; the splat accumulate pass defaults to kHqTune (measured on the
-// 50M-point terrain: 128 threads, 8 points each).
+// 50M-point terrain: 64 threads, 8 points each, the small per-wave tile).
 struct Tune {
     int block = 64;        // threads per workgroup: 64, 128, 256 or 512
     int ppt = 16;          // points per thread: 4, 8 or 16
     int early_out = 1;     // read the framebuffer before the atomic
     int xcd_remap = 0;     // give each XCD a contiguous range of chunks
-    int bin = 2;           // 0 none, 1 workgroup LDS tile, 2 per-wave LDS tile
+    int bin = 2;           // 0 none, 1 workgroup LDS tile, 2 per-wave LDS tile,
+                           // 3 the small per-wave tile
 };
 
-constexpr Tune kHqTune = {128, 8, 1, 0, 2};
+constexpr Tune kHqTune = {64, 8, 1, 0, 3};
 
 constexpr uint64_t kDepthOnes = 0xFFFFFFFFFF000000ull;
 constexpr uint64_t kRgbMask = 0xFFFFFFull;

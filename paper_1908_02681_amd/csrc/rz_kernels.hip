@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(512) k_raster_min(Pts p, Proj P, uint64_t *__r
 // at one pixel per point: the per-wave tile kernel with the encoding's key.
 template <bool VEC, int ZK>
 __global__ void __launch_bounds__(512) k_raster_min_zk(Pts p, Proj P, uint64_t *__restrict__ fb,
-                                                       int64_t nchunks)
+                                                       int64_t nchunks, uint32_t words)
 {
     constexpr int PPT = 16;
     extern __shared__ uint64_t s_waves[];
@@ -65,8 +65,7 @@ __global__ void __launch_bounds__(512) k_raster_min_zk(Pts p, Proj P, uint64_t *
     for (int j = 0; j < PPT; ++j)
         in[j] = true;
     raster_chunk_wave<PPT, false, ZK>(P, fb, x, y, z, c, in,
-                                      s_waves + (threadIdx.x >> 6) * kWaveTileWords,
-                                      kWaveTileWords);
+                                      s_waves + (threadIdx.x >> 6) * words, words);
 }
 
 // Accumulation pass of section 2.2 for one view.
@@ -284,13 +283,14 @@ template <int ZK>
 hipError_t raster_min_zk(const Pts &p, const Proj &P, uint64_t *fb, const Tune &t, hipStream_t s)
 {
     const int64_t nchunks = blocks_for(p.n, (int64_t)t.block * 16);
-    const size_t lds = wave_lds(kBinWave, t.block);
+    const size_t lds = wave_lds(t.bin, t.block);
+    const uint32_t words = wave_tile_words(t.bin);
     if (planes_aligned(p))
         hipLaunchKernelGGL((k_raster_min_zk<true, ZK>), dim3((uint32_t)nchunks), dim3(t.block),
-                           lds, s, p, P, fb, nchunks);
+                           lds, s, p, P, fb, nchunks, words);
     else
         hipLaunchKernelGGL((k_raster_min_zk<false, ZK>), dim3((uint32_t)nchunks), dim3(t.block),
-                           lds, s, p, P, fb, nchunks);
+                           lds, s, p, P, fb, nchunks, words);
     return hipGetLastError();
 }
 
@@ -303,9 +303,10 @@ hipError_t launch_raster_min(const Pts &p, const Proj &P, uint64_t *fb, const Tu
     if (p.n == 0)
         return hipSuccess;
     if (P.zkind != 0) {
-        // float depth encodings: the per-wave tile kernel at the default
-        // shape, the general point kernel for every other launch shape
-        if (t.bin != kBinWave || t.ppt != 16 || t.xcd_remap)
+        // float depth encodings: the per-wave tile kernel (either tile
+        // size) at 16 points per thread, the general point kernel for every
+        // other launch shape
+        if ((t.bin != kBinWave && t.bin != kBinWaveSmall) || t.ppt != 16 || t.xcd_remap)
             return launch_raster_points(p, P, 1, fb, s);
         return P.zkind == RZ_DEPTH_GL24 ? raster_min_zk<RZ_DEPTH_GL24>(p, P, fb, t, s)
                                         : raster_min_zk<RZ_DEPTH_F32REV>(p, P, fb, t, s);

@@ -138,7 +138,7 @@ struct rz_server {
     std::vector<int32_t> free_slots;
     Pool pool;
     std::vector<hipStream_t> streams;
-    std::vector<int32_t> load;
+    std::vector<int64_t> load;   // work (point passes) in flight per stream
     std::vector<hipEvent_t> events;       // pool of ordering events
     std::mutex mu;
     std::condition_variable idle_cv;      // everything finished (with mu)
@@ -188,7 +188,7 @@ void finish(rz_server *s, Req *r, int32_t state, int32_t error)
         r->after = nullptr;
     }
     if (r->stream >= 0)
-        s->load[r->stream]--;
+        s->load[r->stream] -= r->work;
     s->pool.release(r->off, r->bytes);
     // a splat count beyond the exact range of the packed sums leaves some
     // pixels' colours unspecified: the request fails visibly
@@ -259,12 +259,14 @@ void admit(rz_server *s, Req *r)
     r->t_admit = s->now_us();
     r->slot = s->free_slots.back();
     s->free_slots.pop_back();
+    // the stream with the least work in flight: a small request does not
+    // queue behind a large one while another stream is idle or lighter
     int32_t best = 0;
     for (int32_t i = 1; i < (int32_t)s->load.size(); ++i)
         if (s->load[i] < s->load[best])
             best = i;
     r->stream = best;
-    s->load[best]++;
+    s->load[best] += r->work;
     r->state = RZ_REQ_RUNNING;
     s->inflight_work += r->work;
     s->inflight.push_back(r);
