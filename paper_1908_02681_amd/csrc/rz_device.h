@@ -500,10 +500,13 @@ __device__ __forceinline__ void load_points(const Pts &p, int64_t base, float (&
 // quads, 8-lane halves, 16-lane rows, then row broadcasts into lane 63.
 __device__ __forceinline__ uint32_t wave_min(uint32_t v)
 {
+    // Each step moves a neighbour's value in by DPP and keeps the smaller.
+    // Lanes the step does not write get the identity ~0, so the move folds
+    // into the minimum (one v_min_u32 with a DPP operand per step).
 #define RZ_DPP_MIN(ctrl, rows)                                                             \
     {                                                                                      \
-        const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, ctrl,     \
-                                                                 rows, 0xF, false);        \
+        const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, ctrl, rows,   \
+                                                                 0xF, false);              \
         v = v < t ? v : t;                                                                 \
     }
     RZ_DPP_MIN(0xB1, 0xF)    // quad_perm [1,0,3,2]
@@ -513,6 +516,25 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v)
     RZ_DPP_MIN(0x142, 0xA)   // row_bcast:15 into rows 1 and 3
     RZ_DPP_MIN(0x143, 0xC)   // row_bcast:31 into rows 2 and 3
 #undef RZ_DPP_MIN
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// The same for the maximum (identity 0).
+__device__ __forceinline__ uint32_t wave_max(uint32_t v)
+{
+#define RZ_DPP_MAX(ctrl, rows)                                                             \
+    {                                                                                      \
+        const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, rows,    \
+                                                                 0xF, false);              \
+        v = v > t ? v : t;                                                                 \
+    }
+    RZ_DPP_MAX(0xB1, 0xF)
+    RZ_DPP_MAX(0x4E, 0xF)
+    RZ_DPP_MAX(0x141, 0xF)
+    RZ_DPP_MAX(0x140, 0xF)
+    RZ_DPP_MAX(0x142, 0xA)
+    RZ_DPP_MAX(0x143, 0xC)
+#undef RZ_DPP_MAX
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
@@ -708,7 +730,7 @@ __device__ __forceinline__ Box wave_box(const uint32_t (&px)[PPT], const uint32_
         hy = max(hy, max(d0, d1));
     }
     // no live lane: lx = ~0 > hx = 0, an empty box
-    return Box{wave_min(lx), wave_min(ly), ~wave_min(~hx), ~wave_min(~hy)};
+    return Box{wave_min(lx), wave_min(ly), wave_max(hx), wave_max(hy)};
 }
 
 // wave_box() for the wave kernels, one select fewer per coordinate: a point
@@ -735,7 +757,7 @@ __device__ __forceinline__ Box wave_box_live_min(const uint32_t (&px)[PPT],
         hy = max(hy, max(py[j], py[j + 1]));
     }
     // no live lane: lx = ~0 > hx, an empty box
-    return Box{wave_min(lx), wave_min(ly), ~wave_min(~hx), ~wave_min(~hy)};
+    return Box{wave_min(lx), wave_min(ly), wave_max(hx), wave_max(hy)};
 }
 
 // Depth pass over one chunk with a private LDS tile per wave: like
