@@ -262,7 +262,8 @@ class ServingWorld:
 
     def run_server(self, trace):
         rz, a = self.rz, self.a
-        srv = rz.Server(a.serve_budget, streams=a.serve_streams, work_cap=self.work_cap())
+        srv = rz.Server(a.serve_budget, streams=a.serve_streams, work_cap=self.work_cap(),
+                        merge_views=a.serve_merge)
         ids = [srv.add_cloud(p) for p in self.pts]
         pending, status = {}, {}
         slot_owner = {sz: [None] * self.ring for sz in self.gen.SERVE_SIZES}
@@ -330,6 +331,7 @@ class ServingWorld:
                            "gpts": round(work / span / 1e9, 2),
                            "p50_ms": round(pct(ls, 50), 3), "p99_ms": round(pct(ls, 99), 3),
                            "peak_inflight": stats["peak_inflight"],
+                           "merged_requests": stats["merged_requests"],
                            "peak_fb_MB": round(stats["peak_bytes"] / 1e6, 1)},
                 "plain": {"req_s": round(len(trace) / (tp_end - trace[0][0]), 1),
                           "gpts": round(work / (tp_end - trace[0][0]) / 1e9, 2),
@@ -355,7 +357,7 @@ def bench_serve(a):
     # outside the timed runs: a burst of overlapping requests through the
     # server at full size, each image against its one-view call
     burst = serve_trace(64, 1e9, gen.CONFIG_SEEDS[5] + 1, len(pts))
-    srv = rz.Server(a.serve_budget, streams=a.serve_streams)
+    srv = rz.Server(a.serve_budget, streams=a.serve_streams, merge_views=a.serve_merge)
     ids = [srv.add_cloud(p) for p in pts]
     outs = []
     for _, c, v, m in burst:
@@ -435,6 +437,9 @@ def main():
     ap.add_argument("--serve-work-cap", type=int, default=-1,
                     help="server work cap in point passes (0: none; default: the work of the "
                          "largest request); see rz_server_opts")
+    ap.add_argument("--serve-merge", type=int, default=0,
+                    help="server merge_views: queued requests of one cloud run as one "
+                         "multi-view launch (0: no merging)")
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.8, 1.0, 1.3, 2.0])
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="after the timed region, copy BYTES between two device buffers "

@@ -526,6 +526,17 @@ typedef struct rz_server_opts {
                                 for splatting (two passes over the points).
                                 Large requests then run (nearly) alone while
                                 small ones still overlap them.  0: no limit.   */
+    int32_t merge_views;     /* > 1: when a request is admitted, up to
+                                merge_views - 1 more queued requests of the same
+                                cloud (among the next 32 in the queue) that can
+                                be admitted at once join it, and the group runs
+                                as one multi-view launch: each chunk of points
+                                is read once for all of its views (as a batch
+                                does).  Requests of other clouds are never
+                                merged; the results are the same bits as one
+                                request at a time.  0 or 1: no merging; at most
+                                8.                                             */
+    int32_t pad;
 } rz_server_opts;
 
 typedef struct rz_request {
@@ -556,6 +567,9 @@ typedef struct rz_request_status {
                                 was written but some colours are unspecified) */
     uint32_t hq_status;      /* RZ_STATUS_HQ_OVERFLOW bits (RZ_MODE_HQ)        */
     uint32_t stream;         /* stream index the request ran on               */
+    int32_t group;           /* requests in its launch: 1 alone, more when it
+                                was merged (rz_server_opts.merge_views)        */
+    int32_t pad;
     double t_submit_us;      /* host steady clock, microseconds since the
                                 server was created                            */
     double t_admit_us;
@@ -569,6 +583,8 @@ typedef struct rz_server_stats {
     int32_t queued;          /* waiting for admission now                     */
     int32_t inflight;        /* admitted and unfinished now                   */
     int32_t pad;
+    uint64_t merged_launches;  /* multi-view launches of two or more requests  */
+    uint64_t merged_requests;  /* requests that ran in such a launch           */
 } rz_server_stats;
 
 typedef struct rz_server rz_server;

@@ -39,17 +39,9 @@ namespace {
 
 using namespace dev;
 
-constexpr int kMaxK = 8;
+constexpr int kMaxK = kMaxGroupViews;
 constexpr int kMaxViews = 4096;
 constexpr int64_t kResolvePix = 512;   // pixels per resolve workgroup (256 x 2)
-
-// One view of a multi-view pass (device table entry).
-struct MvView {
-    Proj P;
-    uint64_t *fb;
-    uint64_t *acc;
-    uint32_t eps_num, eps_den;
-};
 
 // One view of the fused resolve.
 struct MvResolve {
@@ -288,6 +280,16 @@ rz_launch launch_of(const Tune &t)
 }
 
 }  // namespace
+
+hipError_t launch_multiview(bool hq, bool pw, const Pts &p, const MvView *views, int32_t nv,
+                            const Tune &t, hipStream_t s)
+{
+    if (nv < 0 || nv > kMaxGroupViews)
+        return hipErrorInvalidValue;
+    Range r(hq ? "rz multi-view splat accumulate pass" : "rz multi-view depth pass");
+    return mv_launch(hq, pw, p, views, nv, t, s);
+}
+
 }  // namespace rz
 
 using namespace rz;

@@ -72,6 +72,22 @@ hipError_t launch_clear(uint64_t *fb, uint64_t *acc, int64_t npix, uint32_t bg, 
 // pixel, early-out plus global atomics).
 hipError_t launch_raster_points(const Pts &p, const Proj &P, int32_t k, uint64_t *fb,
                                 hipStream_t s);
+
+// One view of a multi-view pass (an entry of a device table): the batch
+// engine's groups and the server's merged requests.
+struct MvView {
+    Proj P;
+    uint64_t *fb;
+    uint64_t *acc;
+    uint32_t eps_num, eps_den;
+};
+constexpr int kMaxGroupViews = 8;   // views per multi-view launch
+
+// Depth passes (hq false) or accumulate passes (hq true) of views[0 .. nv)
+// (a device table, nv <= kMaxGroupViews) over the points, each chunk of
+// points loaded once for all of them.  pw: some view uses a piecewise map.
+hipError_t launch_multiview(bool hq, bool pw, const Pts &p, const MvView *views, int32_t nv,
+                            const Tune &t, hipStream_t s);
 hipError_t launch_hq_points(const Pts &p, const Proj &P, int32_t k, uint32_t eps_num,
                             uint32_t eps_den, const uint64_t *fb, uint64_t *acc, hipStream_t s);
 

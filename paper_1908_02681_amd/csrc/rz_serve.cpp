@@ -53,6 +53,11 @@ namespace {
 
 constexpr uint64_t kAlign = 256;
 constexpr int kMaxStreams = 16;
+constexpr int kMergeWindow = 32;   // queued requests scanned for a merge
+// Launch shape of a merged group's multi-view passes: the batch engine's
+// measured best for groups of views (256 threads x 4 points, the 2 KiB
+// per-wave tile).
+constexpr Tune kGroupTune = {256, 4, 1, 0, 3};
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -119,6 +124,7 @@ struct Req {
     int32_t stream = -1;
     int32_t slot = -1;         // pinned status slot
     uint32_t hq_status = 0;
+    int32_t group = 1;         // requests in its launch
     double t_submit = 0, t_admit = 0, t_done = 0;
     hipEvent_t after = nullptr;            // recorded on the caller's stream at submit
     std::atomic<bool> gpu_done{false};     // set by the host function after the work
@@ -135,6 +141,11 @@ struct rz_server {
     std::vector<Pts> clouds;
     char *dmem = nullptr;
     uint32_t *host_status = nullptr;      // pinned, one word per slot
+    // merged groups: a view table of 2 * kMaxGroupViews entries per slot (the
+    // group's head's slot), filled on the host in pinned memory and copied
+    // to the device on the group's stream
+    MvView *mv_stage = nullptr;
+    MvView *mv_table = nullptr;
     std::vector<int32_t> free_slots;
     Pool pool;
     std::vector<hipStream_t> streams;
@@ -150,6 +161,7 @@ struct rz_server {
     std::unordered_map<uint64_t, Req *> tickets;
     uint64_t next_ticket = 1;
     uint64_t submitted = 0, completed = 0, failed = 0;
+    uint64_t merged_launches = 0, merged_requests = 0;
     int64_t inflight_work = 0;
     int32_t peak_inflight = 0;
     bool stop = false;
@@ -254,34 +266,114 @@ int launch(rz_server *s, Req *r)
     return e == hipSuccess ? RZ_OK : hip_fail(e);
 }
 
-void admit(rz_server *s, Req *r)
+// Enqueues a merged group (two or more requests of one cloud, one stream):
+// per request its wait, clear and status reset; one multi-view depth launch
+// over every view and one accumulate launch over the splatting ones (the
+// view table is copied from the head's pinned slot to its device slot
+// first); then per request its resolve, status copy and host function.
+// Returns an RZ_* code.
+int launch_group(rz_server *s, const std::vector<Req *> &g)
 {
-    r->t_admit = s->now_us();
-    r->slot = s->free_slots.back();
-    s->free_slots.pop_back();
+    Range range("rz_server merged requests");
+    const Req *head = g[0];
+    hipStream_t st = s->streams[head->stream];
+    const Pts &p = s->clouds[head->r.cloud];
+    MvView *stage = s->mv_stage + (size_t)head->slot * 2 * kMaxGroupViews;
+    MvView *table = s->mv_table + (size_t)head->slot * 2 * kMaxGroupViews;
+    int32_t nv = 0, nhq = 0;
+    bool pw = false, pw_hq = false;
+    hipError_t e = hipSuccess;
+    for (Req *r : g) {
+        uint64_t *fb = (uint64_t *)(s->dmem + r->off);
+        uint64_t *acc = r->acc_bytes ? (uint64_t *)(s->dmem + r->off + r->fb_bytes) : nullptr;
+        uint32_t *status = (uint32_t *)(s->dmem + r->off + r->fb_bytes + r->acc_bytes);
+        if (e == hipSuccess && r->after)
+            e = hipStreamWaitEvent(st, r->after, 0);
+        if (e == hipSuccess)
+            e = launch_clear(fb, acc, (int64_t)r->npix, r->r.background, st);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(status, 0, sizeof(uint32_t), st);
+        MvView m;
+        memset(&m, 0, sizeof(m));
+        m.P = r->P;
+        m.fb = fb;
+        m.acc = acc;
+        m.eps_num = r->num;
+        m.eps_den = r->den;
+        stage[nv++] = m;
+        pw = pw || r->P.nr > 0;
+        if (r->r.mode == RZ_MODE_HQ) {
+            stage[kMaxGroupViews + nhq++] = m;
+            pw_hq = pw_hq || r->P.nr > 0;
+        }
+    }
+    // the pinned slot is not written again before the head's slot is freed,
+    // which happens only after the group's work (and so this copy) is done
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(table, stage, sizeof(MvView) * 2 * kMaxGroupViews,
+                           hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = launch_multiview(false, pw, p, table, nv, kGroupTune, st);
+    if (e == hipSuccess && nhq > 0)
+        e = launch_multiview(true, pw_hq, p, table + kMaxGroupViews, nhq, kGroupTune, st);
+    for (Req *r : g) {
+        uint64_t *fb = (uint64_t *)(s->dmem + r->off);
+        uint64_t *acc = r->acc_bytes ? (uint64_t *)(s->dmem + r->off + r->fb_bytes) : nullptr;
+        uint32_t *status = (uint32_t *)(s->dmem + r->off + r->fb_bytes + r->acc_bytes);
+        if (e == hipSuccess)
+            e = r->r.mode == RZ_MODE_HQ
+                    ? launch_resolve_hq(fb, acc, (int64_t)r->npix, r->r.background, r->r.img,
+                                        status, st)
+                    : launch_resolve_min(fb, (int64_t)r->npix, r->r.background, r->r.img, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&s->host_status[r->slot], status, sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, st);
+    }
+    for (Req *r : g)
+        if (e == hipSuccess)
+            e = hipLaunchHostFunc(st, on_device_done, r);
+    return e == hipSuccess ? RZ_OK : hip_fail(e);
+}
+
+// Admits a group of requests (one, or several of one cloud) on one stream.
+void admit(rz_server *s, const std::vector<Req *> &g)
+{
     // the stream with the least work in flight: a small request does not
     // queue behind a large one while another stream is idle or lighter
     int32_t best = 0;
     for (int32_t i = 1; i < (int32_t)s->load.size(); ++i)
         if (s->load[i] < s->load[best])
             best = i;
-    r->stream = best;
-    s->load[best] += r->work;
-    r->state = RZ_REQ_RUNNING;
-    s->inflight_work += r->work;
-    s->inflight.push_back(r);
+    const double now = s->now_us();
+    for (Req *r : g) {
+        r->t_admit = now;
+        r->slot = s->free_slots.back();
+        s->free_slots.pop_back();
+        r->stream = best;
+        s->load[best] += r->work;
+        r->state = RZ_REQ_RUNNING;
+        r->group = (int32_t)g.size();
+        s->inflight_work += r->work;
+        s->inflight.push_back(r);
+    }
     s->peak_inflight = std::max(s->peak_inflight, (int32_t)s->inflight.size());
+    if (g.size() > 1) {
+        s->merged_launches++;
+        s->merged_requests += g.size();
+    }
     int rc = RZ_OK;
-    if (r->r.flags & RZ_REQ_INJECT_FAILURE) {
+    if (g.size() == 1 && (g[0]->r.flags & RZ_REQ_INJECT_FAILURE)) {
         rc = RZ_EHIP;
     } else if (!s->o.dry_run) {
-        rc = launch(s, r);
+        rc = g.size() == 1 ? launch(s, g[0]) : launch_group(s, g);
         if (rc != RZ_OK)   // part of it may be queued: let it end before reuse
-            (void)hipStreamSynchronize(s->streams[r->stream]);
+            (void)hipStreamSynchronize(s->streams[best]);
     }
     if (rc != RZ_OK) {
-        s->inflight.pop_back();
-        finish(s, r, RZ_REQ_FAILED, rc);
+        // the group fails together (its members are the last in flight)
+        s->inflight.resize(s->inflight.size() - g.size());
+        for (Req *r : g)
+            finish(s, r, RZ_REQ_FAILED, rc);
     }
 }
 
@@ -325,7 +417,32 @@ void scheduler(rz_server *s)
                 if (!s->pool.alloc(r->bytes, &r->off))
                     break;
                 s->queue.pop_front();
-                admit(s, r);
+                std::vector<Req *> g{r};
+                if (s->o.merge_views > 1 && !(r->r.flags & RZ_REQ_INJECT_FAILURE)) {
+                    // later requests of the same cloud that fit now join it
+                    int64_t gwork = r->work;
+                    int scanned = 0;
+                    for (auto it = s->queue.begin();
+                         it != s->queue.end() && scanned < kMergeWindow &&
+                         (int32_t)g.size() < s->o.merge_views;
+                         ++scanned) {
+                        Req *q = *it;
+                        const bool fits =
+                            q->r.cloud == r->r.cloud && !(q->r.flags & RZ_REQ_INJECT_FAILURE) &&
+                            (int32_t)(s->inflight.size() + g.size()) < s->o.max_inflight &&
+                            s->free_slots.size() > g.size() &&
+                            (s->o.work_cap <= 0 ||
+                             s->inflight_work + gwork + q->work <= s->o.work_cap);
+                        if (fits && s->pool.alloc(q->bytes, &q->off)) {
+                            g.push_back(q);
+                            gwork += q->work;
+                            it = s->queue.erase(it);
+                        } else {
+                            ++it;
+                        }
+                    }
+                }
+                admit(s, g);
                 if (s->o.dry_run && r->state == RZ_REQ_RUNNING) {
                     const double end = r->t_admit + s->o.dry_run_us;
                     if (next_deadline < 0 || end < next_deadline)
@@ -396,9 +513,15 @@ void release_device(rz_server *s)
     s->streams.clear();
     if (s->host_status)
         (void)hipHostFree(s->host_status);
+    if (s->mv_stage)
+        (void)hipHostFree(s->mv_stage);
+    if (s->mv_table)
+        (void)hipFree(s->mv_table);
     if (s->dmem)
         (void)hipFree(s->dmem);
     s->host_status = nullptr;
+    s->mv_stage = nullptr;
+    s->mv_table = nullptr;
     s->dmem = nullptr;
 }
 
@@ -418,7 +541,8 @@ int rz_server_create(const rz_server_opts *opts, rz_server **out)
         o.max_inflight = 4 * o.streams;
     if (o.streams < 1 || o.streams > kMaxStreams || o.max_inflight < 1 ||
         o.max_inflight > 1024 || o.budget_bytes < (1u << 20) || (o.dry_run & ~1) ||
-        o.dry_run_us < 0 || o.work_cap < 0)
+        o.dry_run_us < 0 || o.work_cap < 0 || o.merge_views < 0 ||
+        o.merge_views > kMaxGroupViews)
         return RZ_EINVAL;
     rz_server *s = new (std::nothrow) rz_server();
     if (!s)
@@ -436,6 +560,11 @@ int rz_server_create(const rz_server_opts *opts, rz_server **out)
         if (e == hipSuccess)
             e = hipHostMalloc((void **)&s->host_status, sizeof(uint32_t) * o.max_inflight,
                               hipHostMallocDefault);
+        const size_t tables = sizeof(MvView) * 2 * kMaxGroupViews * (size_t)o.max_inflight;
+        if (e == hipSuccess && o.merge_views > 1)
+            e = hipHostMalloc((void **)&s->mv_stage, tables, hipHostMallocDefault);
+        if (e == hipSuccess && o.merge_views > 1)
+            e = hipMalloc((void **)&s->mv_table, tables);
         for (int32_t i = 0; i < o.streams && e == hipSuccess; ++i) {
             hipStream_t st;
             e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
@@ -527,6 +656,7 @@ int rz_server_poll(rz_server *s, uint64_t ticket, rz_request_status *st)
     st->error = r->error;
     st->hq_status = r->hq_status;
     st->stream = r->stream < 0 ? 0u : (uint32_t)r->stream;
+    st->group = r->group;
     st->t_submit_us = r->t_submit;
     st->t_admit_us = r->t_admit;
     st->t_done_us = r->t_done;
@@ -561,6 +691,8 @@ int rz_server_get_stats(rz_server *s, rz_server_stats *st)
     st->peak_inflight = s->peak_inflight;
     st->queued = (int32_t)s->queue.size();
     st->inflight = (int32_t)s->inflight.size();
+    st->merged_launches = s->merged_launches;
+    st->merged_requests = s->merged_requests;
     return RZ_OK;
 }
 

@@ -92,7 +92,8 @@ class rz_tune_entry(ctypes.Structure):
 
 class rz_server_opts(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("streams", c_int32), ("max_inflight", c_int32),
-                ("dry_run", c_int32), ("dry_run_us", c_int32), ("work_cap", c_int64)]
+                ("dry_run", c_int32), ("dry_run_us", c_int32), ("work_cap", c_int64),
+                ("merge_views", c_int32), ("pad", c_int32)]
 
 
 class rz_request(ctypes.Structure):
@@ -103,15 +104,16 @@ class rz_request(ctypes.Structure):
 
 class rz_request_status(ctypes.Structure):
     _fields_ = [("state", c_int32), ("error", c_int32), ("hq_status", c_uint32),
-                ("stream", c_uint32), ("t_submit_us", c_double), ("t_admit_us", c_double),
-                ("t_done_us", c_double)]
+                ("stream", c_uint32), ("group", c_int32), ("pad", c_int32),
+                ("t_submit_us", c_double), ("t_admit_us", c_double), ("t_done_us", c_double)]
 
 
 class rz_server_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("failed", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
                 ("peak_inflight", c_int32), ("queued", c_int32), ("inflight", c_int32),
-                ("pad", c_int32)]
+                ("pad", c_int32), ("merged_launches", ctypes.c_uint64),
+                ("merged_requests", ctypes.c_uint64)]
 
 
 P = ctypes.POINTER
@@ -763,11 +765,11 @@ class Server:
     the scheduler without any device work (requests take dry_run_us)."""
 
     def __init__(self, budget_bytes, streams=4, max_inflight=0, dry_run=False, dry_run_us=0,
-                 work_cap=0):
+                 work_cap=0, merge_views=0):
         if not dry_run:
             _require_gpu()
         o = rz_server_opts(int(budget_bytes), int(streams), int(max_inflight), 1 if dry_run else 0,
-                           int(dry_run_us), int(work_cap))
+                           int(dry_run_us), int(work_cap), int(merge_views), 0)
         h = c_void_p()
         _check(load().rz_server_create(ctypes.byref(o), ctypes.byref(h)), "rz_server_create")
         self._h = h
@@ -807,7 +809,7 @@ class Server:
     def poll(self, ticket) -> dict:
         st = rz_request_status()
         _check(load().rz_server_poll(self._h, int(ticket), ctypes.byref(st)), "rz_server_poll")
-        return {f: getattr(st, f) for f, _ in rz_request_status._fields_}
+        return {f: getattr(st, f) for f, _ in rz_request_status._fields_ if f != "pad"}
 
     def drain(self, timeout_s=60.0):
         _check(load().rz_server_drain(self._h, float(timeout_s)), "rz_server_drain")

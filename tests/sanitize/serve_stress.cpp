@@ -5,8 +5,9 @@
 //     documented code before touching a device.
 //  2. The render server's scheduler in its dry-run mode (no device work):
 //     several threads submit, poll and read statistics at once while the
-//     scheduler admits and completes requests; then drain, a destroy that
-//     times out while work is queued, and a final destroy.
+//     scheduler admits (merging queued requests of one cloud) and completes
+//     requests; then drain, a destroy that times out while work is queued,
+//     and a final destroy.
 //  3. The batch autotune cache's file handling (stores and lookups from
 //     several threads, malformed lines, bad keys) and the point-order
 //     classifier on ragged, NaN-laden and empty inputs.
@@ -54,6 +55,11 @@ hipError_t launch_raster_points(const Pts &, const Proj &, int32_t, uint64_t *, 
 }
 hipError_t launch_hq_points(const Pts &, const Proj &, int32_t, uint32_t, uint32_t,
                             const uint64_t *, uint64_t *, hipStream_t)
+{
+    return hipErrorInvalidValue;
+}
+hipError_t launch_multiview(bool, bool, const Pts &, const MvView *, int32_t, const Tune &,
+                            hipStream_t)
 {
     return hipErrorInvalidValue;
 }
@@ -217,6 +223,7 @@ int main()
     o.dry_run = 1;
     o.dry_run_us = 300;
     o.work_cap = 5000;
+    o.merge_views = 4;
     rz_server *s = nullptr;
     if (rz_server_create(&o, &s) != RZ_OK)
         return 1;
@@ -281,6 +288,8 @@ int main()
     stats.join();
     if (rz_server_drain(s, 30.0) != RZ_OK)
         return 3;
+    rz_server_stats fin;
+    const uint64_t merged = rz_server_get_stats(s, &fin) == RZ_OK ? fin.merged_requests : 0;
     // a destroy that cannot finish in time leaves the server usable
     rz_request r = make_request(ids[0], 1, 64, 64, 0);
     uint64_t k = 0;
@@ -295,5 +304,6 @@ int main()
     if (early == RZ_ESTATE && rz_server_destroy(s, 30.0) != RZ_OK)
         return 4;
     printf("served %d requests, %d errors\n", done.load(), bad.load());
+    printf("merged %llu requests\n", (unsigned long long)merged);
     return bad.load() == 0 && done.load() == kThreads * kPer ? 0 : 5;
 }

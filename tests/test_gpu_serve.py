@@ -183,3 +183,99 @@ def test_requests_wait_for_the_callers_stream(rz, world, alone):
     finally:
         s.close()
         del big
+
+
+def busy_stream(fills=100):
+    """A side stream with about 20 ms of queued device work (fills of a
+    1 GiB buffer), and the buffer, which must outlive that work."""
+    import torch
+    side = torch.cuda.Stream()
+    buf = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    with torch.cuda.stream(side):
+        for k in range(fills):
+            buf.fill_(k)
+    return side, buf
+
+
+def test_merged_requests_equal_alone(rz, world, alone):
+    """With merge_views, queued requests of one cloud run as one multi-view
+    launch; every image is still the one-view call's, bit for bit.  A
+    splatting request of the largest cloud, whose work exceeds the work cap,
+    runs first and alone, so that the others queue behind it and merge."""
+    import torch
+    clouds, pts, reqs = world
+    s = rz.Server(256 << 20, streams=2, max_inflight=16, work_cap=pts[2].n, merge_views=8)
+    ids = [s.add_cloud(p) for p in pts]
+    v0 = reqs[0][1]
+    blk_img = torch.empty(v0.width * v0.height, dtype=torch.int32, device="cuda")   # kept alive
+    torch.cuda.synchronize()
+    side, buf = busy_stream()
+    # in flight until the side stream's work is done: the others queue
+    blocker = s.submit(ids[2], v0, rz.RZ_MODE_HQ, img=blk_img, after=side)
+    imgs, tickets = [], []
+    for c, v, m, bg in reqs:
+        img = torch.full((v.width * v.height,), -1, dtype=torch.int32, device="cuda")
+        imgs.append(img)
+        tickets.append(s.submit(ids[c], v, m, img=img, background=bg))
+    s.drain(120)
+    st = [s.poll(t) for t in tickets]
+    assert s.poll(blocker)["state"] == rz.RZ_REQ_DONE
+    stats = s.stats()
+    s.close()
+    torch.cuda.synchronize()
+    del buf
+    say(f"[serve] merged {stats['merged_requests']} requests in {stats['merged_launches']} "
+        f"launches; groups {[x['group'] for x in st]}")
+    assert all(x["state"] == rz.RZ_REQ_DONE and x["error"] == 0 for x in st)
+    for i, (got, want) in enumerate(zip(imgs, alone)):
+        assert np.array_equal(rz.to_u32(got), want), f"request {i} differs when merged"
+    assert stats["merged_launches"] >= 1 and max(x["group"] for x in st) > 1
+    assert stats["merged_requests"] == sum(1 for x in st if x["group"] > 1)
+
+
+def test_merged_splat_overflow_fails_only_its_request(rz):
+    """Two splatting requests of one cloud merged into one launch: the one
+    whose pixel receives 16,843,010 fragments fails with RZ_EOVERFLOW, the
+    other (its view culls every point) is served, with its own status."""
+    import torch
+    n = 16_843_010
+    pts = rz.Points(torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"),
+                    torch.full((n,), -10.0, device="cuda"),
+                    torch.full((n,), 0xFFFFFF, dtype=torch.int32, device="cuda"))
+    vp = np.array([[1.0, 0, 0, 0], [0, 1.0, 0, 0], [0, 0, 0, 0], [0, 0, -1.0, 0]])
+    hit = gen.View(vp, 1.0, 100.0, 2, 2)
+    cull = gen.View(vp, 20.0, 100.0, 2, 2)      # every point nearer than near
+    a = lambda v: (v + 255) // 256 * 256
+    bw, bh = 1280, 720                          # the request that runs first
+    blocker_bytes = a(8 * bw * bh) + a(16 * bw * bh) + 256
+    small_bytes = a(8 * 4) + a(16 * 4) + 256
+    # memory for the first request only: the two small ones queue behind it
+    # and are admitted together once it is done
+    budget = max(1 << 20, blocker_bytes + small_bytes // 2)
+    assert blocker_bytes + small_bytes > budget >= 2 * small_bytes
+    s = rz.Server(budget, streams=1, max_inflight=8, merge_views=4)
+    try:
+        cid = s.add_cloud(pts)
+        other = s.add_cloud(rz.Points.from_cloud(gen.config1(n=100_000)[0]))
+        v_big = gen.make_view((0.5, 0.5, 2.5), (0.5, 0.5, 0.5), (0, 1, 0), 60.0, bw, bh, 0.01,
+                              10.0)
+        big_img = torch.empty(bw * bh, dtype=torch.int32, device="cuda")   # kept alive
+        torch.cuda.synchronize()
+        side, buf = busy_stream()
+        # in flight until the side stream's work is done: the two queue
+        first = s.submit(other, v_big, rz.RZ_MODE_HQ, img=big_img, after=side)
+        img_hit = torch.zeros(4, dtype=torch.int32, device="cuda")
+        img_cull = torch.zeros(4, dtype=torch.int32, device="cuda")
+        t_hit = s.submit(cid, hit, rz.RZ_MODE_HQ, img=img_hit)
+        t_cull = s.submit(cid, cull, rz.RZ_MODE_HQ, img=img_cull, background=0x123456)
+        s.drain(60)
+        assert s.poll(first)["state"] == rz.RZ_REQ_DONE
+        st_hit, st_cull = s.poll(t_hit), s.poll(t_cull)
+        assert st_hit["group"] == 2 and st_cull["group"] == 2
+        assert st_hit["state"] == rz.RZ_REQ_FAILED and st_hit["error"] == rz.RZ_EOVERFLOW
+        assert st_cull["state"] == rz.RZ_REQ_DONE and st_cull["error"] == rz.RZ_OK
+        assert st_cull["hq_status"] == 0
+        assert (rz.to_u32(img_cull) == 0x123456).all()
+    finally:
+        s.close()
+        torch.cuda.synchronize()

@@ -76,6 +76,12 @@ def test_host_code_under_asan_and_ubsan(tmp_path):
                          env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1"))
     assert run.returncode == 0, (run.stdout[-2000:], run.stderr[-4000:])
     assert "served 600 requests, 0 errors" in run.stdout
+    assert _merged(run.stdout) > 0   # the merging path ran
+
+
+def _merged(out):
+    line = [l for l in out.splitlines() if l.startswith("merged ")][0]
+    return int(line.split()[1])
 
 
 def test_scheduler_under_tsan(tmp_path):

@@ -1,6 +1,7 @@
 """Render-server scheduling on the host (dry-run backend: no device work):
 admission by memory budget and in-flight slots, arrival order, continuous
-admission as memory frees up, error isolation of failed requests."""
+admission as memory frees up, error isolation of failed requests, the work
+cap and the merging of queued requests of one cloud."""
 import time
 
 import numpy as np
@@ -209,3 +210,57 @@ def test_work_cap_keeps_large_requests_apart(rz):
     st = _wait(s, [s.submit(big, _View(32, 32), 1) for _ in range(3)])
     s.close()
     assert all(x["state"] == rz.RZ_REQ_DONE for x in st)
+
+
+def test_merge_groups_requests_of_one_cloud(rz):
+    """With merge_views, queued requests of the admitted request's cloud
+    join its launch (up to merge_views, never another cloud's, never past
+    the work cap); the rest keep arrival order."""
+    s = rz.Server(64 << 20, streams=2, max_inflight=8, dry_run=True, dry_run_us=30_000,
+                  work_cap=1000, merge_views=4)
+    big = s.add_cloud(rz.rz_points(1, 1, 1, 1, 1000))
+    small = s.add_cloud(rz.rz_points(1, 1, 1, 1, 10))
+    first = s.submit(big, _View(32, 32), 0)      # runs alone: nothing fits beside it
+    time.sleep(0.005)
+    plan = [small, big, small, small, big, small, small]
+    ts = [s.submit(c, _View(32, 32), i % 2) for i, c in enumerate(plan)]
+    st = _wait(s, [first] + ts)
+    stats = s.stats()
+    s.close()
+    assert all(x["state"] == rz.RZ_REQ_DONE for x in st)
+    first_st, st = st[0], st[1:]
+    assert first_st["group"] == 1
+    # the first small request and the next three small ones ran as one launch
+    grouped = [0, 2, 3, 5]
+    assert all(st[i]["group"] == 4 for i in grouped)
+    assert len({st[i]["t_admit_us"] for i in grouped}) == 1
+    assert all(st[i]["stream"] == st[0]["stream"] for i in grouped)
+    # the large requests ran alone, after the group, in arrival order
+    assert st[1]["group"] == 1 and st[4]["group"] == 1
+    assert st[1]["t_admit_us"] >= st[0]["t_done_us"] - 1.0
+    assert st[4]["t_admit_us"] >= st[1]["t_done_us"] - 1.0
+    assert st[6]["group"] == 1
+    assert stats["merged_launches"] == 1 and stats["merged_requests"] == 4
+
+
+def test_merge_leaves_failures_alone(rz):
+    """A request with an injected failure is never merged; it fails alone
+    and the requests around it complete."""
+    s = rz.Server(64 << 20, streams=1, max_inflight=8, dry_run=True, dry_run_us=20_000,
+                  work_cap=1000, merge_views=8)
+    big = s.add_cloud(rz.rz_points(1, 1, 1, 1, 1000))
+    small = s.add_cloud(rz.rz_points(1, 1, 1, 1, 10))
+    first = s.submit(big, _View(16, 16), 0)
+    time.sleep(0.005)
+    ts = [s.submit(small, _View(16, 16), 0, inject_failure=(i == 2)) for i in range(6)]
+    st = _wait(s, [first] + ts)[1:]
+    s.close()
+    assert st[2]["state"] == rz.RZ_REQ_FAILED and st[2]["group"] == 1
+    assert all(x["state"] == rz.RZ_REQ_DONE for i, x in enumerate(st) if i != 2)
+    assert max(x["group"] for x in st) > 1
+
+
+@pytest.mark.parametrize("bad", [-1, 9])
+def test_merge_views_validation(rz, bad):
+    with pytest.raises(rz.RzError):
+        rz.Server(64 << 20, dry_run=True, merge_views=bad)
