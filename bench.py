@@ -863,6 +863,9 @@ def time_sort_last(rz, pts, view, G, steps):
 KERNEL_SOURCES = {
     "direct": ("rz_kernels.hip", "rz_device.h", "rz_internal.h", "rz_api.cpp"),
     "sorted": ("rz_sorted.hip", "rz_device.h", "rz_internal.h", "rz_api.cpp"),
+    "general": ("rz_general.hip", "rz_kernels.hip", "rz_device.h", "rz_internal.h",
+                "rz_api.cpp"),
+    "merge": ("rz_merge.hip", "rz_kernels.hip", "rz_device.h", "rz_internal.h", "rz_api.cpp"),
 }
 
 
