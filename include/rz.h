@@ -41,6 +41,9 @@
  *     before anything is enqueued.  Calls are reentrant.
  *   - Return value: RZ_OK (0) or a negative RZ_E* code; rz_error_string()
  *     names it.  No C++ exception crosses this interface.
+ *   - Every call and every pass it enqueues opens a roctx range (for a
+ *     profiler's marker trace); the environment variable RZ_ROCTX=0, read
+ *     once per process, turns them off.
  */
 #ifndef RZ_H
 #define RZ_H
