@@ -3,13 +3,16 @@
 //
 // One scheduler thread owns the device work.  Requests wait in a FIFO queue;
 // the head is admitted as soon as its framebuffer memory fits the budget
-// pool and an in-flight slot is free, then its kernels (clear, depth pass,
-// splat accumulate, resolve: the same launchers as the one-view calls) are
-// enqueued on the least loaded of several HIP streams, after a wait for the
-// event recorded at submission on the caller's stream (if it named one), and
-// followed by an asynchronous copy of its splat status into a pinned host
-// slot and a host function that marks the request finished and wakes the
-// scheduler.  The scheduler sleeps until a submission or a completion wakes
+// pool, an in-flight slot is free and (with a work cap) the point passes in
+// flight leave room for it.  With merging, later queued requests of the same
+// cloud that fit at that moment join it as one multi-view launch.  Its
+// kernels (clear, depth pass, splat accumulate, resolve: the same launchers
+// as the one-view calls, or the batch engine's multi-view passes for a
+// group) are enqueued on the stream with the least work in flight, after a
+// wait for the event recorded at submission on the caller's stream (if it
+// named one), and followed by an asynchronous copy of its splat status into
+// a pinned host slot and a host function that marks the request finished
+// and wakes the scheduler.  The scheduler sleeps until a submission or a completion wakes
 // it, stamps completion, and returns the memory and the slot, which admits
 // the next requests while others still run.  A dry-run mode replaces the
 // device by a host timer so that admission, budgeting and failure isolation
