@@ -655,10 +655,14 @@ int rz_batch_autotune(rz_batch *b, void *stream, int32_t reps, rz_batch_opts *ch
     for (int32_t k : ks)
         for (auto &sh : shapes)
             cands.push_back({k, sh[0], sh[1], 1, 1, sh[0], sh[1]});
-    // the small per-wave tile: more waves per SIMD for the leaner shapes
+    // the small per-wave tile: more waves per SIMD for the leaner shapes,
+    // which also get narrower and wider workgroups here
+    const int32_t lean[][2] = {{64, 4}, {128, 4}, {512, 4}, {64, 8}};
     for (int32_t k : ks) {
         cands.push_back({k, 64, 16, kBinWaveSmall, 0, 128, 8});
         for (auto &sh : shapes)
+            cands.push_back({k, sh[0], sh[1], kBinWaveSmall, 0, sh[0], sh[1]});
+        for (auto &sh : lean)
             cands.push_back({k, sh[0], sh[1], kBinWaveSmall, 0, sh[0], sh[1]});
     }
     cands.push_back({4, 256, 16, 0, 1, 256, 16});
