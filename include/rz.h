@@ -576,7 +576,8 @@ typedef struct rz_request_status {
     double t_submit_us;      /* host steady clock, microseconds since the
                                 server was created                            */
     double t_admit_us;
-    double t_done_us;        /* when the scheduler saw the request complete   */
+    double t_done_us;        /* when its device work had finished (the host
+                                function after it ran), or when it failed    */
 } rz_request_status;
 
 typedef struct rz_server_stats {

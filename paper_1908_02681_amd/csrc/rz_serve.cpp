@@ -129,6 +129,7 @@ struct Req {
     uint32_t hq_status = 0;
     int32_t group = 1;         // requests in its launch
     double t_submit = 0, t_admit = 0, t_done = 0;
+    std::atomic<double> t_device_done{-1.0};   // stamped by the host function
     hipEvent_t after = nullptr;            // recorded on the caller's stream at submit
     std::atomic<bool> gpu_done{false};     // set by the host function after the work
 };
@@ -191,7 +192,10 @@ void finish(rz_server *s, Req *r, int32_t state, int32_t error)
     s->inflight_work -= r->work;   // only admitted requests finish
     r->state = state;
     r->error = error;
-    r->t_done = s->now_us();
+    // the host function's stamp when the device work finished, else now
+    // (dry run, failures)
+    const double dev = r->t_device_done.load(std::memory_order_relaxed);
+    r->t_done = dev >= 0 ? dev : s->now_us();
     if (r->slot >= 0) {
         if (!s->o.dry_run)
             r->hq_status = s->host_status[r->slot];
@@ -226,6 +230,7 @@ void on_device_done(void *p)
 {
     Req *r = static_cast<Req *>(p);
     rz_server *s = r->srv;
+    r->t_device_done.store(s->now_us(), std::memory_order_relaxed);
     std::lock_guard<std::mutex> lk(s->wake_mu);
     r->gpu_done.store(true, std::memory_order_release);
     ++s->wake_seq;
