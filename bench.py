@@ -263,7 +263,7 @@ class ServingWorld:
     def run_server(self, trace):
         rz, a = self.rz, self.a
         srv = rz.Server(a.serve_budget, streams=a.serve_streams, work_cap=self.work_cap(),
-                        merge_views=a.serve_merge)
+                        merge_views=a.serve_merge, exclusive_work=self.exclusive_work())
         ids = [srv.add_cloud(p) for p in self.pts]
         pending, status = {}, {}
         slot_owner = {sz: [None] * self.ring for sz in self.gen.SERVE_SIZES}
@@ -312,6 +312,11 @@ class ServingWorld:
         such a request runs alone while smaller ones still overlap."""
         return self.a.serve_work_cap if self.a.serve_work_cap >= 0 else 2 * max(self.npts)
 
+    def exclusive_work(self):
+        """Requests at least this large run alone: the option's value, or by
+        default none."""
+        return self.a.serve_exclusive if self.a.serve_exclusive >= 0 else 0
+
     def capacity(self):
         """Requests per second of the plain loop on back-to-back requests."""
         probe = serve_trace(200, 1e9, self.gen.CONFIG_SEEDS[5], len(self.pts))
@@ -332,6 +337,7 @@ class ServingWorld:
                            "p50_ms": round(pct(ls, 50), 3), "p99_ms": round(pct(ls, 99), 3),
                            "peak_inflight": stats["peak_inflight"],
                            "merged_requests": stats["merged_requests"],
+                           "chained_requests": stats["chained_requests"],
                            "peak_fb_MB": round(stats["peak_bytes"] / 1e6, 1)},
                 "plain": {"req_s": round(len(trace) / (tp_end - trace[0][0]), 1),
                           "gpts": round(work / (tp_end - trace[0][0]) / 1e9, 2),
@@ -437,6 +443,9 @@ def main():
     ap.add_argument("--serve-work-cap", type=int, default=-1,
                     help="server work cap in point passes (0: none; default: the work of the "
                          "largest request); see rz_server_opts")
+    ap.add_argument("--serve-exclusive", type=int, default=-1,
+                    help="server exclusive_work in point passes: requests at least this "
+                         "large run alone (0 or default: none)")
     ap.add_argument("--serve-merge", type=int, default=0,
                     help="server merge_views: queued requests of one cloud run as one "
                          "multi-view launch (0: no merging)")

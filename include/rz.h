@@ -540,6 +540,14 @@ typedef struct rz_server_opts {
                                 request at a time.  0 or 1: no merging; at most
                                 8.                                             */
     int32_t pad;
+    int64_t exclusive_work;  /* > 0: a request whose work (as for work_cap) is
+                                at least exclusive_work runs alone: it is
+                                admitted only when nothing is in flight, and
+                                nothing else is admitted until it finishes
+                                (requests behind it wait, in order).  Large
+                                requests then keep the whole device, as in a
+                                one-at-a-time loop, while small ones overlap
+                                each other.  0: no such rule.                  */
 } rz_server_opts;
 
 typedef struct rz_request {
@@ -589,6 +597,11 @@ typedef struct rz_server_stats {
     int32_t pad;
     uint64_t merged_launches;  /* multi-view launches of two or more requests  */
     uint64_t merged_requests;  /* requests that ran in such a launch           */
+    uint64_t chained_requests; /* requests admitted behind a running request on
+                                  its stream because the work cap or an
+                                  exclusive request held them back: they start
+                                  when it ends, without waiting for the
+                                  scheduler                                    */
 } rz_server_stats;
 
 typedef struct rz_server rz_server;

@@ -57,6 +57,9 @@ namespace {
 constexpr uint64_t kAlign = 256;
 constexpr int kMaxStreams = 16;
 constexpr int kMergeWindow = 32;   // queued requests scanned for a merge
+// Rough device time per point pass (about 200 G point passes per second on
+// the one-view kernels): only to guess which running request ends first.
+constexpr double kUsPerPointPass = 5e-6;
 // Launch shape of a merged group's multi-view passes: the batch engine's
 // measured best for groups of views (256 threads x 4 points, the 2 KiB
 // per-wave tile).
@@ -128,6 +131,9 @@ struct Req {
     int32_t slot = -1;         // pinned status slot
     uint32_t hq_status = 0;
     int32_t group = 1;         // requests in its launch
+    bool chained = false;      // a request was admitted behind it on its stream
+    bool queued_behind = false;   // admitted behind another request
+    double t_end_guess = 0;    // when its device work should end (dry run: does)
     double t_submit = 0, t_admit = 0, t_done = 0;
     std::atomic<double> t_device_done{-1.0};   // stamped by the host function
     hipEvent_t after = nullptr;            // recorded on the caller's stream at submit
@@ -165,8 +171,9 @@ struct rz_server {
     std::unordered_map<uint64_t, Req *> tickets;
     uint64_t next_ticket = 1;
     uint64_t submitted = 0, completed = 0, failed = 0;
-    uint64_t merged_launches = 0, merged_requests = 0;
+    uint64_t merged_launches = 0, merged_requests = 0, chained_requests = 0;
     int64_t inflight_work = 0;
+    int32_t inflight_exclusive = 0;       // requests in flight that run alone
     int32_t peak_inflight = 0;
     bool stop = false;
     std::thread th;
@@ -187,9 +194,16 @@ struct rz_server {
 
 namespace {
 
+bool exclusive(const rz_server *s, const Req *r)
+{
+    return s->o.exclusive_work > 0 && r->work >= s->o.exclusive_work;
+}
+
 void finish(rz_server *s, Req *r, int32_t state, int32_t error)
 {
     s->inflight_work -= r->work;   // only admitted requests finish
+    if (exclusive(s, r))
+        s->inflight_exclusive--;
     r->state = state;
     r->error = error;
     // the host function's stamp when the device work finished, else now
@@ -343,8 +357,10 @@ int launch_group(rz_server *s, const std::vector<Req *> &g)
     return e == hipSuccess ? RZ_OK : hip_fail(e);
 }
 
-// Admits a group of requests (one, or several of one cloud) on one stream.
-void admit(rz_server *s, const std::vector<Req *> &g)
+// Admits a group of requests (one, or several of one cloud) on one stream:
+// the stream with the least work in flight, or, with `behind`, that
+// request's stream, where the group starts as soon as it ends.
+void admit(rz_server *s, const std::vector<Req *> &g, Req *behind = nullptr)
 {
     // the stream with the least work in flight: a small request does not
     // queue behind a large one while another stream is idle or lighter
@@ -353,8 +369,22 @@ void admit(rz_server *s, const std::vector<Req *> &g)
         if (s->load[i] < s->load[best])
             best = i;
     const double now = s->now_us();
+    double start = now;
+    if (behind) {
+        best = behind->stream;
+        behind->chained = true;
+        start = std::max(now, behind->t_end_guess);
+        s->chained_requests += g.size();
+    }
+    int64_t gwork = 0;
+    for (Req *r : g)
+        gwork += r->work;
+    const double end = start + (s->o.dry_run ? (double)s->o.dry_run_us
+                                             : (double)gwork * kUsPerPointPass);
     for (Req *r : g) {
         r->t_admit = now;
+        r->t_end_guess = end;
+        r->queued_behind = behind != nullptr;
         r->slot = s->free_slots.back();
         s->free_slots.pop_back();
         r->stream = best;
@@ -362,6 +392,8 @@ void admit(rz_server *s, const std::vector<Req *> &g)
         r->state = RZ_REQ_RUNNING;
         r->group = (int32_t)g.size();
         s->inflight_work += r->work;
+        if (exclusive(s, r))
+            s->inflight_exclusive++;
         s->inflight.push_back(r);
     }
     s->peak_inflight = std::max(s->peak_inflight, (int32_t)s->inflight.size());
@@ -385,6 +417,32 @@ void admit(rz_server *s, const std::vector<Req *> &g)
     }
 }
 
+// The running request behind which the blocked head request r may start:
+// one alone on the device that is exclusive, or one at least as large as r
+// (so that the work running at once never grows), with nothing chained
+// behind it yet, not itself waiting behind another (so that blocked
+// requests do not line up on one stream) and not part of a merged group; if
+// r must run alone, only a request alone on the device.  Of those, the one
+// expected to end first.  With merging on, requests are not chained: a
+// request held back is admitted by the scheduler, with the others of its
+// cloud.
+Req *chain_target(rz_server *s, const Req *r)
+{
+    if ((r->r.flags & RZ_REQ_INJECT_FAILURE) || s->o.merge_views > 1)
+        return nullptr;
+    Req *best = nullptr;
+    for (Req *p : s->inflight) {
+        if (p->chained || p->queued_behind || p->group != 1 || p->state != RZ_REQ_RUNNING)
+            continue;
+        const bool alone = s->inflight.size() == 1;
+        const bool ok = (exclusive(s, p) && alone) ||
+                        (p->work >= r->work && (!exclusive(s, r) || alone));
+        if (ok && (!best || p->t_end_guess < best->t_end_guess))
+            best = p;
+    }
+    return best;
+}
+
 void scheduler(rz_server *s)
 {
     if (!s->o.dry_run)
@@ -400,7 +458,7 @@ void scheduler(rz_server *s)
                 Req *r = s->inflight[i];
                 bool done;
                 if (s->o.dry_run) {
-                    const double end = r->t_admit + s->o.dry_run_us;
+                    const double end = r->t_end_guess;
                     done = s->now_us() >= end;
                     if (!done && (next_deadline < 0 || end < next_deadline))
                         next_deadline = end;
@@ -419,14 +477,31 @@ void scheduler(rz_server *s)
             while (!s->queue.empty() && (int32_t)s->inflight.size() < s->o.max_inflight &&
                    !s->free_slots.empty()) {
                 Req *r = s->queue.front();
-                if (s->o.work_cap > 0 && !s->inflight.empty() &&
-                    s->inflight_work + r->work > s->o.work_cap)
+                // a request that runs alone waits for an empty device, and
+                // nothing joins it; the work cap bounds the work in flight
+                const bool blocked =
+                    (s->o.work_cap > 0 && !s->inflight.empty() &&
+                     s->inflight_work + r->work > s->o.work_cap) ||
+                    s->inflight_exclusive > 0 || (exclusive(s, r) && !s->inflight.empty());
+                // blocked: it may still go behind a running request on that
+                // request's stream, so that it starts the moment the device
+                // would otherwise wait for the scheduler
+                Req *behind = blocked ? chain_target(s, r) : nullptr;
+                if (blocked && !behind)
                     break;
                 if (!s->pool.alloc(r->bytes, &r->off))
                     break;
                 s->queue.pop_front();
+                if (behind) {
+                    admit(s, std::vector<Req *>{r}, behind);
+                    if (s->o.dry_run && r->state == RZ_REQ_RUNNING &&
+                        (next_deadline < 0 || r->t_end_guess < next_deadline))
+                        next_deadline = r->t_end_guess;
+                    continue;
+                }
                 std::vector<Req *> g{r};
-                if (s->o.merge_views > 1 && !(r->r.flags & RZ_REQ_INJECT_FAILURE)) {
+                if (s->o.merge_views > 1 && !(r->r.flags & RZ_REQ_INJECT_FAILURE) &&
+                    !exclusive(s, r)) {
                     // later requests of the same cloud that fit now join it
                     int64_t gwork = r->work;
                     int scanned = 0;
@@ -437,6 +512,7 @@ void scheduler(rz_server *s)
                         Req *q = *it;
                         const bool fits =
                             q->r.cloud == r->r.cloud && !(q->r.flags & RZ_REQ_INJECT_FAILURE) &&
+                            !exclusive(s, q) &&
                             (int32_t)(s->inflight.size() + g.size()) < s->o.max_inflight &&
                             s->free_slots.size() > g.size() &&
                             (s->o.work_cap <= 0 ||
@@ -451,11 +527,9 @@ void scheduler(rz_server *s)
                     }
                 }
                 admit(s, g);
-                if (s->o.dry_run && r->state == RZ_REQ_RUNNING) {
-                    const double end = r->t_admit + s->o.dry_run_us;
-                    if (next_deadline < 0 || end < next_deadline)
-                        next_deadline = end;
-                }
+                if (s->o.dry_run && r->state == RZ_REQ_RUNNING &&
+                    (next_deadline < 0 || r->t_end_guess < next_deadline))
+                    next_deadline = r->t_end_guess;
             }
             if (s->inflight.empty() && s->queue.empty()) {
                 s->idle_cv.notify_all();
@@ -549,7 +623,7 @@ int rz_server_create(const rz_server_opts *opts, rz_server **out)
         o.max_inflight = 4 * o.streams;
     if (o.streams < 1 || o.streams > kMaxStreams || o.max_inflight < 1 ||
         o.max_inflight > 1024 || o.budget_bytes < (1u << 20) || (o.dry_run & ~1) ||
-        o.dry_run_us < 0 || o.work_cap < 0 || o.merge_views < 0 ||
+        o.dry_run_us < 0 || o.work_cap < 0 || o.exclusive_work < 0 || o.merge_views < 0 ||
         o.merge_views > kMaxGroupViews)
         return RZ_EINVAL;
     rz_server *s = new (std::nothrow) rz_server();
@@ -701,6 +775,7 @@ int rz_server_get_stats(rz_server *s, rz_server_stats *st)
     st->inflight = (int32_t)s->inflight.size();
     st->merged_launches = s->merged_launches;
     st->merged_requests = s->merged_requests;
+    st->chained_requests = s->chained_requests;
     return RZ_OK;
 }
 

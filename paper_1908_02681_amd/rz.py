@@ -93,7 +93,7 @@ class rz_tune_entry(ctypes.Structure):
 class rz_server_opts(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("streams", c_int32), ("max_inflight", c_int32),
                 ("dry_run", c_int32), ("dry_run_us", c_int32), ("work_cap", c_int64),
-                ("merge_views", c_int32), ("pad", c_int32)]
+                ("merge_views", c_int32), ("pad", c_int32), ("exclusive_work", c_int64)]
 
 
 class rz_request(ctypes.Structure):
@@ -113,7 +113,7 @@ class rz_server_stats(ctypes.Structure):
                 ("failed", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
                 ("peak_inflight", c_int32), ("queued", c_int32), ("inflight", c_int32),
                 ("pad", c_int32), ("merged_launches", ctypes.c_uint64),
-                ("merged_requests", ctypes.c_uint64)]
+                ("merged_requests", ctypes.c_uint64), ("chained_requests", ctypes.c_uint64)]
 
 
 P = ctypes.POINTER
@@ -765,11 +765,12 @@ class Server:
     the scheduler without any device work (requests take dry_run_us)."""
 
     def __init__(self, budget_bytes, streams=4, max_inflight=0, dry_run=False, dry_run_us=0,
-                 work_cap=0, merge_views=0):
+                 work_cap=0, merge_views=0, exclusive_work=0):
         if not dry_run:
             _require_gpu()
         o = rz_server_opts(int(budget_bytes), int(streams), int(max_inflight), 1 if dry_run else 0,
-                           int(dry_run_us), int(work_cap), int(merge_views), 0)
+                           int(dry_run_us), int(work_cap), int(merge_views), 0,
+                           int(exclusive_work))
         h = c_void_p()
         _check(load().rz_server_create(ctypes.byref(o), ctypes.byref(h)), "rz_server_create")
         self._h = h

@@ -210,7 +210,9 @@ static int tune_checks()
     return bad;
 }
 
-int main()
+// argv[1]: the server's merge_views (default 4); with 0, requests held back
+// by the work cap or an exclusive request are chained behind running ones
+int main(int argc, char **argv)
 {
     if (api_checks())
         return 6;
@@ -223,7 +225,8 @@ int main()
     o.dry_run = 1;
     o.dry_run_us = 300;
     o.work_cap = 5000;
-    o.merge_views = 4;
+    o.merge_views = argc > 1 ? atoi(argv[1]) : 4;
+    o.exclusive_work = 3000;
     rz_server *s = nullptr;
     if (rz_server_create(&o, &s) != RZ_OK)
         return 1;
@@ -289,7 +292,9 @@ int main()
     if (rz_server_drain(s, 30.0) != RZ_OK)
         return 3;
     rz_server_stats fin;
-    const uint64_t merged = rz_server_get_stats(s, &fin) == RZ_OK ? fin.merged_requests : 0;
+    const bool got = rz_server_get_stats(s, &fin) == RZ_OK;
+    const uint64_t merged = got ? fin.merged_requests : 0;
+    const uint64_t chained = got ? fin.chained_requests : 0;
     // a destroy that cannot finish in time leaves the server usable
     rz_request r = make_request(ids[0], 1, 64, 64, 0);
     uint64_t k = 0;
@@ -305,5 +310,6 @@ int main()
         return 4;
     printf("served %d requests, %d errors\n", done.load(), bad.load());
     printf("merged %llu requests\n", (unsigned long long)merged);
+    printf("chained %llu requests\n", (unsigned long long)chained);
     return bad.load() == 0 && done.load() == kThreads * kPer ? 0 : 5;
 }

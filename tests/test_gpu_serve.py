@@ -279,3 +279,28 @@ def test_merged_splat_overflow_fails_only_its_request(rz):
     finally:
         s.close()
         torch.cuda.synchronize()
+
+
+def test_chained_requests_equal_alone(rz, world, alone):
+    """With a work cap and exclusive requests, requests held back are
+    admitted behind running ones on their streams (chained); every image is
+    still the one-view call's, bit for bit."""
+    import torch
+    clouds, pts, reqs = world
+    s = rz.Server(256 << 20, streams=4, max_inflight=16, work_cap=pts[2].n,
+                  exclusive_work=pts[2].n)
+    ids = [s.add_cloud(p) for p in pts]
+    imgs, tickets = [], []
+    for c, v, m, bg in reqs:
+        img = torch.full((v.width * v.height,), -1, dtype=torch.int32, device="cuda")
+        imgs.append(img)
+        tickets.append(s.submit(ids[c], v, m, img=img, background=bg))
+    s.drain(120)
+    st = [s.poll(t) for t in tickets]
+    stats = s.stats()
+    s.close()
+    say(f"[serve] chained {stats['chained_requests']} of {len(reqs)} requests")
+    assert all(x["state"] == rz.RZ_REQ_DONE and x["error"] == 0 for x in st)
+    for i, (got, want) in enumerate(zip(imgs, alone)):
+        assert np.array_equal(rz.to_u32(got), want), f"request {i} differs when chained"
+    assert stats["chained_requests"] > 0

@@ -72,22 +72,24 @@ def _build_driver(tmp_path, name, flags):
 def test_host_code_under_asan_and_ubsan(tmp_path):
     exe = _build_driver(tmp_path, "serve_asan",
                         ["-fsanitize=address,undefined", "-fno-sanitize-recover=all"])
-    run = subprocess.run([exe], capture_output=True, text=True, timeout=300,
-                         env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1"))
-    assert run.returncode == 0, (run.stdout[-2000:], run.stderr[-4000:])
-    assert "served 600 requests, 0 errors" in run.stdout
-    assert _merged(run.stdout) > 0   # the merging path ran
+    for merge in ("4", "0"):   # merging; then chaining behind running requests
+        run = subprocess.run([exe, merge], capture_output=True, text=True, timeout=300,
+                             env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1"))
+        assert run.returncode == 0, (run.stdout[-2000:], run.stderr[-4000:])
+        assert "served 600 requests, 0 errors" in run.stdout
+        assert _count(run.stdout, "merged" if merge == "4" else "chained") > 0   # the path ran
 
 
-def _merged(out):
-    line = [l for l in out.splitlines() if l.startswith("merged ")][0]
+def _count(out, what):
+    line = [l for l in out.splitlines() if l.startswith(what + " ")][0]
     return int(line.split()[1])
 
 
 def test_scheduler_under_tsan(tmp_path):
     exe = _build_driver(tmp_path, "serve_tsan", ["-fsanitize=thread"])
-    run = subprocess.run([exe], capture_output=True, text=True, timeout=300,
-                         env=dict(os.environ, TSAN_OPTIONS="halt_on_error=1"))
-    assert run.returncode == 0, (run.stdout[-2000:], run.stderr[-4000:])
-    assert "ThreadSanitizer" not in run.stderr
-    assert "served 600 requests, 0 errors" in run.stdout
+    for merge in ("4", "0"):
+        run = subprocess.run([exe, merge], capture_output=True, text=True, timeout=300,
+                             env=dict(os.environ, TSAN_OPTIONS="halt_on_error=1"))
+        assert run.returncode == 0, (run.stdout[-2000:], run.stderr[-4000:])
+        assert "ThreadSanitizer" not in run.stderr
+        assert "served 600 requests, 0 errors" in run.stdout

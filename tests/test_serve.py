@@ -195,7 +195,9 @@ def test_work_cap_keeps_large_requests_apart(rz):
     st = _wait(s, ts)
     s.close()
     assert all(x["state"] == rz.RZ_REQ_DONE for x in st)
-    spans = [(x["t_admit_us"], x["t_done_us"]) for x in st]
+    # when each request ran: every dry-run request runs 20 ms and ends at
+    # t_done (one admitted behind a running request starts when that ends)
+    spans = [(x["t_done_us"] - 20_000, x["t_done_us"]) for x in st]
     bigs = [spans[i] for i, c in enumerate(plan) if c == big]
     for (a0, a1), (b0, b1) in zip(bigs, bigs[1:]):
         assert b0 >= a1 - 1.0            # the next large request starts after the last ends
@@ -264,3 +266,55 @@ def test_merge_leaves_failures_alone(rz):
 def test_merge_views_validation(rz, bad):
     with pytest.raises(rz.RzError):
         rz.Server(64 << 20, dry_run=True, merge_views=bad)
+
+
+def test_exclusive_requests_run_alone(rz):
+    """With exclusive_work, a request at least that large waits for an empty
+    device and runs alone; smaller ones still overlap each other; arrival
+    order is kept."""
+    s = rz.Server(64 << 20, streams=4, max_inflight=8, dry_run=True, dry_run_us=20_000,
+                  exclusive_work=1000)
+    big = s.add_cloud(rz.rz_points(1, 1, 1, 1, 1000))
+    small = s.add_cloud(rz.rz_points(1, 1, 1, 1, 10))
+    plan = [small, small, big, small, small, big, small]
+    st = _wait(s, [s.submit(c, _View(32, 32), 0) for c in plan])
+    stats = s.stats()
+    s.close()
+    assert all(x["state"] == rz.RZ_REQ_DONE for x in st)
+    spans = [(x["t_done_us"] - 20_000, x["t_done_us"]) for x in st]   # when each ran
+    for i, c in enumerate(plan):
+        if c != big:
+            continue
+        a0, a1 = spans[i]
+        for j, (b0, b1) in enumerate(spans):
+            if j != i:   # nothing else ran while it did
+                assert b1 <= a0 + 1.0 or b0 >= a1 - 1.0, (i, j)
+    # the first two small requests overlapped, and so did the two after the
+    # first large one
+    assert spans[1][0] < spans[0][1] and spans[4][0] < spans[3][1]
+    for a, b in zip(st, st[1:]):
+        assert b["t_admit_us"] >= a["t_admit_us"]
+    assert stats["peak_inflight"] >= 2
+
+
+def test_blocked_request_starts_behind_a_running_one(rz):
+    """A request held back by the work cap is admitted behind a running
+    request at least as large, on its stream: it is admitted at once, runs
+    right after it (never beside it) and is counted as chained."""
+    s = rz.Server(64 << 20, streams=4, max_inflight=8, dry_run=True, dry_run_us=20_000,
+                  work_cap=1000)
+    big = s.add_cloud(rz.rz_points(1, 1, 1, 1, 1000))
+    small = s.add_cloud(rz.rz_points(1, 1, 1, 1, 10))
+    first = s.submit(big, _View(32, 32), 0)
+    time.sleep(0.003)
+    second = s.submit(big, _View(32, 32), 0)
+    third = s.submit(small, _View(32, 32), 0)    # nothing left to go behind: waits
+    a, b, c = _wait(s, [first, second, third])
+    stats = s.stats()
+    s.close()
+    assert a["state"] == b["state"] == c["state"] == rz.RZ_REQ_DONE
+    assert b["t_admit_us"] < a["t_done_us"]              # admitted while the first ran
+    assert b["stream"] == a["stream"]
+    assert b["t_done_us"] >= a["t_done_us"] + 20_000 * 0.95   # and ran after it
+    assert c["t_done_us"] >= b["t_done_us"] - 20_000 + 20_000 * 0.95 - 1.0
+    assert stats["chained_requests"] == 1
