@@ -206,10 +206,11 @@ void finish(rz_server *s, Req *r, int32_t state, int32_t error)
         s->inflight_exclusive--;
     r->state = state;
     r->error = error;
-    // the host function's stamp when the device work finished, else now
-    // (dry run, failures)
+    // the host function's stamp when the device work finished (in a dry
+    // run, when its simulated work ended), else now (failures)
     const double dev = r->t_device_done.load(std::memory_order_relaxed);
-    r->t_done = dev >= 0 ? dev : s->now_us();
+    r->t_done = dev >= 0 ? dev
+                         : (s->o.dry_run && state == RZ_REQ_DONE ? r->t_end_guess : s->now_us());
     if (r->slot >= 0) {
         if (!s->o.dry_run)
             r->hq_status = s->host_status[r->slot];
