@@ -971,8 +971,8 @@ __device__ __forceinline__ void accum_chunk(const Proj &P, uint32_t eps_num, uin
 }
 
 // Accumulate pass over one chunk with a private LDS tile per wave of
-// `words` words, two per pixel (see raster_chunk_wave).  Same result bits as
-// accum_chunk.
+// `words` words, one or two per pixel (see raster_chunk_wave and the
+// weights below).  Same result bits as accum_chunk.
 template <int PPT, bool PW>
 __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num,
                                                  uint32_t eps_den,
@@ -1036,26 +1036,44 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
             }
         }
     }
+    // Weights.  A wave of at most 512 points (PPT <= 8) adds one packed word
+    // per fragment, R | G << 17 | B << 34 | count << 51: no field of a sum
+    // over the wave can carry into the next (512 * 255 < 2^17, 512 < 2^13),
+    // so the tile holds one word per pixel and each fragment takes one LDS
+    // add; larger waves keep the accumulator's own two words.
+    constexpr bool kPacked = PPT <= 8;
+    constexpr uint32_t kPerPix = kPacked ? 1u : 2u;
     uint64_t w0[PPT], w1[PPT];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        w0[j] = (uint64_t)(c[j] & 0xFFu) | ((uint64_t)((c[j] >> 8) & 0xFFu) << 32);
-        w1[j] = (uint64_t)((c[j] >> 16) & 0xFFu) | (1ull << 32);
+        const uint32_t r = c[j] & 0xFFu, g = (c[j] >> 8) & 0xFFu, b = (c[j] >> 16) & 0xFFu;
+        if (kPacked) {
+            w0[j] = ((uint64_t)((b << 2) | (1u << 19)) << 32) | (r | (g << 17));
+            w1[j] = 0;
+        } else {
+            w0[j] = (uint64_t)r | ((uint64_t)g << 32);
+            w1[j] = (uint64_t)b | (1ull << 32);
+        }
     }
     // runs of one pixel summed in registers: unlike the depth pass's LDS
-    // minimum, the tile's two 64-bit LDS adds per fragment are slower than
-    // this merge on runs of Morton-ordered points.  Only within each group
-    // of four consecutive points: the next group lies 4 * blockDim points
-    // further on.
+    // minimum, the tile's LDS adds are slower than this merge on runs of
+    // Morton-ordered points.  Only within each group of four consecutive
+    // points: the next group lies 4 * blockDim points further on.
 #pragma unroll
     for (int j = 1; j < PPT; ++j) {
         if (j % 4 == 0)
             continue;
         const bool same = ok[j] && ok[j - 1] && pix[j] == pix[j - 1];
         w0[j] += same ? w0[j - 1] : 0ull;
-        w1[j] += same ? w1[j - 1] : 0ull;
+        if (!kPacked)
+            w1[j] += same ? w1[j - 1] : 0ull;
         ok[j - 1] = ok[j - 1] && !same;
     }
+    // the accumulator's two words of a packed sum
+    auto unpack = [](uint64_t w, uint64_t &a0, uint64_t &a1) {
+        a0 = (w & 0x1FFFFull) | (((w >> 17) & 0x1FFFFull) << 32);
+        a1 = ((w >> 34) & 0x1FFFFull) | ((w >> 51) << 32);
+    };
     const Box box = wave_box_live_min<PPT>(px, py, ok);
     const uint32_t lane = threadIdx.x & 63u;
     bool tiled = false;
@@ -1063,31 +1081,37 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
     if (box.x0 <= box.x1) {
         bw = box.x1 - box.x0 + 1;
         bh = box.y1 - box.y0 + 1;
-        tiled = (uint64_t)bw * bh <= words / 2;
+        tiled = (uint64_t)bw * bh <= words / kPerPix;
     }
     if (tiled) {
         // every accepted fragment of the wave lies in the box (see
         // raster_chunk_wave)
         const uint32_t area = bw * bh;
         const uint32_t org = box.y0 * bw + box.x0;
-        for (uint32_t i = lane; i < 2 * area; i += 64)
+        for (uint32_t i = lane; i < kPerPix * area; i += 64)
             w_tile[i] = 0ull;
         wave_sync();
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             if (ok[j]) {
-                uint64_t *t = &w_tile[2 * (__umul24(py[j], bw) + px[j] - org)];
+                uint64_t *t = &w_tile[kPerPix * (__umul24(py[j], bw) + px[j] - org)];
                 __hip_atomic_fetch_add(t, w0[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                __hip_atomic_fetch_add(t + 1, w1[j], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (!kPacked)
+                    __hip_atomic_fetch_add(t + 1, w1[j], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
         wave_sync();
         const float inv_bw = 1.0f / (float)bw;
         for (uint32_t i = lane; i < area; i += 64) {
-            const uint64_t a1 = w_tile[2 * i + 1];
-            if (a1 != 0ull) {
-                const uint64_t a0 = w_tile[2 * i];
+            uint64_t a0, a1;
+            if (kPacked) {
+                unpack(w_tile[i], a0, a1);
+            } else {
+                a0 = w_tile[2 * i];
+                a1 = w_tile[2 * i + 1];
+            }
+            if (a1 != 0ull) {   // count > 0
                 uint32_t r, col;
                 tile_rc(i, bw, inv_bw, r, col);
                 uint64_t *dst =
@@ -1102,9 +1126,12 @@ __device__ __forceinline__ void accum_chunk_wave(const Proj &P, uint32_t eps_num
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         if (ok[j]) {
+            uint64_t a0 = w0[j], a1 = w1[j];
+            if (kPacked)
+                unpack(w0[j], a0, a1);
             uint64_t *a = acc + 2 * (uint64_t)pix[j];
-            __hip_atomic_fetch_add(a, w0[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(a + 1, w1[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(a, a0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(a + 1, a1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
