@@ -469,6 +469,37 @@ def test_hq_count_limit(rz, oracle):
         del pts
 
 
+@pytest.mark.parametrize("shape", [(64, 8, 3), (64, 8, 2), (128, 4, 3), (64, 16, 2)])
+@pytest.mark.parametrize("rgb", [0xFFFFFF, 0xFF00FF, 0x00FF00])
+def test_splat_sums_at_the_tile_word_limit(rz, shape, rgb):
+    """Every point in one pixel with the same colour: with at most 8 points
+    per thread each wave adds 512 fragments into one packed tile word
+    (R | G << 17 | B << 34 | count << 51), the most a field can hold without
+    carrying; 16 points per thread take the two-word tile.  The accumulator
+    must hold exactly n times each channel and the count n (a carry would
+    show in the next field: G for a magenta cloud, R and B for a green one)."""
+    import torch
+    view = gen.View(np.diag([1.0, 1.0, 0.0, 0.0]) + np.array(
+        [[0, 0, 0, 0], [0, 0, 0, 0], [0, 0, 0, 0], [0, 0, -1.0, 0]]), 1.0, 100.0, 2, 2)
+    n = 5 * 64 * 16 * 8 + 77   # several workgroups of every shape and a ragged tail
+    block, ppt, binm = shape
+    say(f"[tile word] shape={shape} rgb={rgb:06x} n={n}")
+    pts = rz.Points(torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda"),
+                    torch.full((n,), -10.0, device="cuda"),
+                    torch.full((n,), rgb, dtype=torch.int32, device="cuda"))
+    rz.set_launch(block, ppt, 1, 0, binm)
+    try:
+        fb, acc, _, _ = rz.rasterize_hq_splat(pts, view, keep_keys=True)
+        torch.cuda.synchronize()
+    finally:
+        rz.reset_launch()
+    sums = rz.unpack_acc(acc)
+    hit = np.flatnonzero(sums[:, 3])
+    assert hit.size == 1
+    want = [n * (rgb & 0xFF), n * ((rgb >> 8) & 0xFF), n * ((rgb >> 16) & 0xFF), n]
+    assert sums[hit[0]].tolist() == want
+
+
 def _sparse_sums_equal(rz, acc, want_sums):
     """The packed device sums against the oracle's exact sums, read back only
     at the pixels the oracle accepted fragments in; every other pixel of acc
