@@ -1,7 +1,9 @@
-"""Past 2^31 points: 2^31 + 2^20 + 77 points (34 GB of planes) on a 1024x1024
-screen, 2049 or 2048 layers of points per pixel, through the direct and the
-screen-sorted paths, both methods.  Every point index, chunk base and sorted
-position beyond the 32-bit signed range is exercised.
+"""Past 2^31 points: 2^31 + 2^20 + 77 points (34 GB of planes), and the
+largest cloud the interface accepts, 2^32 - 512 points (69 GB), on a 1024x1024
+screen with about 2050 or 4096 layers of points per pixel, through the direct
+and the screen-sorted paths, both methods.  Every point index, chunk base and
+sorted position beyond the 32-bit signed range is exercised, up to the last
+unsigned 32-bit position the sorted path uses.
 
 Point i lies on the centre ray of pixel p = i mod P (P = 1024 * 1024) at depth
 1 + (i div P) / 2000, with a colour hashed from i.  The oracle checks the keys
@@ -20,7 +22,7 @@ pytestmark = pytest.mark.gpu
 
 W = H = 1024
 P = W * H
-N = (1 << 31) + (1 << 20) + 77
+SIZES = [(1 << 31) + (1 << 20) + 77, (1 << 32) - 512]   # the second: kMaxPoints
 
 
 def say(msg):
@@ -45,9 +47,10 @@ def view():
     return gen.View(vp, 0.5, 4.0, W, H)
 
 
-@pytest.fixture(scope="module")
-def planes(rz):
+@pytest.fixture(scope="module", params=SIZES, ids=["2^31+", "2^32-512"])
+def planes(rz, request):
     import torch
+    N = request.param
     torch.cuda.empty_cache()
     say(f"[max] generating {N} points on the device")
     x = torch.empty(N, dtype=torch.float32, device="cuda")
@@ -64,7 +67,7 @@ def planes(rz):
         x[s:s + i.numel()] = cx * d
         y[s:s + i.numel()] = cy * d
         z[s:s + i.numel()] = -d
-        c[s:s + i.numel()] = ((i * 2654435761) >> 7).bitwise_and(0xFFFFFF).to(torch.int32)
+        c[s:s + i.numel()] = (i * 40503 + (i >> 13)).bitwise_and(0xFFFFFF).to(torch.int32)
         del i, p, d, cx, cy
     torch.cuda.synchronize()
     yield rz.Points(x, y, z, c)
@@ -75,7 +78,7 @@ def planes(rz):
 def sampled_points(pts, pix):
     """Every point of the given pixels, read back from the device planes."""
     import torch
-    idx = np.concatenate([np.arange(p, N, P, dtype=np.int64) for p in pix])
+    idx = np.concatenate([np.arange(p, pts.n, P, dtype=np.int64) for p in pix])
     t = torch.from_numpy(idx).to("cuda")
     out = [pts.x[t].cpu().numpy(), pts.y[t].cpu().numpy(), pts.z[t].cpu().numpy(),
            pts.rgb[t].cpu().numpy().view(np.uint32)]
@@ -108,7 +111,7 @@ def test_past_two_to_the_31_points(rz, oracle, planes, path):
     pix = np.unique(np.concatenate([[0, 76, 77, P - 1], rng.integers(0, P, 2046)]))
     sx, sy, sz, sc = sampled_points(planes, pix)
     want_keys, want_sums, _ = oracle.render_hq(sx, sy, sz, sc, v.vp, v.near, v.far, W, H)
-    ws = rz.new_workspace(N, W, H) if path == "sorted" else None
+    ws = rz.new_workspace(planes.n, W, H) if path == "sorted" else None
     keys, _ = run(rz, planes, v, path, False, ws)
     hkeys, sums = run(rz, planes, v, path, True, ws)
     del ws
