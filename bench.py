@@ -6,8 +6,10 @@ One step = one frame of both methods over the same resident cloud:
   HQ splat   : depth pass + accumulate pass (k_hq_accum) + resolve (k_resolve_hq)
 Value = points rasterized per second over the step (each method's frame
 counts its N points once): Gpoints/s.  Inputs are resident in HBM before the
-timed region.  Per-kernel durations come from HIP events recorded on the
-launch stream around each pass, averaged over the timed steps.
+timed region.  Before the W warm-up steps the step runs untimed for
+--settle-ms of wall time (reported as detail.settle), so that the timed steps
+start at the GPU's sustained clock.  Per-kernel durations come from HIP events
+recorded on the launch stream around each pass, averaged over the timed steps.
 
     python bench.py [--steps K] [--warmup W] [--workload terrain50m|spheres1m|...]
 """
