@@ -1,0 +1,166 @@
+"""Seeded random scenes through the one-view calls against the oracle, bit for
+bit: cloud shape (blobs, box, plane, spherical shell, stacks of duplicate
+positions), size (empty to 250k, ragged), point order, camera, resolution
+(1x1 to 801x599), depth map (linear, scale, piecewise), eps, background,
+launch shape and path (direct, screen-sorted).  Keys, exact splat sums and
+images are compared; each case names its seed and parameters first."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1908_02681_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+CASES = 200
+Q40 = float((1 << 40) - 2)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rz():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1908_02681_amd import rz as binding
+    binding.load()
+    yield binding
+    binding.reset_launch()
+
+
+def random_cloud(rng):
+    n = int(rng.choice([0, 1, 63, 64, 65, 1000, 4097, 30_000, 120_000, 250_000]))
+    kind = str(rng.choice(["blobs", "box", "plane", "shell", "dups"]))
+    if kind == "blobs":
+        centres = rng.uniform(-1, 1, (int(rng.integers(1, 9)), 3))
+        pick = rng.integers(0, len(centres), n)
+        p = centres[pick] + rng.normal(0, float(rng.uniform(0.01, 0.3)), (n, 3))
+    elif kind == "box":
+        p = rng.uniform(-1, 1, (n, 3))
+    elif kind == "plane":
+        u, v = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+        a, b = rng.normal(size=3), rng.normal(size=3)
+        p = u[:, None] * a + v[:, None] * b
+    elif kind == "shell":
+        d = rng.normal(size=(n, 3))
+        p = d / np.maximum(np.linalg.norm(d, axis=1, keepdims=True), 1e-9) * rng.uniform(0.3, 1)
+    else:   # many points on few positions, colours differing: ties on the key's depth
+        base = rng.uniform(-1, 1, (max(1, n // 50), 3))
+        p = base[rng.integers(0, len(base), n)]
+    p = p.astype(np.float32)
+    rgb = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)   # bits 24-31 ignored
+    order = str(rng.choice(["as made", "shuffled", "sorted by x"]))
+    if order == "shuffled":
+        perm = rng.permutation(n)
+        p, rgb = p[perm], rgb[perm]
+    elif order == "sorted by x":
+        perm = np.argsort(p[:, 0], kind="stable")
+        p, rgb = p[perm], rgb[perm]
+    cloud = gen.Cloud(np.ascontiguousarray(p[:, 0]), np.ascontiguousarray(p[:, 1]),
+                      np.ascontiguousarray(p[:, 2]), rgb)
+    return cloud, f"{kind} n={n} {order}"
+
+
+def random_view(rng):
+    w = int(rng.choice([1, 2, 7, 64, 333, 640, 801]))
+    h = int(rng.choice([1, 3, 48, 240, 480, 599]))
+    d = rng.normal(size=3)
+    eye = d / np.linalg.norm(d) * rng.uniform(1.5, 6.0)
+    target = rng.uniform(-0.3, 0.3, 3)
+    up = (0.0, 1.0, 0.0) if abs(d[1] / np.linalg.norm(d)) < 0.95 else (1.0, 0.0, 0.0)
+    dist = float(np.linalg.norm(eye - target))
+    if rng.random() < 0.75:   # the cloud (within about 1.7 of the origin) between near and far
+        near = float(rng.uniform(0.01, max(0.02, dist - 1.8)))
+        far = float((dist + 1.8) * 10 ** rng.uniform(0, 2))
+    else:                     # near and far anywhere: clipping by depth
+        near = float(10 ** rng.uniform(-2, 0))
+        far = float(near * 10 ** rng.uniform(1, 3))
+    fovy = float(rng.uniform(20, 100))
+    return gen.make_view(eye, target, up, fovy, w, h, near, far), f"{w}x{h} near={near:.3g} far={far:.3g}"
+
+
+def random_depth(rng, view):
+    kind = int(rng.integers(0, 3))
+    if kind == 0:
+        return (0, 0.0)
+    if kind == 1:
+        return (1, float(rng.uniform(0.05, 1.0) * Q40 / view.far))
+    # piecewise: up to three ranges from 0, breakpoints inside (near, far),
+    # each range spanning at most 2^38 quanta
+    nr = int(rng.integers(1, 4))
+    cuts = np.sort(rng.uniform(view.near, view.far, nr - 1))
+    starts = [0.0] + [float(c) for c in cuts]
+    ends = starts[1:] + [view.far]
+    ranges = tuple((s, float(rng.uniform(0.1, 1.0) * 2.0 ** 38 / max(e - s, 1e-6)))
+                   for s, e in zip(starts, ends))
+    return (2, ranges)
+
+
+def gpu_frames(rz, pts, view, depth, eps, bg, path, ws):
+    """Keys, exact sums and both images of one call each (raw buffers kept,
+    then resolved)."""
+    import torch
+    npix = view.width * view.height
+    fb, acc = rz.new_framebuffer(view, bg, hq=True)
+    if path == "sorted":
+        rz.rasterize_sorted(pts, view, depth, False, eps, bg, fb=fb, acc=acc, workspace=ws,
+                            keep_keys=True)
+    else:
+        rz.rasterize_atomicmin(pts, view, depth, bg, fb=fb, keep_keys=True)
+    keys = rz.to_u64(fb)
+    img = rz.to_u32(rz.resolve_min(fb, npix, bg))
+    if path == "sorted":
+        rz.rasterize_sorted(pts, view, depth, True, eps, bg, fb=fb, acc=acc, workspace=ws,
+                            keep_keys=True)
+    else:
+        rz.rasterize_hq_splat(pts, view, depth, eps, bg, fb=fb, acc=acc, keep_keys=True)
+    hkeys = rz.to_u64(fb)
+    sums = rz.unpack_acc(acc)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    himg = rz.to_u32(rz.resolve_hq(fb, acc, npix, bg, status=status))
+    torch.cuda.synchronize()
+    cleared = rz.to_u64(fb)
+    return keys, img, hkeys, sums, himg, int(status.item()), cleared, rz.to_u64(acc)
+
+
+@pytest.mark.parametrize("seed", range(CASES))
+def test_random_scene(rz, oracle, seed):
+    rng = np.random.default_rng([1908, seed])
+    cloud, what = random_cloud(rng)
+    view, cam = random_view(rng)
+    depth = random_depth(rng, view)
+    den = int(rng.choice([1, 7, 100, 1000, 1 << 20]))
+    eps = (int(rng.choice([0, 1, 3, den])), den)
+    bg = int(rng.integers(0, 1 << 32))
+    shape = (int(rng.choice([64, 256, 512])), int(rng.choice([4, 8, 16])),
+             int(rng.integers(0, 2)), int(rng.integers(0, 2)), int(rng.integers(0, 4)))
+    buckets = ((view.width + 63) // 64) * ((view.height + 63) // 64)
+    path = str(rng.choice(["direct", "sorted"])) if buckets <= 4096 else "direct"
+    say(f"[random] seed={seed} {what} {cam} depth={depth[0]} eps={eps} bg={bg:#x} "
+        f"launch={shape} path={path}")
+    want_keys, want_img = oracle.render_atomicmin(cloud.x, cloud.y, cloud.z, cloud.rgb, view.vp,
+                                                  view.near, view.far, view.width, view.height,
+                                                  depth[0], depth[1], bg)
+    hk, want_sums, want_himg = oracle.render_hq(cloud.x, cloud.y, cloud.z, cloud.rgb, view.vp,
+                                                view.near, view.far, view.width, view.height,
+                                                depth[0], depth[1], eps, bg)
+    assert np.array_equal(hk, want_keys)
+    pts = rz.Points.from_cloud(cloud)
+    ws = rz.new_workspace(cloud.n, view.width, view.height) if path == "sorted" else None
+    rz.set_launch(*shape)
+    try:
+        keys, img, hkeys, sums, himg, status, cleared, acc = gpu_frames(rz, pts, view, depth,
+                                                                        eps, bg, path, ws)
+    finally:
+        rz.reset_launch()
+    assert np.array_equal(keys, want_keys), f"keys differ at {np.flatnonzero(keys != want_keys)[:8]}"
+    assert np.array_equal(img, want_img)
+    assert np.array_equal(hkeys, want_keys)
+    assert np.array_equal(sums, want_sums), f"sums differ at {np.flatnonzero((sums != want_sums).any(1))[:8]}"
+    assert np.array_equal(himg, want_himg)
+    assert status == 0
+    assert (cleared == np.uint64(oracle.clear_value(bg))).all() and (acc == 0).all()
