@@ -1,9 +1,11 @@
-"""Seeded random scenes through the one-view calls against the oracle, bit for
-bit: cloud shape (blobs, box, plane, spherical shell, stacks of duplicate
-positions), size (empty to 250k, ragged), point order, camera, resolution
-(1x1 to 801x599), depth map (linear, scale, piecewise), eps, background,
-launch shape and path (direct, screen-sorted).  Keys, exact splat sums and
-images are compared; each case names its seed and parameters first."""
+"""Seeded random scenes against the oracle, bit for bit: cloud shape (blobs,
+box, plane, spherical shell, stacks of duplicate positions), size (empty to
+250k, ragged), point order, camera, resolution (1x1 to 801x599), depth map
+(linear, scale, piecewise; the float encodings for points of any size), eps,
+background, launch shape and path (direct, screen-sorted), point size (1 to
+16 pixels), and batches of up to 20 views with mixed methods, depth maps and
+group sizes.  Keys, exact splat sums and images are compared; each case names
+its seed and parameters first."""
 import sys
 
 import numpy as np
@@ -32,8 +34,11 @@ def rz():
     binding.reset_launch()
 
 
-def random_cloud(rng):
-    n = int(rng.choice([0, 1, 63, 64, 65, 1000, 4097, 30_000, 120_000, 250_000]))
+SIZES = [0, 1, 63, 64, 65, 1000, 4097, 30_000, 120_000, 250_000]
+
+
+def random_cloud(rng, sizes=SIZES):
+    n = int(rng.choice(sizes))
     kind = str(rng.choice(["blobs", "box", "plane", "shell", "dups"]))
     if kind == "blobs":
         centres = rng.uniform(-1, 1, (int(rng.integers(1, 9)), 3))
@@ -83,10 +88,10 @@ def random_view(rng):
     return gen.make_view(eye, target, up, fovy, w, h, near, far), f"{w}x{h} near={near:.3g} far={far:.3g}"
 
 
-def random_depth(rng, view):
-    kind = int(rng.integers(0, 3))
-    if kind == 0:
-        return (0, 0.0)
+def random_depth(rng, view, kind=None):
+    kind = int(rng.integers(0, 3)) if kind is None else kind
+    if kind in (0, 3, 4):   # linear, or the float encodings (no map parameters)
+        return (kind, 0.0)
     if kind == 1:
         return (1, float(rng.uniform(0.05, 1.0) * Q40 / view.far))
     # piecewise: up to three ranges from 0, breakpoints inside (near, far),
@@ -164,3 +169,87 @@ def test_random_scene(rz, oracle, seed):
     assert np.array_equal(himg, want_himg)
     assert status == 0
     assert (cleared == np.uint64(oracle.clear_value(bg))).all() and (acc == 0).all()
+
+
+POINT_CASES = 80
+
+
+@pytest.mark.parametrize("seed", range(POINT_CASES))
+def test_random_points(rz, oracle, seed):
+    """rasterize_points: squares of k x k pixels, every depth encoding."""
+    import torch
+    rng = np.random.default_rng([1909, seed])
+    cloud, what = random_cloud(rng, [0, 1, 65, 1000, 4097, 30_000, 60_000])
+    view, cam = random_view(rng)
+    k = int(rng.choice([1, 2, 3, 4, 5, 7, 11, 16]))
+    enc = int(rng.integers(0, 5))   # linear, scale, piecewise, 24-bit window, reversed float
+    depth = random_depth(rng, view, enc)
+    hq = enc < 3 and bool(rng.random() < 0.7)
+    den = int(rng.choice([1, 7, 100, 1000]))
+    eps = (int(rng.choice([0, 1, 3, den])), den)
+    bg = int(rng.integers(0, 1 << 32))
+    say(f"[random points] seed={seed} {what} {cam} k={k} depth={depth[0]} hq={hq} eps={eps}")
+    args = (cloud.x, cloud.y, cloud.z, cloud.rgb, view.vp, view.near, view.far, view.width,
+            view.height, depth[0], depth[1])
+    pts = rz.Points.from_cloud(cloud)
+    want_keys, want_img = oracle.render_atomicmin(*args, bg=bg, point_size=k)
+    fb, acc = rz.new_framebuffer(view, bg, hq=False)
+    rz.rasterize_points(pts, view, depth, False, eps, k, bg, fb=fb, keep_keys=True)
+    keys = rz.to_u64(fb)
+    _, _, img, _ = rz.rasterize_points(pts, view, depth, False, eps, k, bg)
+    torch.cuda.synchronize()
+    assert np.array_equal(keys, want_keys), f"keys differ at {np.flatnonzero(keys != want_keys)[:8]}"
+    assert np.array_equal(rz.to_u32(img), want_img)
+    if hq:
+        hk, want_sums, want_himg = oracle.render_hq(*args, eps=eps, bg=bg, point_size=k)
+        fb, acc = rz.new_framebuffer(view, bg, hq=True)
+        rz.rasterize_points(pts, view, depth, True, eps, k, bg, fb=fb, acc=acc, keep_keys=True)
+        hkeys, sums = rz.to_u64(fb), rz.unpack_acc(acc)
+        _, _, himg, st = rz.rasterize_points(pts, view, depth, True, eps, k, bg)
+        torch.cuda.synchronize()
+        assert np.array_equal(hkeys, hk)
+        assert np.array_equal(sums, want_sums)
+        assert np.array_equal(rz.to_u32(himg), want_himg) and int(st.item()) == 0
+
+
+BATCH_CASES = 30
+
+
+@pytest.mark.parametrize("seed", range(BATCH_CASES))
+def test_random_batch(rz, oracle, seed):
+    """rz_batch_*: up to 20 random views of one cloud, mixed methods, depth
+    maps and backgrounds, random group size, launch shape and graph use; two
+    runs, each image against the oracle's."""
+    import torch
+    rng = np.random.default_rng([1910, seed])
+    cloud, what = random_cloud(rng, [1, 65, 4097, 30_000, 120_000])
+    nv = int(rng.integers(1, 21))
+    views, modes, depths, bgs = [], [], [], []
+    for _ in range(nv):
+        v, _ = random_view(rng)
+        views.append(v)
+        modes.append(int(rng.integers(0, 2)))
+        depths.append(random_depth(rng, v))
+        bgs.append(int(rng.integers(0, 1 << 32)))
+    den = int(rng.choice([1, 7, 100, 1000]))
+    eps = (int(rng.choice([0, 1, 3, den])), den)
+    k = int(rng.integers(0, 9))   # 0: the library's choice
+    shape = (int(rng.choice([64, 128, 256, 512])), int(rng.choice([4, 8, 16])),
+             int(rng.integers(0, 2)), int(rng.integers(0, 2)), int(rng.integers(0, 4)))
+    graph = bool(rng.random() < 0.5)
+    say(f"[random batch] seed={seed} {what} views={nv} modes={modes} eps={eps} k={k} "
+        f"launch={shape} graph={graph}")
+    pts = rz.Points.from_cloud(cloud)
+    b = rz.Batch(pts, views, modes, depth=depths, eps=eps, backgrounds=bgs, views_per_group=k,
+                 launch=shape, use_graph=graph)
+    want = []
+    for v, m, d, bg in zip(views, modes, depths, bgs):
+        args = (cloud.x, cloud.y, cloud.z, cloud.rgb, v.vp, v.near, v.far, v.width, v.height,
+                d[0], d[1])
+        want.append(oracle.render_hq(*args, eps=eps, bg=bg)[2] if m == 1
+                    else oracle.render_atomicmin(*args, bg=bg)[1])
+    for run in range(2):
+        b.run()
+        torch.cuda.synchronize()
+        for i, (img, w) in enumerate(zip(b.imgs, want)):
+            assert np.array_equal(rz.to_u32(img), w), f"run {run} view {i} differs"
