@@ -253,3 +253,57 @@ def test_random_batch(rz, oracle, seed):
         torch.cuda.synchronize()
         for i, (img, w) in enumerate(zip(b.imgs, want)):
             assert np.array_equal(rz.to_u32(img), w), f"run {run} view {i} differs"
+
+
+SERVE_CASES = 40
+
+
+@pytest.mark.parametrize("seed", range(SERVE_CASES))
+def test_random_serving(rz, oracle, seed):
+    """rz_server_*: random clouds and requests (views, methods, integer depth
+    maps, eps, backgrounds) under random budgets, streams, work caps,
+    exclusive sizes and request merging; every image against the oracle."""
+    import torch
+    rng = np.random.default_rng([1911, seed])
+    clouds = [random_cloud(rng, [1, 65, 4097, 30_000, 120_000])[0]
+              for _ in range(int(rng.integers(1, 5)))]
+    nreq = int(rng.integers(5, 61))
+    reqs = []
+    for _ in range(nreq):
+        c = int(rng.integers(0, len(clouds)))
+        v, _ = random_view(rng)
+        reqs.append((c, v, int(rng.integers(0, 2)), random_depth(rng, v),
+                     int(rng.integers(0, 1 << 32))))
+    den = int(rng.choice([1, 7, 100, 1000]))
+    eps = (int(rng.choice([0, 1, 3, den])), den)
+    biggest = 2 * max(cl.n for cl in clouds)
+    opts = dict(budget_bytes=int(rng.choice([16, 64, 512])) << 20,
+                streams=int(rng.choice([1, 2, 4, 8])),
+                work_cap=int(rng.choice([0, biggest, max(1, biggest // 3)])),
+                merge_views=int(rng.choice([0, 0, 2, 8])),
+                exclusive_work=int(rng.choice([0, 0, max(1, biggest // 2)])))
+    say(f"[random serve] seed={seed} clouds={[cl.n for cl in clouds]} requests={nreq} "
+        f"eps={eps} {opts}")
+    pts = [rz.Points.from_cloud(cl) for cl in clouds]
+    s = rz.Server(**opts)
+    try:
+        ids = [s.add_cloud(p) for p in pts]
+        imgs, tickets = [], []
+        for c, v, m, d, bg in reqs:
+            img = torch.full((v.width * v.height,), -1, dtype=torch.int32, device="cuda")
+            imgs.append(img)
+            tickets.append(s.submit(ids[c], v, m, img=img, depth=d, eps=eps, background=bg))
+        s.drain(120)
+        st = [s.poll(t) for t in tickets]
+        stats = s.stats()
+    finally:
+        s.close()
+    assert stats["completed"] == nreq and stats["failed"] == 0
+    assert stats["peak_bytes"] <= opts["budget_bytes"]
+    for i, ((c, v, m, d, bg), img, x) in enumerate(zip(reqs, imgs, st)):
+        assert x["state"] == rz.RZ_REQ_DONE and x["error"] == 0, f"request {i}: {x}"
+        cl = clouds[c]
+        args = (cl.x, cl.y, cl.z, cl.rgb, v.vp, v.near, v.far, v.width, v.height, d[0], d[1])
+        want = (oracle.render_hq(*args, eps, bg)[2] if m == 1
+                else oracle.render_atomicmin(*args, bg)[1])
+        assert np.array_equal(rz.to_u32(img), want), f"request {i} differs"
