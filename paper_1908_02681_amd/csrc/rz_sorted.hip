@@ -8,7 +8,7 @@
 //                      (LDS histogram); one row of counts per workgroup
 //   B  k_sort_prefix   per bucket: each workgroup's offset (prefix over
 //                      workgroups) and the bucket's total
-//      k_sort_scan     bucket starts and the chunk work list of D and E
+//      k_sort_scan     bucket starts and the chunk work list of E
 //   C  k_sort_scatter  the same ranges again, with the whole fragment (depth
 //                      in double precision).  Per step of 4096 points the
 //                      workgroup sorts its entries by bucket in LDS (a
@@ -16,7 +16,8 @@
 //                      own cursor in that bucket: consecutive lanes write
 //                      consecutive entries.  Entry = key (u64) + pixel in
 //                      the tile (u16).  (8192 points per step)
-//   D  k_sort_raster   per chunk of a bucket: LDS minimum over the tile, then
+//   D  k_sort_raster   an equal share of the entries per workgroup; per run
+//                      of one bucket in it: LDS minimum over the tile, then
 //                      one coalesced early-out atomic per touched pixel
 //   E  k_sort_accum    per chunk: the tile's nearest depths staged in LDS,
 //                      the eps window, LDS sums, one flush per pixel
@@ -60,6 +61,7 @@ constexpr int kScPpt = 8;
 constexpr int kScStep = kScBlock * kScPpt;
 constexpr int kScBuckets = kMaxBuckets / kScBlock;   // buckets per thread in C's scan
 constexpr int kRasterBlock = 256;
+constexpr int kRasterGroups = 512;            // pass D: two workgroups per CU
 constexpr int kAccumBlock = 1024;
 constexpr int kUnroll = 8;                    // bucket entries in flight per thread (D, E)
 constexpr int kPrefixCols = 32;               // pass B: columns per workgroup
@@ -74,7 +76,7 @@ size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 struct Layout {
     int32_t ntx = 0, nty = 0, nb = 0, groups = 0;
     int64_t per_wg = 0;
-    uint32_t chunk = 0;          // bucket entries per work item of D and E
+    uint32_t chunk = 0;          // bucket entries per work item of E
     int64_t chunks_max = 0;      // bound on the work items
     size_t ccounts = 0, btotal = 0, bstart = 0, bchunk = 0, keys = 0, lps = 0, bytes = 0;
 };
@@ -106,7 +108,7 @@ Layout layout(int64_t n, int32_t w, int32_t h)
     L.ccounts = take((size_t)L.groups * L.nb * 4);
     L.btotal = take((size_t)L.nb * 4);
     L.bstart = take(((size_t)L.nb + 1) * 4);
-    L.bchunk = take(((size_t)L.nb + 1) * 4);
+    L.bchunk = take(((size_t)L.nb + 1 + L.chunks_max) * 4);   // + the bucket of each item
     L.keys = take((size_t)n * 8);
     L.lps = take((size_t)n * 2);
     L.bytes = o;
@@ -227,16 +229,32 @@ __global__ void __launch_bounds__(kPrefixCols * kPrefixSegs)
     }
 }
 
+// Last index a with list[a] <= b (list[0] = 0 <= b < list[count]).
+__device__ __forceinline__ int32_t find_item(const uint32_t *list, int32_t count, uint32_t b)
+{
+    int32_t a = 0, z = count;
+    while (z - a > 1) {
+        const int32_t m = (a + z) >> 1;
+        if (list[m] <= b)
+            a = m;
+        else
+            z = m;
+    }
+    return a;
+}
+
 // Pass B, second part: one workgroup, 4 buckets per thread.
 //   bstart  exclusive scan of the bucket totals; bstart[nb] = all entries;
-//   bchunk  exclusive scan of ceil(total / chunk): the work items of D and E;
-//           bchunk[nb] = all work items.
+//   bchunk  exclusive scan of ceil(total / chunk): the work items of E;
+//           bchunk[nb] = all work items, then from bchunk[nb + 1] on the
+//           bucket of each work item.
 __global__ void __launch_bounds__(kScanThreads) k_sort_scan(const uint32_t *total,
                                                             uint32_t *bstart, uint32_t *bchunk,
                                                             int32_t nb, uint32_t chunk)
 {
     constexpr int K = kMaxBuckets / kScanThreads;
     __shared__ uint32_t s_sum[kScanThreads], s_ch[kScanThreads];
+    __shared__ uint32_t s_first[kMaxBuckets + 1];   // each bucket's first item
     const int32_t t0 = threadIdx.x * K;
     uint32_t v[K];
     uint32_t local = 0, lch = 0;
@@ -264,14 +282,23 @@ __global__ void __launch_bounds__(kScanThreads) k_sort_scan(const uint32_t *tota
         if (t0 + k < nb) {
             bstart[t0 + k] = run;
             bchunk[t0 + k] = runc;
+            s_first[t0 + k] = runc;
         }
         run += v[k];
         runc += (v[k] + chunk - 1) / chunk;
     }
+    const uint32_t items = s_ch[kScanThreads - 1];
     if (threadIdx.x == kScanThreads - 1) {
         bstart[nb] = s_sum[kScanThreads - 1];
-        bchunk[nb] = s_ch[kScanThreads - 1];
+        bchunk[nb] = items;
     }
+    __syncthreads();
+    // the item table after bchunk[nb]: the bucket of each work item of E
+    // (the last bucket whose first item is <= the item; empty buckets share
+    // their successor's first item and never own one)
+    uint32_t *item_bucket = bchunk + nb + 1;
+    for (uint32_t i = threadIdx.x; i < items; i += kScanThreads)
+        item_bucket[i] = (uint32_t)find_item(s_first, nb, i);
 }
 
 // Pass C: the fragments of pass A's ranges, sorted into the buckets.
@@ -315,9 +342,8 @@ __global__ void __launch_bounds__(kScBlock) k_sort_scatter(Pts p, Proj P,
         for (int r = 0; r < kScBuckets; ++r)
             if (b0 + r < nb)
                 s_off[b0 + r] = 0u;
-        uint32_t lb[kScPpt], rank[kScPpt];
+        uint32_t lb[kScPpt], rank[kScPpt];   // rank ~0: not on screen
         uint64_t key[kScPpt];
-        bool vis[kScPpt];
         __syncthreads();   // counters zero (and the previous step's write-out done)
 #pragma unroll
         for (int j = 0; j < kScPpt; ++j) {
@@ -326,16 +352,16 @@ __global__ void __launch_bounds__(kScBlock) k_sort_scatter(Pts p, Proj P,
             double tq;
             bool v = false;
             const bool live = fragment<PW>(P, T, x[j], y[j], z[j], px, py, qq, tq, v);
-            vis[j] = v;
             key[j] = live ? (qq << 24) | ((uint64_t)c[j] & kRgbMask) : ~0ull;
             lb[j] = bucket_pixel(px, py, ntx);
-            rank[j] = v ? atomicAdd(&s_off[lb[j] >> 12], 1u) : 0u;
+            rank[j] = v ? atomicAdd(&s_off[lb[j] >> 12], 1u) : ~0u;
         }
         if (base + kScStep < q.n)   // workgroup-uniform
             load_points_nan<kScPpt, VEC>(q, base + kScStep, x, y, z, c);
         __syncthreads();   // counts complete
-        // exclusive scan of the counts over the buckets
-        uint32_t cnt[kScBuckets], off[kScBuckets];
+        // exclusive scan of the counts over the buckets; staging index i of
+        // bucket b goes to cursor(b) + (i - off(b)): each bucket's delta
+        uint32_t cnt[kScBuckets], delta[kScBuckets];
         uint32_t sum = 0;
 #pragma unroll
         for (int r = 0; r < kScBuckets; ++r) {
@@ -351,7 +377,8 @@ __global__ void __launch_bounds__(kScBlock) k_sort_scatter(Pts p, Proj P,
             run += s_wsum[w];
 #pragma unroll
         for (int r = 0; r < kScBuckets; ++r) {
-            off[r] = run;
+            delta[r] = cur[r] - run;
+            cur[r] += cnt[r];
             if (b0 + r < nb)
                 s_off[b0 + r] = run;
             run += cnt[r];
@@ -361,20 +388,17 @@ __global__ void __launch_bounds__(kScBlock) k_sort_scatter(Pts p, Proj P,
         __syncthreads();   // offsets complete
 #pragma unroll
         for (int j = 0; j < kScPpt; ++j) {
-            if (vis[j]) {
+            if (rank[j] != ~0u) {
                 const uint32_t i = s_off[lb[j] >> 12] + rank[j];
                 s_key[i] = key[j];
                 s_lb[i] = lb[j];
             }
         }
         __syncthreads();   // staging complete, offsets read
-        // staging index i of bucket b goes to cursor(b) + (i - off(b))
 #pragma unroll
-        for (int r = 0; r < kScBuckets; ++r) {
+        for (int r = 0; r < kScBuckets; ++r)
             if (b0 + r < nb)
-                s_off[b0 + r] = cur[r] - off[r];
-            cur[r] += cnt[r];
-        }
+                s_off[b0 + r] = delta[r];
         __syncthreads();   // deltas complete
         const uint32_t total = s_total;
         for (uint32_t i = tid; i < total; i += kScBlock) {
@@ -387,86 +411,108 @@ __global__ void __launch_bounds__(kScBlock) k_sort_scatter(Pts p, Proj P,
     }
 }
 
-// Last index a with list[a] <= b (list[0] = 0 <= b < list[count]).
-__device__ __forceinline__ int32_t find_item(const uint32_t *list, int32_t count, uint32_t b)
-{
-    int32_t a = 0, z = count;
-    while (z - a > 1) {
-        const int32_t m = (a + z) >> 1;
-        if (list[m] <= b)
-            a = m;
-        else
-            z = m;
-    }
-    return a;
-}
-
-// The work item of this workgroup in passes D and E: bucket t and the range
+// The work item b of a workgroup of pass E: bucket t and the range
 // [lo, hi) of its entries, at most `chunk` of them.  Workgroups past the
 // last item get lo >= hi.
 __device__ __forceinline__ void chunk_of(const uint32_t *bstart, const uint32_t *bchunk,
-                                         int32_t nb, uint32_t chunk, int32_t &t, uint32_t &lo,
-                                         uint32_t &hi)
+                                         int32_t nb, uint32_t chunk, uint32_t b, int32_t &t,
+                                         uint32_t &lo, uint32_t &hi)
 {
-    const uint32_t b = blockIdx.x;
+    const uint32_t items = bchunk[nb];
+    const uint32_t tb = bchunk[nb + 1 + b];   // in the table (b < its length), read early
     t = 0;
     hi = lo = 0;
-    if (b >= bchunk[nb])
+    if (b >= items)
         return;
-    t = find_item(bchunk, nb, b);
+    t = (int32_t)tb;
     const uint32_t end = bstart[t + 1];
     lo = bstart[t] + (b - bchunk[t]) * chunk;
     hi = end - lo > chunk ? lo + chunk : end;
 }
 
-// Pass D: depth pass of one chunk of a bucket (section 2.1's minimum).
+// Pass D: depth pass (section 2.1's minimum) over an equal share of the
+// sorted entries per workgroup, whatever buckets it spans: each run of the
+// share that lies in one bucket is reduced in the LDS tile, then flushed
+// with one coalesced early-out atomic per touched pixel.  Equal shares keep
+// every CU's load the same (work items of whole buckets left the CUs with
+// two full items a third above the mean).
 __global__ void __launch_bounds__(kRasterBlock) k_sort_raster(const uint64_t *__restrict__ keys,
                                                               const uint16_t *__restrict__ lps,
                                                               const uint32_t *__restrict__ bstart,
-                                                              const uint32_t *__restrict__ bchunk,
                                                               uint64_t *__restrict__ fb,
                                                               int32_t ntx, int32_t nb,
-                                                              uint32_t chunk, int32_t width)
+                                                              int32_t width)
 {
     __shared__ uint64_t tile[kTilePix];
-    int32_t t;
-    uint32_t lo, hi;
-    chunk_of(bstart, bchunk, nb, chunk, t, lo, hi);
+    __shared__ uint32_t s_start[kMaxBuckets + 1];
+    for (int i = threadIdx.x; i <= nb; i += kRasterBlock)
+        s_start[i] = bstart[i];
+    __syncthreads();
+    const uint32_t total = s_start[nb];
+    const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
+    const uint64_t lo64 = (uint64_t)blockIdx.x * per;
+    uint32_t lo = lo64 < total ? (uint32_t)lo64 : total;
+    const uint32_t hi = total - lo > per ? lo + per : total;
     if (lo >= hi)
         return;
-    for (int i = threadIdx.x; i < kTilePix; i += blockDim.x)
-        tile[i] = ~0ull;
-    __syncthreads();
-    for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kUnroll * blockDim.x) {
-        uint64_t k[kUnroll];
-        uint32_t l[kUnroll];
-        bool ok[kUnroll];
+    // the bucket of entry lo: the last one starting at or before it (an empty
+    // bucket shares its successor's start and is passed over)
+    int32_t t = find_item(s_start, nb, lo);
+    while (lo < hi) {
+        const uint32_t end = s_start[t + 1] < hi ? s_start[t + 1] : hi;
+        for (int i = threadIdx.x; i < kTilePix; i += kRasterBlock)
+            tile[i] = ~0ull;
+        __syncthreads();
+        for (uint64_t i0 = lo + threadIdx.x; i0 < end; i0 += kUnroll * kRasterBlock) {
+            uint64_t k[kUnroll];
+            uint32_t l[kUnroll];
+            bool ok[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const uint64_t i = i0 + (uint64_t)u * blockDim.x;
-            ok[u] = i < hi;
-            k[u] = ok[u] ? ldnt(keys + i) : ~0ull;
-            l[u] = ok[u] ? ldnt(lps + i) : 0u;
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint64_t i = i0 + (uint64_t)u * kRasterBlock;
+                ok[u] = i < end;
+                k[u] = ok[u] ? ldnt(keys + i) : ~0ull;
+                l[u] = ok[u] ? ldnt(lps + i) : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                if (ok[u])
+                    __hip_atomic_fetch_min(&tile[l[u]], k[u], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __syncthreads();
+        const uint32_t x0 = ((uint32_t)t % (uint32_t)ntx) << kTileShift;
+        const uint32_t y0 = ((uint32_t)t / (uint32_t)ntx) << kTileShift;
+        // the flush: all of the thread's early-out reads first, then its
+        // atomics (framebuffer words only decrease, so a value read early is
+        // still an upper bound when the atomic runs)
+        constexpr int kFlush = kTilePix / kRasterBlock;
+        uint64_t v[kFlush], cur[kFlush];
+#pragma unroll
+        for (int f = 0; f < kFlush; ++f) {
+            const uint32_t l = threadIdx.x + f * kRasterBlock;
+            v[f] = tile[l];
+            cur[f] = 0ull;
+            if (v[f] != ~0ull)   // a fragment in range landed here: the pixel is on screen
+                cur[f] = __hip_atomic_load(fb + (uint64_t)(y0 + (l >> kTileShift)) *
+                                                    (uint32_t)width +
+                                               x0 + (l & (kTileSide - 1)),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-            if (ok[u])
-                __hip_atomic_fetch_min(&tile[l[u]], k[u], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
-    __syncthreads();
-    const uint32_t x0 = ((uint32_t)t % (uint32_t)ntx) << kTileShift;
-    const uint32_t y0 = ((uint32_t)t / (uint32_t)ntx) << kTileShift;
-    for (int l = threadIdx.x; l < kTilePix; l += blockDim.x) {
-        const uint64_t v = tile[l];
-        if (v != ~0ull) {   // a fragment in range landed here, so the pixel is on screen
-            uint64_t *dst = fb + (uint64_t)(y0 + (l >> kTileShift)) * (uint32_t)width + x0 +
-                            (l & (kTileSide - 1));
-            const uint64_t cur = __hip_atomic_load(dst, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-            if (v < cur)
-                __hip_atomic_fetch_min(dst, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int f = 0; f < kFlush; ++f) {
+            const uint32_t l = threadIdx.x + f * kRasterBlock;
+            if (v[f] < cur[f])
+                __hip_atomic_fetch_min(fb + (uint64_t)(y0 + (l >> kTileShift)) *
+                                                (uint32_t)width +
+                                           x0 + (l & (kTileSide - 1)),
+                                       v[f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        lo = end;
+        ++t;
+        while (t < nb && s_start[t + 1] <= lo)   // empty buckets
+            ++t;
+        __syncthreads();   // the tile is read before the next run clears it
     }
 }
 
@@ -489,7 +535,7 @@ __global__ void __launch_bounds__(kAccumBlock) k_sort_accum(const uint64_t *__re
     __shared__ uint64_t sums[2 * kTilePix];
     int32_t t;
     uint32_t lo, hi;
-    chunk_of(bstart, bchunk, nb, chunk, t, lo, hi);
+    chunk_of(bstart, bchunk, nb, chunk, blockIdx.x, t, lo, hi);
     if (lo >= hi)
         return;
     const uint32_t x0 = ((uint32_t)t % (uint32_t)ntx) << kTileShift;
@@ -558,7 +604,7 @@ void launch_count_scatter(const Pts &p, const Proj &P, const Layout &L, uint32_t
 }
 
 // Passes A to C: leaves the buckets (keys, lps), their starts and the work
-// list of D and E.
+// list of E.
 hipError_t sort_passes(const Pts &p, const Proj &P, const Layout &L, char *ws, bool vec,
                        hipStream_t s)
 {
@@ -641,8 +687,8 @@ int rasterize_sorted(const rz_points *pts, const rz_view *view, const rz_depth_m
         const dim3 grid((uint32_t)L.chunks_max);   // workgroups past the last item exit
         if (e == hipSuccess) {
             Range r("rz sort: bucket minima");
-            hipLaunchKernelGGL(k_sort_raster, grid, dim3(kRasterBlock), 0, s, keys, lps, bstart,
-                               bchunk, fb, L.ntx, L.nb, L.chunk, P.width);
+            hipLaunchKernelGGL(k_sort_raster, dim3(kRasterGroups), dim3(kRasterBlock), 0, s, keys,
+                               lps, bstart, fb, L.ntx, L.nb, P.width);
             e = hipGetLastError();
         }
         if (e == hipSuccess && hq) {
