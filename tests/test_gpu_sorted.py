@@ -184,3 +184,45 @@ def test_count_limit(rz):
     rz.resolve_hq(fb, acc, 4, 0, status=status)
     torch.cuda.synchronize()
     assert int(status.item()) & rz.RZ_STATUS_HQ_OVERFLOW
+
+
+LAYOUTS = {   # bucket (64x64 tile of a 640x360 screen, 10 x 6 of them) -> entries
+    "sparse": {0: 3, 10: 100_000, 31: 1, 59: 777},
+    "511 entries": {5: 200, 40: 311},
+    "512 entries": {5: 200, 40: 312},
+    "513 entries": {5: 200, 40: 313},
+    "one bucket": {59: 3 * 512 + 1},
+    "every other": {b: 1000 + b for b in range(0, 60, 2)},
+}
+
+
+@pytest.mark.parametrize("layout", list(LAYOUTS))
+def test_shares_across_buckets(rz, oracle, layout):
+    """Equal shares of the sorted entries per workgroup of the depth pass:
+    totals around a multiple of the workgroup count, shares that cross runs
+    of empty buckets, one bucket holding most entries, and depth-culled
+    points (on screen, past far) among the entries."""
+    W, H = 640, 360
+    rng = np.random.default_rng(2024)
+    xs, ys, ds = [], [], []
+    for b, c in LAYOUTS[layout].items():
+        tx, ty = b % 10, b // 10
+        px = rng.integers(tx * 64, min(W, tx * 64 + 64), c)
+        py = rng.integers(ty * 64, min(H, ty * 64 + 64), c)
+        d = rng.uniform(1.0, 3.9, c)
+        d[: c // 20] = 5.0   # past far: an entry with the key ~0
+        xs.append(px)
+        ys.append(py)
+        ds.append(d)
+    px, py, d = np.concatenate(xs), np.concatenate(ys), np.concatenate(ds)
+    perm = rng.permutation(len(d))
+    px, py, d = px[perm], py[perm], d[perm]
+    cx = (2 * px + 1) / W - 1.0
+    cy = (2 * py + 1) / H - 1.0
+    cloud = gen.Cloud((cx * d).astype(np.float32), (cy * d).astype(np.float32),
+                      (-d).astype(np.float32),
+                      rng.integers(0, 1 << 24, len(d)).astype(np.uint32))
+    # clip w = -z and x, y unscaled: (c * D, c' * D, -D) lands on NDC (c, c')
+    vp = np.diag([1.0, 1.0, 0.0, 0.0]) + np.array(
+        [[0, 0, 0, 0], [0, 0, 0, 0], [0, 0, 0, 0], [0, 0, -1.0, 0]])
+    check(rz, oracle, cloud, gen.View(vp, 0.5, 4.0, W, H), label=layout)
